@@ -1,0 +1,289 @@
+"""Serial FP64 CPU oracle of the resonant-line Monte Carlo transport.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product library
+(``paper_2507_11603_amd``) never imports, links or calls it, and the two share
+no code: the oracle is plain C (``thor_oracle.c``) bound here with ctypes.
+
+Parity status of each exported function (what pins it) is listed in
+``thor_oracle.c``'s header comments and in the tests under ``tests/``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "thor_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GEOMETRY = {"shell": 0, "sphere": 0, "slab": 1, "grid": 2}
+VELOCITY = {"none": 0, "const_radial": 1, "linear": 2}
+SOURCE = {"point": 0, "cell_n2": 1}
+SPECTRUM = {"delta": 0, "gauss": 1, "thermal": 2}
+PHASE = {"iso": 0, "dipole": 1, "core_wing": 2, "hg": 3}
+CORE_SKIP = {"off": 0, "fixed": 1, "adaptive": 2}
+OBS_AXIS = {"+x": 0, "+y": 1, "+z": 2, "-x": 3, "-y": 4, "-z": 5}
+FATE = {0: "none", 1: "escaped", 2: "absorbed", 3: "capped"}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Geometry(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("r_inner", C.c_double), ("r_outer", C.c_double),
+                ("n_HI", C.c_double), ("tau0", C.c_double), ("T", C.c_double),
+                ("v_profile", C.c_int32), ("v_max", C.c_double), ("step_f", C.c_double),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("f_n", C.c_void_p), ("f_T", C.c_void_p), ("f_vx", C.c_void_p),
+                ("f_vy", C.c_void_p), ("f_vz", C.c_void_p),
+                ("boundary_handoff", C.c_int32),
+                ("sigma_d", C.c_double), ("tau_d", C.c_double),
+                ("albedo", C.c_double), ("g_hg", C.c_double)]
+
+
+class Source(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pos", C.c_double * 3), ("spectrum", C.c_int32),
+                ("dv0", C.c_double), ("sigma_v", C.c_double),
+                ("seed", C.c_uint32), ("request_id", C.c_uint32)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("phase", C.c_int32), ("core_skip", C.c_int32), ("x_crit", C.c_double),
+                ("n_obs", C.c_int32), ("obs_axis", C.c_int32 * 6),
+                ("cube_nx", C.c_int32), ("cube_ny", C.c_int32), ("cube_nb", C.c_int32),
+                ("img_lo", C.c_double * 2), ("img_hi", C.c_double * 2),
+                ("cube_v_lo", C.c_double), ("cube_v_hi", C.c_double),
+                ("spec_nb", C.c_int32), ("spec_lo", C.c_double), ("spec_hi", C.c_double),
+                ("spec_T_ref", C.c_double), ("tau_cut", C.c_double),
+                ("max_events", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "emitted", "escaped", "absorbed", "capped", "handed_off", "n_res", "n_dust",
+        "main_visits", "peel_visits", "peel_contrib", "peel_dropped", "peel_cut",
+        "upar_trials")] + [("w_escaped", C.c_double), ("w_absorbed", C.c_double)]
+
+
+RECORD_DTYPE = np.dtype([("dv", "<f8"), ("n_res", "<u4"), ("n_dust", "<u4"),
+                         ("fate", "<i4"), ("pad", "<u4")])
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        d, u32, u64 = C.c_double, C.c_uint32, C.c_uint64
+        L.or_voigt.restype = d
+        L.or_voigt.argtypes = [d, d]
+        L.or_dawson.restype = d
+        L.or_dawson.argtypes = [d]
+        L.or_line_params.argtypes = [d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
+        L.or_philox4x32_10.argtypes = [C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
+        L.or_draw.argtypes = [u32, u32, u32, u32, u64, C.POINTER(d)]
+        L.or_sample_upar.restype = d
+        L.or_sample_upar.argtypes = [d, d, u32, u32, u64, C.POINTER(u64)]
+        L.or_upar_expected_trials.restype = d
+        L.or_upar_expected_trials.argtypes = [d, d]
+        L.or_sample_mu.restype = d
+        L.or_sample_mu.argtypes = [C.c_int, d, d]
+        L.or_basis.argtypes = [C.POINTER(d)] * 3
+        L.or_transport.restype = C.c_int
+        L.or_transport.argtypes = [C.POINTER(Geometry), C.POINTER(Source), C.POINTER(Opts),
+                                   u64, u64, C.c_void_p, C.c_void_p, C.POINTER(Stats),
+                                   C.c_void_p]
+        _lib = L
+    return _lib
+
+
+# ----------------------------------------------------------------- scalars
+def line_params(T: float):
+    """(v_th [cm/s], a, sigma0 [cm^2]) at temperature T (Section 2.3.1)."""
+    v, a, s = C.c_double(), C.c_double(), C.c_double()
+    lib().or_line_params(float(T), C.byref(v), C.byref(a), C.byref(s))
+    return v.value, a.value, s.value
+
+
+def voigt(a, x):
+    """H(a, x) = Re w(x + i a), elementwise (Section 3.4, Appendix A.3)."""
+    a_b, x_b = np.broadcast_arrays(np.asarray(a, float), np.asarray(x, float))
+    f = lib().or_voigt
+    return np.array([f(float(ai), float(xi)) for ai, xi in zip(a_b.ravel(), x_b.ravel())]
+                    ).reshape(a_b.shape)
+
+
+def dawson(x):
+    f = lib().or_dawson
+    return np.array([f(float(v)) for v in np.ravel(x)]).reshape(np.shape(x))
+
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().or_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def draw(seed, request_id, slot, event, pid):
+    out = (C.c_double * 2)()
+    lib().or_draw(seed, request_id, slot, event, pid, out)
+    return out[0], out[1]
+
+
+def sample_upar(x: float, a: float, n: int, seed: int = 7, event: int = 1):
+    """n samples of u_parallel at fixed (x, a), photon ids 0..n-1; returns (u, trials)."""
+    f = lib().or_sample_upar
+    u = np.empty(n)
+    tr = np.empty(n, dtype=np.uint64)
+    t = C.c_uint64()
+    for i in range(n):
+        u[i] = f(float(x), float(a), seed, event, i, C.byref(t))
+        tr[i] = t.value
+    return u, tr
+
+
+def upar_expected_trials(x: float, a: float) -> float:
+    return lib().or_upar_expected_trials(float(x), float(a))
+
+
+def sample_mu(phase: str, U, g: float = 0.0):
+    f = lib().or_sample_mu
+    ph = PHASE[phase]
+    return np.array([f(ph, float(u), float(g)) for u in np.ravel(U)])
+
+
+def basis(n):
+    nn = (C.c_double * 3)(*map(float, n))
+    e1, e2 = (C.c_double * 3)(), (C.c_double * 3)()
+    lib().or_basis(nn, e1, e2)
+    return np.array(list(e1)), np.array(list(e2))
+
+
+# ----------------------------------------------------------------- transport
+def _f32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+
+
+def make_structs(geom: dict, src: dict, opts: dict):
+    """Build (Geometry, Source, Opts, keepalive) from the plain-dict description
+    used by the tests and the benchmark (see ``workloads``)."""
+    g = Geometry()
+    g.kind = GEOMETRY[geom["kind"]]
+    g.r_inner = geom.get("r_inner", 0.0)
+    g.r_outer = geom.get("r_outer", 0.0)
+    g.n_HI = geom.get("n_HI", 0.0)
+    g.tau0 = geom.get("tau0", 0.0)
+    g.T = geom.get("T", 1e4)
+    g.v_profile = VELOCITY[geom.get("v_profile", "none")]
+    g.v_max = geom.get("v_max", 0.0)
+    g.step_f = geom.get("step_f", 0.01)
+    keep = []
+    if g.kind == 2:
+        fields = [_f32(geom[k]) for k in ("n_HI_field", "T_field", "vx", "vy", "vz")]
+        keep += fields
+        nz, ny, nx = fields[0].shape
+        g.nx, g.ny, g.nz = nx, ny, nz
+        g.lo[:] = list(map(float, geom["lo"]))
+        g.hi[:] = list(map(float, geom["hi"]))
+        g.f_n, g.f_T, g.f_vx, g.f_vy, g.f_vz = [f.ctypes.data for f in fields]
+    g.boundary_handoff = int(geom.get("boundary_handoff", 0))
+    g.sigma_d = geom.get("sigma_d", 0.0)
+    g.tau_d = geom.get("tau_d", 0.0)
+    g.albedo = geom.get("albedo", 0.0)
+    g.g_hg = geom.get("g_hg", 0.73)
+
+    s = Source()
+    s.kind = SOURCE[src.get("kind", "point")]
+    s.pos[:] = list(map(float, src.get("pos", (0.0, 0.0, 0.0))))
+    s.spectrum = SPECTRUM[src.get("spectrum", "delta")]
+    s.dv0 = src.get("dv0", 0.0)
+    s.sigma_v = src.get("sigma_v", 0.0)
+    s.seed = src.get("seed", 1)
+    s.request_id = src.get("request_id", 0)
+
+    o = Opts()
+    o.phase = PHASE[opts.get("phase", "iso")]
+    o.core_skip = CORE_SKIP[opts.get("core_skip", "off")]
+    o.x_crit = opts.get("x_crit", 0.0)
+    obs = opts.get("observers", [])
+    o.n_obs = len(obs)
+    for i, ax in enumerate(obs):
+        o.obs_axis[i] = OBS_AXIS[ax]
+    cube = opts.get("cube", None)
+    if cube:
+        o.cube_nx, o.cube_ny, o.cube_nb = cube["nx"], cube["ny"], cube["nb"]
+        o.img_lo[:] = list(map(float, cube["img_lo"]))
+        o.img_hi[:] = list(map(float, cube["img_hi"]))
+        o.cube_v_lo, o.cube_v_hi = cube["v_lo"], cube["v_hi"]
+    sp = opts["spectrum"]
+    o.spec_nb, o.spec_lo, o.spec_hi = sp["nb"], sp["lo"], sp["hi"]
+    o.spec_T_ref = sp.get("T_ref", 0.0)
+    o.tau_cut = opts.get("tau_cut", 40.0)
+    o.max_events = opts.get("max_events", 0)
+    return g, s, o, keep
+
+
+def run(geom: dict, src: dict, opts: dict, first_id: int, n: int, records: bool = False):
+    """Transport packets [first_id, first_id + n) serially.  Returns a dict with
+    'spectrum' (f64), 'cube' (f64 [n_obs, ny, nx, nb] or None), 'stats' (dict)
+    and optionally 'records' (structured array)."""
+    g, s, o, keep = make_structs(geom, src, opts)
+    spec = np.zeros(o.spec_nb)
+    cube = None
+    if o.n_obs > 0:
+        cube = np.zeros((o.n_obs, o.cube_ny, o.cube_nx, o.cube_nb))
+    st = Stats()
+    rec = np.zeros(n, dtype=RECORD_DTYPE) if records else None
+    rc = lib().or_transport(C.byref(g), C.byref(s), C.byref(o), first_id, n,
+                            spec.ctypes.data, None if cube is None else cube.ctypes.data,
+                            C.byref(st), None if rec is None else rec.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("oracle transport failed with code %d" % rc)
+    del keep
+    stats = {name: getattr(st, name) for name, _ in Stats._fields_}
+    out = {"spectrum": spec, "cube": cube, "stats": stats}
+    if records:
+        out["records"] = rec
+    return out
+
+
+def _run_chunk(args):
+    return run(*args)
+
+
+def run_parallel(geom, src, opts, first_id, n, workers=None, records=False):
+    """Same result as ``run`` (up to summation order of the FP64 accumulators),
+    split into contiguous id ranges over ``workers`` processes."""
+    workers = workers or min(8, os.cpu_count() or 1)
+    if workers <= 1 or n < 2 * workers:
+        return run(geom, src, opts, first_id, n, records)
+    bounds = np.linspace(0, n, workers + 1).astype(np.int64)
+    jobs = [(geom, src, opts, first_id + int(bounds[i]), int(bounds[i + 1] - bounds[i]), records)
+            for i in range(workers)]
+    build()
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        parts = list(ex.map(_run_chunk, jobs))
+    out = {"spectrum": sum(p["spectrum"] for p in parts),
+           "cube": None if parts[0]["cube"] is None else sum(p["cube"] for p in parts),
+           "stats": {k: sum(p["stats"][k] for p in parts) for k in parts[0]["stats"]}}
+    if records:
+        out["records"] = np.concatenate([p["records"] for p in parts])
+    return out
