@@ -1,0 +1,152 @@
+"""Benchmark of the Lyman-alpha packet-transport hot path on one MI355X.
+
+One step = one whole pass of the hot path over one batch: emit 1e6 packets
+from the central source of the 128^3 expanding-shell grid, march them with
+the Voigt cross-section in the gas frame, scatter (resonant and dust), peel
+off to the +z cube and bin the escapes.  Inputs are resident in HBM before
+the timed region (the grid is loaded once, untimed).
+
+Prints one JSON line (see the keys below).  `value` is photon scatterings
+per second (resonant + dust) of the persistent mixed-precision path; the
+plain one-launch-per-batch FP64 path is timed on the same GPU beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+BYTES_PER_VISIT = 20.0         # (vx, vy, vz, n_HI, T) float32 per cell visit
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--packets", type=int, default=1_000_000)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--path", default="persistent", choices=["persistent", "plain"])
+    ap.add_argument("--plain-steps", type=int, default=2, help="steps of the plain FP64 path (0: skip)")
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=400000, help="packets of the oracle sample")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (PMC calibration)")
+    return ap.parse_args()
+
+
+def run_steps(T, wl, n, steps, first_id, **kw):
+    import torch
+    tot = dict(n_res=0, n_dust=0, emitted=0, main_visits=0, peel_visits=0, kernel_ms=0.0,
+               escaped=0, absorbed=0, peel_contrib=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        T.reset()
+        T.emit(wl["src"], n, first_id + s * n)
+        code, st = T.transport(wl["opts"], **kw)
+        for k in tot:
+            tot[k] += st[k]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, tot
+
+
+def cpu_baseline(wl, n):
+    import oracle
+    workers = min(16, os.cpu_count() or 1)
+    oracle.build()
+    t0 = time.perf_counter()
+    r = oracle.run_parallel(wl["geom"], wl["src"], wl["opts"], 0, n, workers=workers)
+    dt = time.perf_counter() - t0
+    scat = r["stats"]["n_res"] + r["stats"]["n_dust"]
+    return dict(value=scat / dt, unit="scatterings/s", cores=workers, kind="oracle",
+                sample="%d packets of the same 128^3 shell workload (ids 0..%d, seed 2), "
+                       "%d scatterings in %.1f s over %d processes" % (n, n - 1, scat, dt, workers),
+                packets_per_s=n / dt)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import workloads as W
+    wl = W.shell(n_grid=a.grid, n_packets=a.packets)
+    # the CPU baseline runs first, in forked workers, before anything touches the GPU
+    cpu = cpu_baseline(wl, a.cpu_sample) if a.cpu_baseline else None
+
+    import torch
+
+    from paper_2507_11603_amd import thor
+
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    thor.lib()
+    if a.calib_copy_mib:
+        x = torch.empty(a.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    T = thor.Transport(0)
+    T.load(wl["geom"])
+    kw = dict(precision=a.precision, path=a.path, waves_per_cu=a.waves_per_cu, block=a.block)
+    if a.warmup:
+        run_steps(T, wl, a.packets, a.warmup, 10**12, **kw)
+    dt, tot = run_steps(T, wl, a.packets, a.steps, 0, **kw)
+    scat = tot["n_res"] + tot["n_dust"]
+    value = scat / dt
+    visits = tot["main_visits"] + tot["peel_visits"]
+    kernel_s = tot["kernel_ms"] / 1e3
+    achieved = BYTES_PER_VISIT * visits / a.steps / (kernel_s / a.steps) / 1e9
+    out = {
+        "metric": "photon scatterings/s on 1 MI355X (vs FP64 plain path)",
+        "value": value,
+        "unit": "scatterings/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if a.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": "expanding shell r in [0.8, 1] on a %d^3 grid, N_HI 1e19, v_exp 200 km/s, "
+                               "tau_d 0.5 (albedo 0.3), Gaussian source 20 km/s, dipole, +z peel cube "
+                               "%dx%dx256" % (a.grid, a.grid, a.grid),
+                   "packets_per_step": a.packets, "precision": a.precision, "path": a.path},
+        "packets_per_s": tot["emitted"] / dt,
+        "scatterings_per_packet": scat / max(tot["emitted"], 1),
+        "cell_visits_per_s": visits / dt,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_persistent<float,true>" if a.path == "persistent" else "k_plain",
+                     "kernel_ms_per_step": tot["kernel_ms"] / a.steps,
+                     "bytes_per_visit": BYTES_PER_VISIT, "visits_per_step": visits / a.steps},
+    }
+    if a.plain_steps:
+        pdt, ptot = run_steps(T, wl, a.packets, a.plain_steps, 2 * 10**12, precision="fp64", path="plain")
+        pval = (ptot["n_res"] + ptot["n_dust"]) / pdt
+        out["plain_fp64"] = {"value": pval, "unit": "scatterings/s", "ms_per_step": pdt / a.plain_steps * 1e3,
+                             "packets_per_s": ptot["emitted"] / pdt}
+        out["speedup_vs_plain_fp64"] = value / pval
+    T.close()
+    if cpu:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,293 @@
+/*
+ * thor.h -- C ABI of the MI355X resonant-line (Lyman-alpha) Monte Carlo
+ * transport library (libthor.so).
+ *
+ * The calls follow the paper's statement of the problem (arXiv 2507.11603,
+ * Section 3.2 building blocks and Section 3.4 MCRT driver):
+ *   a dataset answers where the next cell face is and what gas fills the cell
+ *        -> thor_load_grid      (Section 3.3, dataset "query")
+ *   a generator spawns photons with weights, frequencies and directions
+ *        -> thor_emit           (Section 3.4, "Emission")
+ *   the MCRT driver propagates packets and handles interactions
+ *        -> thor_transport      (Section 3.4 "Propagation", "Interaction",
+ *                                3.4.1 peeling, 3.4.2 core skipping, 3.4.3 RNG)
+ *   output processors reduce finished photons into spectra and cubes
+ *        -> thor_read_spectra   (Section 3.2, output processors)
+ * plus a continuous-batching extension for stream of shell-model solves
+ * (Section 5.1's parameter grid): thor_submit / thor_step / thor_poll.
+ *
+ * Conventions for every call:
+ *   - Units are cgs: lengths in cm, velocities and frequency offsets in cm/s
+ *     (a frequency offset dv = c (nu - nu0)/nu0 is stored in the lab frame),
+ *     densities in cm^-3, temperatures in K.
+ *   - Pointers are plain host or device pointers as stated per argument; a
+ *     "device" pointer is memory of the context's HIP device.
+ *   - No call throws; failures return a negative thor_status, and
+ *     thor_last_error() gives a message (thread-local).  THOR_E_INVAL and
+ *     THOR_E_BUDGET leave the context unchanged; THOR_E_DEVICE poisons it
+ *     (only thor_destroy is valid afterwards).
+ *   - A context must not be used from two host threads at once.
+ *   - All device work is ordered on the stream given to thor_create.
+ */
+#ifndef THOR_H
+#define THOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define THOR_ABI_VERSION 1
+
+typedef enum {
+    THOR_OK = 0,
+    THOR_INCOMPLETE = 1,        /* bounded step ended with work left: call again */
+    THOR_E_INVAL = -1,          /* bad argument; context unchanged */
+    THOR_E_NOMEM = -2,          /* device allocation failed */
+    THOR_E_BUDGET = -3,         /* HBM budget of the context would be exceeded */
+    THOR_E_DEVICE = -4,         /* HIP runtime error; context poisoned */
+    THOR_E_STATE = -5,          /* call not valid in the current state */
+    THOR_E_UNSUPPORTED = -6     /* option combination not implemented */
+} thor_status;
+
+typedef struct thor_ctx thor_ctx;
+
+/* ---------------------------------------------------------------- geometry */
+typedef enum { THOR_GEOM_SHELL = 0, THOR_GEOM_SLAB = 1, THOR_GEOM_GRID = 2 } thor_geom_kind;
+typedef enum { THOR_VEL_NONE = 0, THOR_VEL_CONST_RADIAL = 1, THOR_VEL_LINEAR = 2 } thor_vel_profile;
+typedef enum { THOR_MEM_HOST = 0, THOR_MEM_DEVICE = 1 } thor_mem;
+
+/* The medium (Section 3.3).  Meshless kinds (Section 4 validation media):
+ *   SHELL: homogeneous gas for r_inner <= r < r_outer around the origin,
+ *          vacuum inside (r_inner = 0 gives a sphere);
+ *   SLAB:  homogeneous gas for |z| < r_outer, infinite in x and y.
+ * Their density is n_HI, or, when tau0 > 0, tau0 / (sigma0(T) (r_outer -
+ * r_inner)) (tau0 = line-centre optical depth of the column).  Velocity
+ * profiles: CONST_RADIAL v = v_max r_hat; LINEAR v = v_max r / r_outer (slab:
+ * v_z = v_max z / r_outer).  Velocity fields are integrated in sub-steps of
+ * at most step_f v_th r / |v_max| (CONST_RADIAL) or step_f v_th r_outer /
+ * |v_max| (LINEAR), with the fields at each sub-step's midpoint.
+ * GRID: uniform Cartesian grid nx * ny * nz over [lo, hi]; five float32
+ * fields in C order [z][y][x] (x fastest), each nx*ny*nz values, in host or
+ * device memory per `mem`; cells with n_HI = 0 are vacuum.  The fields are
+ * copied into the context (the caller may free them on return).
+ * Dust (Section 2.3.2): opacity k_d = sigma_d n_HI, or for meshless kinds
+ * with tau_d > 0, tau_d / (r_outer - r_inner); interaction is absorption
+ * with probability 1 - albedo, else Henyey-Greenstein scattering with
+ * asymmetry g_hg, coherent in the gas frame. */
+typedef struct {
+    int32_t kind;
+    double r_inner, r_outer;
+    double n_HI;
+    double tau0;
+    double T;
+    int32_t v_profile;
+    double v_max;
+    double step_f;
+    int32_t nx, ny, nz;
+    double lo[3], hi[3];
+    const float *n_HI_field, *T_field, *vx, *vy, *vz;
+    int32_t mem;
+    int32_t boundary_handoff;   /* grid exits also counted as hand-offs */
+    double sigma_d;
+    double tau_d;
+    double albedo, g_hg;
+} thor_geometry;
+
+/* ---------------------------------------------------------------- sources */
+typedef enum { THOR_SRC_POINT = 0, THOR_SRC_CELL_N2 = 1 } thor_source_kind;
+typedef enum { THOR_SPEC_DELTA = 0, THOR_SPEC_GAUSS = 1, THOR_SPEC_THERMAL = 2 } thor_spectrum_kind;
+
+/* Generator (Section 3.4 "Emission"): isotropic directions; frequency
+ * DELTA dv0, GAUSS dv0 + sigma_v N(0,1) (source frame = lab frame), or
+ * THERMAL: the gas-frame Doppler profile of the emitting cell,
+ * dv0 + v_th N(0,1)/sqrt(2), shifted to the lab frame by v.k.
+ * POINT: emitted at pos.  CELL_N2 (grid only): cell drawn with probability
+ * proportional to n_HI^2, uniform position inside the cell.
+ * Packet ids and (seed, request_id) key the Philox4x32-10 stream. */
+typedef struct {
+    int32_t kind;
+    double pos[3];
+    int32_t spectrum;
+    double dv0, sigma_v;
+    uint32_t seed, request_id;
+} thor_source;
+
+/* ---------------------------------------------------------------- transport */
+typedef enum { THOR_PREC_FP64 = 0, THOR_PREC_MIXED = 1 } thor_precision;
+typedef enum { THOR_PATH_PLAIN = 0, THOR_PATH_PERSISTENT = 1 } thor_path;
+typedef enum { THOR_PHASE_ISO = 0, THOR_PHASE_DIPOLE = 1, THOR_PHASE_CORE_WING = 2 } thor_phase;
+typedef enum { THOR_CS_OFF = 0, THOR_CS_FIXED = 1, THOR_CS_ADAPTIVE = 2 } thor_core_skip;
+typedef enum { THOR_OBS_PX = 0, THOR_OBS_PY = 1, THOR_OBS_PZ = 2,
+               THOR_OBS_MX = 3, THOR_OBS_MY = 4, THOR_OBS_MZ = 5 } thor_obs_axis;
+
+/* Options of one transport call.
+ *   precision: FP64 everywhere, or MIXED (FP32 Voigt, direction and frequency
+ *              redistribution; FP64 position, cell distances, tau).
+ *   path:      PLAIN = one thread per packet, one launch per emitted batch,
+ *              runs to completion; PERSISTENT = resident waves refill lanes
+ *              from a queue over all pending batches.
+ *   phase:     resonant phase function (Section 2.3.1); core_skip/x_crit as
+ *              in Section 3.4.2 (ADAPTIVE: 0.2 (a tau0)^(1/3) for meshless
+ *              media with a tau0 >= 1, from the column of the medium).
+ *   observers: n_obs axis-aligned observers at infinity (peeling, Section
+ *              3.4.1); image axes: +-z -> (x, y), +-x -> (y, z), +-y -> (z, x).
+ *   cube:      [n_obs][cube_ny][cube_nx][cube_nb] float32, pixel of the
+ *              projected event position over [img_lo, img_hi), frequency bin
+ *              of the peeled dv over [cube_v_lo, cube_v_hi).
+ *   spectrum:  escaped weight per bin of dv over [spec_lo, spec_hi), or of
+ *              dv / v_th(spec_T_ref) when spec_T_ref > 0 (float64).
+ *   tau_cut:   peel rays stop once tau exceeds it (contribution dropped).
+ *   max_events: interaction cap per packet (0 = 1e8); capped packets are
+ *              counted, not binned.
+ *   step_events: PERSISTENT only: 0 = run to completion; else each call
+ *              advances every resident packet by at most this many
+ *              interactions and returns THOR_INCOMPLETE while work is left.
+ *   waves_per_cu, block: PERSISTENT launch shape (0 = automatic). */
+typedef struct {
+    int32_t precision;
+    int32_t path;
+    int32_t phase;
+    int32_t core_skip;
+    double x_crit;
+    int32_t n_obs;
+    int32_t obs_axis[6];
+    int32_t cube_nx, cube_ny, cube_nb;
+    double img_lo[2], img_hi[2];
+    double cube_v_lo, cube_v_hi;
+    int32_t spec_nb;
+    double spec_lo, spec_hi, spec_T_ref;
+    double tau_cut;
+    uint64_t max_events;
+    uint64_t step_events;
+    int32_t waves_per_cu;
+    int32_t block;
+    int32_t records;            /* 1: keep per-packet records of this call */
+} thor_transport_opts;
+
+/* Counters of one thor_transport call (device counters read back at the end
+ * of the call). */
+typedef struct {
+    uint64_t emitted, escaped, absorbed, capped, handed_off;
+    uint64_t n_res, n_dust;         /* resonant / dust scatterings */
+    uint64_t main_visits;           /* cell (segment) visits of the main march */
+    uint64_t peel_visits;           /* cell visits of peel rays */
+    uint64_t peel_contrib, peel_dropped, peel_cut;
+    uint64_t upar_trials;           /* u_parallel proposals */
+    double w_escaped, w_absorbed;
+    double kernel_ms;               /* device time of the transport kernels */
+} thor_stats;
+
+/* Per-packet record (index = packet id - first id of its batch, batches in
+ * emission order). */
+typedef struct {
+    double dv;          /* final lab-frame frequency offset, cm/s */
+    uint32_t n_res;
+    uint32_t n_dust;
+    int32_t fate;       /* 1 escaped, 2 absorbed, 3 capped */
+    uint32_t pad;
+} thor_record;
+
+typedef enum { THOR_OUT_SPECTRUM = 0, THOR_OUT_CUBE = 1, THOR_OUT_RECORDS = 2,
+               THOR_OUT_STATS = 3 } thor_output;
+
+/* ---------------------------------------------------------------- calls */
+
+/* Create a context on HIP device `hip_device`.  `hip_stream` is a
+ * hipStream_t of that device (e.g. torch.cuda.current_stream().cuda_stream)
+ * or NULL for the device's null stream.  hbm_budget_bytes bounds what the
+ * context allocates (0 = no bound); exceeding it gives THOR_E_BUDGET. */
+thor_status thor_create(thor_ctx **out, int hip_device, void *hip_stream, uint64_t hbm_budget_bytes);
+
+/* Release the context and all device memory it owns. NULL is ignored. */
+void thor_destroy(thor_ctx *ctx);
+
+/* Install the medium (dataset).  Replaces any previous one and discards
+ * emitted batches that have not been transported. */
+thor_status thor_load_grid(thor_ctx *ctx, const thor_geometry *g);
+
+/* Queue n_packets packets with ids first_photon_id .. + n_packets - 1 from
+ * source `src` (generator).  Packets are created lazily inside
+ * thor_transport; a CELL_N2 source builds the n_HI^2 emission CDF here once
+ * per medium. */
+thor_status thor_emit(thor_ctx *ctx, const thor_source *src, uint64_t n_packets,
+                      uint64_t first_photon_id);
+
+/* Transport every queued packet (MCRT driver).  Outputs (spectrum, cube)
+ * are shaped by `opt` and accumulated across calls until
+ * thor_reset_outputs; `out_stats` (may be NULL) receives this call's
+ * counters.  Returns THOR_INCOMPLETE for a bounded PERSISTENT step with
+ * work left. */
+thor_status thor_transport(thor_ctx *ctx, const thor_transport_opts *opt, thor_stats *out_stats);
+
+/* Zero the accumulated spectrum and cube. */
+thor_status thor_reset_outputs(thor_ctx *ctx);
+
+/* Copy an output to dst (host memory, or device memory when dst_on_device):
+ *   SPECTRUM: float64[spec_nb]; CUBE: float32[n_obs][ny][nx][nb] (index
+ *   selects nothing and must be 0); RECORDS: thor_record[packets of the last
+ *   call]; STATS: thor_stats of the last call.  dst_bytes must be at least
+ *   the size of the output (THOR_E_INVAL otherwise). */
+thor_status thor_read_spectra(thor_ctx *ctx, thor_output which, uint32_t index, void *dst,
+                              uint64_t dst_bytes, int dst_on_device);
+
+/* Size in bytes of an output as thor_read_spectra would copy it. */
+uint64_t thor_output_bytes(thor_ctx *ctx, thor_output which);
+
+/* Message of the last failure in this thread ("" if none). */
+const char *thor_last_error(void);
+
+/* ------------------------------------------------ device-function harness */
+/* Evaluate H(a, x) (the Voigt-Hjerting function used for sigma(x),
+ * Section 3.4 and Appendix A.3) with the transport kernels' own device code
+ * on n (a, x) pairs: a, x, out are device float64 arrays; precision FP64 or
+ * MIXED (FP32 evaluation, result widened).  For tests of the device code. */
+thor_status thor_eval_voigt(thor_ctx *ctx, const double *a, const double *x, double *out,
+                            uint64_t n, int32_t precision);
+
+/* Draw n u_parallel samples (eq. uparallel) at (x, a) with the kernels' own
+ * sampler, photon ids 0..n-1, event `event`, key (seed, 0): out_u float64[n]
+ * and out_trials uint32[n], device arrays. */
+thor_status thor_sample_upar(thor_ctx *ctx, double x, double a, uint32_t seed, uint32_t event,
+                             double *out_u, uint32_t *out_trials, uint64_t n, int32_t precision);
+
+/* --------------------------------------------- serving extension (batching) */
+/* One shell-model solve (Section 5.1): homogeneous shell r_inner..r_outer
+ * (cm) with column N_HI (cm^-2) at temperature T, constant radial expansion
+ * v_exp (cm/s), dust optical depth tau_d (albedo, g_hg), central GAUSS source
+ * of width sigma_v, n_packets packets keyed (seed, request_id), dipole
+ * phase function, adaptive core skipping, spectrum of spec_nb bins over
+ * [spec_lo, spec_hi) of dv. */
+typedef struct {
+    double N_HI, v_exp, T, tau_d, albedo, g_hg;
+    double r_inner, r_outer, sigma_v, step_f;
+    uint64_t n_packets;
+    uint32_t seed, request_id;
+    int32_t spec_nb;
+    double spec_lo, spec_hi;
+} thor_shell_request;
+
+/* Admit a request if its packet slots and output memory fit the context's
+ * HBM budget, else THOR_E_BUDGET (nothing changes; submit again later).
+ * *req_id receives the handle.  Requests share the device with every other
+ * admitted request; each packet's random stream depends only on (seed,
+ * request_id, photon id), so a result is the same alone and in any mix. */
+thor_status thor_submit(thor_ctx *ctx, const thor_shell_request *r, uint64_t *req_id);
+
+/* Run one bounded persistent step over all admitted requests: every
+ * resident packet advances by at most max_events_per_packet interactions
+ * (0 = to completion).  Returns THOR_OK when no admitted work is left,
+ * THOR_INCOMPLETE otherwise. */
+thor_status thor_step(thor_ctx *ctx, uint32_t max_events_per_packet, const thor_transport_opts *opt);
+
+/* Poll a request: *done = 1 once all its packets finished; then spectrum
+ * (host float64[spec_nb], may be NULL) and st (may be NULL) are filled and
+ * the request's memory is released (the handle becomes invalid). */
+thor_status thor_poll(thor_ctx *ctx, uint64_t req_id, double *spectrum, thor_stats *st, int *done);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

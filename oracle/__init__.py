@@ -13,7 +13,6 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
-from concurrent.futures import ProcessPoolExecutor
 
 import numpy as np
 
@@ -265,22 +264,33 @@ def run(geom: dict, src: dict, opts: dict, first_id: int, n: int, records: bool 
     return out
 
 
-def _run_chunk(args):
-    return run(*args)
+_JOB = None
+
+
+def _run_chunk(bounds):
+    geom, src, opts, records = _JOB
+    return run(geom, src, opts, bounds[0], bounds[1], records)
 
 
 def run_parallel(geom, src, opts, first_id, n, workers=None, records=False):
     """Same result as ``run`` (up to summation order of the FP64 accumulators),
-    split into contiguous id ranges over ``workers`` processes."""
+    split into contiguous id ranges over ``workers`` forked processes (which
+    inherit the inputs instead of receiving copies)."""
+    import multiprocessing as mp
+    global _JOB
     workers = workers or min(8, os.cpu_count() or 1)
     if workers <= 1 or n < 2 * workers:
         return run(geom, src, opts, first_id, n, records)
     bounds = np.linspace(0, n, workers + 1).astype(np.int64)
-    jobs = [(geom, src, opts, first_id + int(bounds[i]), int(bounds[i + 1] - bounds[i]), records)
-            for i in range(workers)]
+    jobs = [(first_id + int(bounds[i]), int(bounds[i + 1] - bounds[i])) for i in range(workers)]
     build()
-    with ProcessPoolExecutor(max_workers=workers) as ex:
-        parts = list(ex.map(_run_chunk, jobs))
+    lib()
+    _JOB = (geom, src, opts, records)
+    try:
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_run_chunk, jobs)
+    finally:
+        _JOB = None
     out = {"spectrum": sum(p["spectrum"] for p in parts),
            "cube": None if parts[0]["cube"] is None else sum(p["cube"] for p in parts),
            "stats": {k: sum(p["stats"][k] for p in parts) for k in parts[0]["stats"]}}

@@ -417,15 +417,21 @@ static void meshless_velocity(const model_t *m, const double q[3], double v[3])
     }
 }
 
-/* Positive root t of |p + t k|^2 = R^2 for a point inside the sphere. */
+/* Exit distance from a sphere of radius R along k: the far root of
+ * |p + t k|^2 = R^2.  A point that rounding put just outside the sphere while
+ * it moves inwards still crosses it (far root > 0); a point outside moving
+ * away exits at once (0). */
 static double sphere_exit(const double p[3], const double k[3], double R)
 {
     double b = dot3(p, k);
     double c = dot3(p, p) - R * R;
-    if (c >= 0.0)
+    double disc = b * b - c;
+    if (disc <= 0.0)
         return 0.0;
-    double q = sqrt(b * b - c);
-    return b <= 0.0 ? q - b : -c / (q + b);
+    double q = sqrt(disc);
+    if (b <= 0.0)
+        return q - b;
+    return c < 0.0 ? -c / (q + b) : 0.0;
 }
 
 /* Segment query.  Returns the path length t to the end of the segment and  */

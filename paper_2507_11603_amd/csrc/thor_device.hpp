@@ -1,0 +1,516 @@
+// thor_device.hpp -- device code of the MI355X resonant-line Monte Carlo
+// transport (arXiv 2507.11603, Sections 2.2-2.3 physics, 3.4 MCRT driver).
+//
+// Everything here runs on CDNA4 VALU: there is no dense contraction in the
+// method, so no MFMA.  The per-packet engine is shared by the plain kernel
+// (one thread per packet) and the persistent refilling kernel.
+//
+// Precision policy R: double for the FP64 path; float for the mixed path,
+// where the Voigt evaluation, the direction vector and the frequency
+// redistribution run in FP32 while position, cell-boundary distances and
+// optical depths stay FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace thor {
+
+// ---------------------------------------------------------------------------
+// Physical constants (cgs) and Lyman-alpha atomic data.  The paper prints
+// none of them; these are CODATA and the standard Lya values.
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.77245385090551602730;
+constexpr double kClight = 2.99792458e10;
+constexpr double kBoltzmann = 1.380649e-16;
+constexpr double kMassH = 1.6735575e-24;
+constexpr double kMassE = 9.1093837015e-28;
+constexpr double kCharge = 4.80320471e-10;
+constexpr double kLambda0 = 1215.67e-8;
+constexpr double kA21 = 6.265e8;
+constexpr double kF12 = 0.4162;
+// Section 2.3.1: v_th = sqrt(2kT/m); Doppler width dnu_D = v_th / lambda0,
+// a = A21 / (4 pi dnu_D), sigma0 = f12 sqrt(pi) e^2 / (m_e c dnu_D).
+constexpr double kVth2PerT = 2.0 * kBoltzmann / kMassH;
+constexpr double kDampTimesVth = kA21 * kLambda0 / (4.0 * kPi);
+constexpr double kSigma0TimesVth = kF12 * kSqrtPi * kCharge * kCharge * kLambda0 / (kMassE * kClight);
+
+// ---------------------------------------------------------------------------
+// Dawson's integral table (filled at context creation): 52 intervals of
+// width 1/8 on [0, 6.5], Taylor coefficients in s = (x - centre) * 16.
+// ---------------------------------------------------------------------------
+constexpr int kDawsonIntervals = 52;
+constexpr int kDawsonDeg64 = 12;
+constexpr int kDawsonDeg32 = 6;
+extern __constant__ double c_dawson64[kDawsonIntervals * (kDawsonDeg64 + 1)];
+extern __constant__ float c_dawson32[kDawsonIntervals * (kDawsonDeg32 + 1)];
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11), the counter-based stream replacing
+// the paper's per-work-item generator (Section 3.4.3): key = (seed, request),
+// counter = (slot, event, id_lo, id_hi).
+// ---------------------------------------------------------------------------
+struct Words { uint32_t w0, w1, w2, w3; };
+
+__device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    return Words{c0, c1, c2, c3};
+}
+
+struct Key {
+    uint32_t seed, req, id_lo, id_hi;
+};
+
+template <class R> struct Uni2 { R a, b; };
+
+// Two uniforms in [0,1): 53 random bits each in FP64 ((w0:w1) >> 11, (w2:w3) >> 11);
+// the top 24 bits of the same words in FP32.
+template <class R> __device__ __forceinline__ Uni2<R> draw(const Key& k, uint32_t slot, uint32_t event);
+template <> __device__ __forceinline__ Uni2<double> draw<double>(const Key& k, uint32_t slot, uint32_t event) {
+    const Words w = philox10(slot, event, k.id_lo, k.id_hi, k.seed, k.req);
+    const uint64_t hi = (uint64_t(w.w0) << 32) | w.w1;
+    const uint64_t lo = (uint64_t(w.w2) << 32) | w.w3;
+    return Uni2<double>{double(hi >> 11) * 0x1p-53, double(lo >> 11) * 0x1p-53};
+}
+template <> __device__ __forceinline__ Uni2<float> draw<float>(const Key& k, uint32_t slot, uint32_t event) {
+    const Words w = philox10(slot, event, k.id_lo, k.id_hi, k.seed, k.req);
+    return Uni2<float>{float(w.w0 >> 8) * 0x1p-24f, float(w.w2 >> 8) * 0x1p-24f};
+}
+
+// Slot map: event 0 = emission, event e >= 1 = e-th interaction.
+enum : uint32_t { kSlotEDir = 0, kSlotEGauss = 1, kSlotECell = 2, kSlotEOffs = 3, kSlotETau = 4 };
+enum : uint32_t { kSlotType = 0, kSlotUperp = 1, kSlotMu = 2, kSlotTau = 3, kSlotUpar = 4 };
+
+// ---------------------------------------------------------------------------
+// math shims per precision
+// ---------------------------------------------------------------------------
+template <class R> struct M;
+template <> struct M<double> {
+    static __device__ __forceinline__ double exp(double v) { return ::exp(v); }
+    static __device__ __forceinline__ double expm1(double v) { return ::expm1(v); }
+    static __device__ __forceinline__ double log(double v) { return ::log(v); }
+    static __device__ __forceinline__ double log1p(double v) { return ::log1p(v); }
+    static __device__ __forceinline__ double sqrt(double v) { return ::sqrt(v); }
+    static __device__ __forceinline__ double cbrt(double v) { return ::cbrt(v); }
+    static __device__ __forceinline__ double atan(double v) { return ::atan(v); }
+    static __device__ __forceinline__ double tan(double v) { return ::tan(v); }
+    static __device__ __forceinline__ void sincos(double v, double* s, double* c) { ::sincos(v, s, c); }
+    static __device__ __forceinline__ double sinpi2(double u, double* c) {  // sin/cos(2 pi u)
+        double s; ::sincos(2.0 * kPi * u, &s, c); return s;
+    }
+};
+template <> struct M<float> {
+    static __device__ __forceinline__ float exp(float v) { return __expf(v); }
+    static __device__ __forceinline__ float expm1(float v) { return ::expm1f(v); }
+    static __device__ __forceinline__ float log(float v) { return __logf(v); }
+    static __device__ __forceinline__ float log1p(float v) { return ::log1pf(v); }
+    static __device__ __forceinline__ float sqrt(float v) { return ::sqrtf(v); }
+    static __device__ __forceinline__ float cbrt(float v) { return ::cbrtf(v); }
+    static __device__ __forceinline__ float atan(float v) { return ::atanf(v); }
+    static __device__ __forceinline__ float tan(float v) { return ::tanf(v); }
+    static __device__ __forceinline__ void sincos(float v, float* s, float* c) { ::sincosf(v, s, c); }
+    static __device__ __forceinline__ float sinpi2(float u, float* c) {
+        float s; ::sincospif(2.0f * u, &s, c); return s;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Voigt-Hjerting function H(a, x) = Re w(x + i a), the profile of
+// sigma(x) = sigma0 H(a, x) evaluated at every march step (Section 3.4,
+// Appendix A.3).  |x| <= 6.5: Taylor series of w in i a about the real point
+// x, from w(x) = exp(-x^2) + (2i/sqrt(pi)) F(x) and the derivative recurrence
+// w^(n+1) = -2x w^(n) - 2n w^(n-1) (w' = -2x w + 2i/sqrt(pi)); the number of
+// terms depends on a.  |x| > 6.5: Laplace continued fraction of w - exp(-z^2)
+// with the Gaussian term added back.  FP64: <= 1e-13 relative for
+// a <= 0.05; FP32: <= 2e-5.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dawson64(double ax) {
+    int i = int(ax * 8.0);
+    i = i < kDawsonIntervals - 1 ? i : kDawsonIntervals - 1;
+    const double s = (ax - (double(i) + 0.5) * 0.125) * 16.0;
+    const double* c = c_dawson64 + i * (kDawsonDeg64 + 1);
+    // Estrin evaluation of the degree-12 polynomial
+    const double s2 = s * s, s4 = s2 * s2, s8 = s4 * s4;
+    const double p01 = fma(c[1], s, c[0]), p23 = fma(c[3], s, c[2]);
+    const double p45 = fma(c[5], s, c[4]), p67 = fma(c[7], s, c[6]);
+    const double p89 = fma(c[9], s, c[8]), pab = fma(c[11], s, c[10]);
+    const double q0 = fma(p23, s2, p01), q1 = fma(p67, s2, p45), q2 = fma(pab, s2, p89);
+    const double r0 = fma(q1, s4, q0), r1 = fma(c[12], s4, q2);
+    return fma(r1, s8, r0);
+}
+
+__device__ __forceinline__ float dawson32(float ax) {
+    int i = int(ax * 8.0f);
+    i = i < kDawsonIntervals - 1 ? i : kDawsonIntervals - 1;
+    const float s = (ax - (float(i) + 0.5f) * 0.125f) * 16.0f;
+    const float* c = c_dawson32 + i * (kDawsonDeg32 + 1);
+    const float s2 = s * s, s4 = s2 * s2;
+    const float p01 = fmaf(c[1], s, c[0]), p23 = fmaf(c[3], s, c[2]), p45 = fmaf(c[5], s, c[4]);
+    return fmaf(fmaf(c[6], s2, p45), s4, fmaf(p23, s2, p01));
+}
+
+__device__ __forceinline__ double voigt64(double a, double x) {
+    const double ax = fabs(x);
+    constexpr double two_rsqpi = 2.0 / kSqrtPi;
+    if (ax <= 6.5) {
+        const int nterms = a <= 1.2e-3 ? 4 : (a <= 1.2e-2 ? 6 : (a <= 2.5e-2 ? 8 : 12));
+        const double e = exp(-ax * ax);
+        double wr_p = e, wi_p = two_rsqpi * dawson64(ax);          // w(x)
+        double wr = -2.0 * ax * wr_p, wi = fma(-2.0 * ax, wi_p, two_rsqpi);  // w'(x)
+        double sum = wr_p;
+        double pr = 1.0, pi = 0.0, inv_fact = 1.0;                  // (i a)^n, 1/n!
+        for (int n = 1; n <= nterms; ++n) {
+            const double npr = -pi * a, npi = pr * a;
+            pr = npr; pi = npi;
+            inv_fact /= double(n);
+            sum = fma(pr * wr - pi * wi, inv_fact, sum);
+            const double nr = fma(-2.0 * ax, wr, -2.0 * double(n) * wr_p);
+            const double ni = fma(-2.0 * ax, wi, -2.0 * double(n) * wi_p);
+            wr_p = wr; wi_p = wi; wr = nr; wi = ni;
+        }
+        return sum;
+    }
+    // continued fraction t = z - (1/2)/(z - 1/(z - (3/2)/(...))), 14 levels
+    double tr = ax, ti = a;
+#pragma unroll
+    for (int k = 14; k >= 1; --k) {
+        const double inv = 1.0 / (tr * tr + ti * ti);
+        const double h = 0.5 * double(k);
+        tr = ax - h * tr * inv;
+        ti = a + h * ti * inv;
+    }
+    // Re[(i/sqrt(pi)) / t] = (ti / |t|^2) / sqrt(pi)
+    double h = ti / ((tr * tr + ti * ti) * kSqrtPi);
+    if (ax < 9.0) h += exp(-ax * ax);
+    return h;
+}
+
+__device__ __forceinline__ float voigt32(float a, float x) {
+    const float ax = fabsf(x);
+    constexpr float two_rsqpi = float(2.0 / kSqrtPi);
+    if (ax <= 6.5f) {
+        const float e = __expf(-ax * ax);
+        float wr_p = e, wi_p = two_rsqpi * dawson32(ax);
+        float wr = -2.0f * ax * wr_p, wi = fmaf(-2.0f * ax, wi_p, two_rsqpi);
+        // n = 1: Re(i a w') = -a Im w'
+        float sum = fmaf(-a, wi, wr_p);
+        // n = 2: Re((i a)^2 w'')/2 = -a^2 Re w''/2
+        float nr = fmaf(-2.0f * ax, wr, -2.0f * wr_p);
+        float ni = fmaf(-2.0f * ax, wi, -2.0f * wi_p);
+        sum = fmaf(-0.5f * a * a, nr, sum);
+        if (a > 3e-3f) {
+            // n = 3: Re((i a)^3 w''')/6 = a^3 Im w'''/6 ; n = 4: a^4 Re w''''/24
+            const float r3 = fmaf(-2.0f * ax, nr, -4.0f * wr), i3 = fmaf(-2.0f * ax, ni, -4.0f * wi);
+            const float r4 = fmaf(-2.0f * ax, r3, -6.0f * nr);
+            const float a2 = a * a;
+            sum = fmaf(a2 * a * (1.0f / 6.0f), i3, sum);
+            sum = fmaf(a2 * a2 * (1.0f / 24.0f), r4, sum);
+        }
+        return sum;
+    }
+    float tr = ax, ti = a;
+#pragma unroll
+    for (int k = 6; k >= 1; --k) {
+        const float inv = 1.0f / (tr * tr + ti * ti);
+        const float h = 0.5f * float(k);
+        tr = ax - h * tr * inv;
+        ti = a + h * ti * inv;
+    }
+    float h = ti / ((tr * tr + ti * ti) * float(kSqrtPi));
+    if (ax < 9.0f) h += __expf(-ax * ax);
+    return h;
+}
+
+template <class R> __device__ __forceinline__ R voigt(R a, R x);
+template <> __device__ __forceinline__ double voigt<double>(double a, double x) { return voigt64(a, x); }
+template <> __device__ __forceinline__ float voigt<float>(float a, float x) { return voigt32(a, x); }
+
+// ---------------------------------------------------------------------------
+// u_parallel sampler, eq. (uparallel): f(u) ~ exp(-u^2) / ((x-u)^2 + a^2).
+// Exact rejection sampling for any split u0 >= 0.
+//   |x| < 2.25: the paper's comparison function (eq. uparallel_comparisonfunc):
+//     1/((x-u)^2+a^2) below u0, exp(-u0^2)/((x-u)^2+a^2) above;
+//     u0 from two steps of u0 <- x - sqrt(a expm1(u0^2) / (2 pi u0)), u0 = x first.
+//   |x| >= 2.25: the same Lorentzian envelope above u0 and, below u0, the
+//     Gaussian envelope exp(-u^2) x^-2 exp(2u/x + c u^2/x^2) with
+//     c = (-2 ln(1 - t0) - 2 t0)/t0^2, t0 = u0/x;
+//     u0 = min(sqrt(ln(sqrt(pi) x^2 / a) + 3), x - 0.3/x).
+// Trial j draws slot 4+2j (choice, accept) and, for a Gaussian proposal,
+// slot 5+2j (radius, angle).  The FP64 version evaluates the same formulas
+// in the same order as the CPU reference so that same-seed runs follow the
+// same decisions; the FP32 version uses cancellation-free equivalents.
+// ---------------------------------------------------------------------------
+constexpr double kUparSwitch = 2.25;
+// Hard bound on proposals (never reached for finite x, a > 0: the expected
+// count is below 10); keeps a non-finite input from spinning a lane forever.
+constexpr uint32_t kUparMaxTrials = 1u << 20;
+
+__device__ __forceinline__ double upar_sample64(double x, double a, const Key& key, uint32_t event,
+                                                uint32_t* trials) {
+    const double xa = fabs(x);
+    const double sgn = x < 0.0 ? -1.0 : 1.0;
+    uint32_t n = 0;
+    double u = 0.0;
+    if (!(xa < 1e300) || !(a > 0.0)) { *trials = 0; return 0.0; }
+    if (xa < kUparSwitch) {
+        double u0 = xa;
+        for (int it = 0; it < 2; ++it) {
+            if (u0 <= 0.0) break;
+            u0 = xa - sqrt(a * expm1(u0 * u0) / (2.0 * kPi * u0));
+            u0 = u0 < 0.0 ? 0.0 : (u0 > xa ? xa : u0);
+        }
+        const double th0 = atan((u0 - xa) / a);
+        const double p1 = th0 + kPi / 2;
+        const double e0 = exp(-u0 * u0);
+        const double m = p1 + e0 * (kPi / 2 - th0);
+        for (;;) {
+            if (n >= kUparMaxTrials) break;
+            const Uni2<double> r12 = draw<double>(key, kSlotUpar + 2u * n, event);
+            ++n;
+            const double r = r12.a * m;
+            if (r < p1) {
+                u = xa + a * tan(r - kPi / 2);
+                if (r12.b < exp(-u * u)) break;
+            } else {
+                u = xa + a * tan(th0 + (r - p1) / e0);
+                if (r12.b < exp(u0 * u0 - u * u)) break;
+            }
+        }
+    } else {
+        double u0 = sqrt(log(kSqrtPi * xa * xa / a) + 3.0);
+        const double cap = xa - 0.3 / xa;
+        u0 = u0 < cap ? u0 : cap;
+        const double t0 = u0 / xa;
+        const double c = (-2.0 * log1p(-t0) - 2.0 * t0) / (t0 * t0);
+        const double p = 1.0 - c / (xa * xa), mu = 1.0 / (xa * p);
+        const double za = exp(p * mu * mu) * sqrt(kPi / p) / (xa * xa);
+        const double th0 = atan((u0 - xa) / a);
+        const double e0 = exp(-u0 * u0);
+        const double zb = e0 * (kPi / 2 - th0) / a;
+        for (;;) {
+            if (n >= kUparMaxTrials) break;
+            const Uni2<double> r12 = draw<double>(key, kSlotUpar + 2u * n, event);
+            const double r = r12.a * (za + zb);
+            if (r < za) {
+                const Uni2<double> r34 = draw<double>(key, kSlotUpar + 2u * n + 1u, event);
+                ++n;
+                double cs, sn;
+                sincos(2.0 * kPi * r34.b, &sn, &cs);
+                u = mu + sqrt(-log(1.0 - r34.a) / p) * cs;
+                if (u > u0) continue;
+                const double t = u / xa;
+                const double env = exp(2.0 * t + c * t * t) / (xa * xa);
+                const double tgt = 1.0 / ((xa - u) * (xa - u) + a * a);
+                if (r12.b * env < tgt) break;
+            } else {
+                ++n;
+                u = xa + a * tan(th0 + (r - za) * a / e0);
+                if (r12.b < exp(u0 * u0 - u * u)) break;
+            }
+        }
+    }
+    *trials = n;
+    return sgn * u;
+}
+
+__device__ __forceinline__ float upar_sample32(float x, float a, const Key& key, uint32_t event,
+                                               uint32_t* trials) {
+    const float xa = fabsf(x);
+    const float sgn = x < 0.0f ? -1.0f : 1.0f;
+    constexpr float pi = float(kPi), hpi = float(kPi / 2);
+    uint32_t n = 0;
+    float u = 0.0f;
+    if (!(xa < 1e30f) || !(a > 0.0f)) { *trials = 0; return 0.0f; }
+    if (xa < float(kUparSwitch)) {
+        float u0 = xa;
+        for (int it = 0; it < 2; ++it) {
+            if (u0 <= 0.0f) break;
+            u0 = xa - sqrtf(a * expm1f(u0 * u0) / (2.0f * pi * u0));
+            u0 = fminf(fmaxf(u0, 0.0f), xa);
+        }
+        const float d = xa - u0;                    // >= 0
+        const float p1 = d > 0.0f ? atanf(a / d) : hpi;           // theta0 + pi/2
+        const float q2 = d > 0.0f ? pi - atanf(a / d) : hpi;      // pi/2 - theta0
+        const float e0 = __expf(-u0 * u0);
+        const float m = fmaf(e0, q2, p1);
+        for (;;) {
+            if (n >= kUparMaxTrials) break;
+            const Uni2<float> r12 = draw<float>(key, kSlotUpar + 2u * n, event);
+            ++n;
+            const float r = r12.a * m;
+            if (r < p1) {
+                u = xa - a / tanf(r);                   // tan(r - pi/2) = -1/tan(r)
+                if (r12.b < __expf(-u * u)) break;
+            } else {
+                u = xa + a / tanf(q2 - (r - p1) / e0);  // tan(pi/2 - psi) = 1/tan(psi)
+                if (r12.b < __expf((u0 - u) * (u0 + u))) break;
+            }
+        }
+    } else {
+        float u0 = sqrtf(__logf(float(kSqrtPi) * xa * xa / a) + 3.0f);
+        u0 = fminf(u0, xa - 0.3f / xa);
+        const float t0 = u0 / xa;
+        float c;
+        if (t0 < 0.125f) {   // h(t) = sum_{k>=2} 2 t^(k-2) / k
+            c = 1.0f + t0 * (2.0f / 3.0f + t0 * (0.5f + t0 * (0.4f + t0 * (1.0f / 3.0f + t0 * (2.0f / 7.0f + t0 * 0.25f)))));
+            c *= 1.0f + 1e-5f;   // keeps the envelope a strict bound after truncation
+        } else {
+            c = (-2.0f * log1pf(-t0) - 2.0f * t0) / (t0 * t0) * (1.0f + 1e-5f);
+        }
+        const float p = 1.0f - c / (xa * xa), mu = 1.0f / (xa * p);
+        const float za = __expf(p * mu * mu) * sqrtf(pi / p) / (xa * xa);
+        const float d = xa - u0;
+        const float q2 = pi - atanf(a / d);
+        const float e0 = __expf(-u0 * u0);
+        const float zb = e0 * q2 / a;
+        for (;;) {
+            if (n >= kUparMaxTrials) break;
+            const Uni2<float> r12 = draw<float>(key, kSlotUpar + 2u * n, event);
+            const float r = r12.a * (za + zb);
+            if (r < za) {
+                const Uni2<float> r34 = draw<float>(key, kSlotUpar + 2u * n + 1u, event);
+                ++n;
+                float sn, cs;
+                sincospif(2.0f * r34.b, &sn, &cs);
+                u = mu + sqrtf(-__logf(1.0f - r34.a) / p) * cs;
+                if (u > u0) continue;
+                const float t = u / xa;
+                const float env = __expf(fmaf(c * t, t, 2.0f * t)) / (xa * xa);
+                const float tgt = 1.0f / fmaf(xa - u, xa - u, a * a);
+                if (r12.b * env < tgt) break;
+            } else {
+                ++n;
+                u = xa + a / tanf(q2 - (r - za) * a / e0);
+                if (r12.b < __expf((u0 - u) * (u0 + u))) break;
+            }
+        }
+    }
+    *trials = n;
+    return sgn * u;
+}
+
+template <class R> __device__ __forceinline__ R upar_sample(R x, R a, const Key& k, uint32_t e, uint32_t* t);
+template <> __device__ __forceinline__ double upar_sample<double>(double x, double a, const Key& k, uint32_t e, uint32_t* t) {
+    return upar_sample64(x, a, k, e, t);
+}
+template <> __device__ __forceinline__ float upar_sample<float>(float x, float a, const Key& k, uint32_t e, uint32_t* t) {
+    return upar_sample32(x, a, k, e, t);
+}
+
+// ---------------------------------------------------------------------------
+// Phase functions (Sections 2.3.1, 2.3.2): inverse CDFs of mu = cos(theta).
+//   isotropic 1/2; dipole 3/8(1+mu^2) (mu^3 + 3mu = 8U - 4); core mix
+//   11/24 + 3/24 mu^2 (mu^3 + 11 mu = 24U - 12); Henyey-Greenstein.
+// ---------------------------------------------------------------------------
+enum : int { kPhaseIso = 0, kPhaseDipole = 1, kPhaseCoreWing = 2, kPhaseHG = 3 };
+
+template <class R> __device__ __forceinline__ R cubic_root_mu(R p, R q) {
+    // real root of mu^3 + p mu = q (Cardano, p > 0)
+    const R disc = M<R>::sqrt(q * q / R(4) + p * p * p / R(27));
+    const R s = M<R>::cbrt(q / R(2) + disc);
+    return s - p / (R(3) * s);
+}
+
+template <class R> __device__ __forceinline__ R sample_mu(int phase, R U, R g) {
+    if (phase == kPhaseIso) return R(2) * U - R(1);
+    if (phase == kPhaseDipole) return cubic_root_mu<R>(R(3), R(8) * U - R(4));
+    if (phase == kPhaseCoreWing) return cubic_root_mu<R>(R(11), R(24) * U - R(12));
+    if (g == R(0)) return R(2) * U - R(1);
+    const R frac = (R(1) - g * g) / (R(1) - g + R(2) * g * U);
+    return (R(1) + g * g - frac * frac) / (R(2) * g);
+}
+
+template <class R> __device__ __forceinline__ R phase_value(int phase, R mu, R g) {
+    if (phase == kPhaseIso) return R(0.5);
+    if (phase == kPhaseDipole) return R(0.375) * (R(1) + mu * mu);
+    if (phase == kPhaseCoreWing) return R(11.0 / 24.0) + R(3.0 / 24.0) * mu * mu;
+    const R b = R(1) + g * g - R(2) * g * mu;
+    return R(0.5) * (R(1) - g * g) / (b * M<R>::sqrt(b));
+}
+
+// Orthonormal basis perpendicular to unit n (Duff et al. 2017, JCGT 6(1)).
+template <class R> __device__ __forceinline__ void onb(const R n[3], R e1[3], R e2[3]) {
+    const R sign = copysign(R(1), n[2]);
+    const R a = R(-1) / (sign + n[2]);
+    const R b = n[0] * n[1] * a;
+    e1[0] = R(1) + sign * n[0] * n[0] * a; e1[1] = sign * b; e1[2] = -sign * n[0];
+    e2[0] = b; e2[1] = sign + n[1] * n[1] * a; e2[2] = -n[1];
+}
+
+// ---------------------------------------------------------------------------
+// Device-side descriptions of the medium, the batch models and the outputs.
+// ---------------------------------------------------------------------------
+enum : int { kGeomShell = 0, kGeomSlab = 1, kGeomGrid = 2 };
+enum : int { kVelNone = 0, kVelConstRadial = 1, kVelLinear = 2 };
+enum : int { kSrcPoint = 0, kSrcCellN2 = 1 };
+enum : int { kSpecDelta = 0, kSpecGauss = 1, kSpecThermal = 2 };
+enum : int { kFateNone = 0, kFateEscaped = 1, kFateAbsorbed = 2, kFateCapped = 3 };
+enum : int { kRegCavity = 0, kRegGas = 1, kRegOut = 2 };
+
+struct GridDev {
+    int nx, ny, nz, handoff;
+    double lo[3], dx[3];
+    const float4* vn;     // (vx, vy, vz, n_HI) per cell, [z][y][x]
+    const float* T;       // temperature per cell
+    const double* cdf;    // inclusive prefix of n_HI^2 (CELL_N2 sources)
+    double cdf_total;
+    uint64_t ncell;
+    double sigma_d;
+};
+
+// One batch model: medium constants (meshless), dust, source, output slice.
+struct ModelDev {
+    int kind, v_profile, src_kind, spectrum;
+    double r_in, r_out, n, vth, a, k0, kd, v_max, step_f, xcrit;
+    double albedo, g_hg;
+    double pos[3];
+    double dv0, sigma_v;
+    uint32_t seed, req;
+    double* spec;               // escape spectrum of this model
+    int spec_nb;
+    double spec_lo, spec_w, spec_scale;
+    unsigned long long* done;   // packets finished (escaped, absorbed, capped)
+};
+
+struct BatchDev {
+    uint64_t q0;          // first queue index of the batch
+    uint64_t first_id;    // photon id of its first packet
+    uint64_t n;
+    int model;
+    int pad;
+};
+
+struct OutDev {
+    int phase;
+    int n_obs;
+    int obs_axis[6];
+    int cube_nx, cube_ny, cube_nb;
+    double img_lo[2], img_w[2];
+    double v_lo, v_w;
+    float* cube;
+    double tau_cut;
+    uint64_t max_events;
+    double* rec_dv;       // optional per-packet records (SoA), indexed by queue index - q_rec0
+    uint32_t* rec_nres;
+    uint32_t* rec_ndust;
+    int32_t* rec_fate;
+    uint64_t q_rec0;
+};
+
+// Per-lane counters, reduced per wave at the end of a launch.
+struct Counters {
+    uint64_t emitted, escaped, absorbed, capped, handed_off, n_res, n_dust;
+    uint64_t main_visits, peel_visits, peel_contrib, peel_dropped, peel_cut, upar_trials;
+    double w_escaped, w_absorbed;
+};
+constexpr int kNumU64Counters = 13;
+
+}  // namespace thor

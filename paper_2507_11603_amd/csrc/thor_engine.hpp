@@ -1,0 +1,544 @@
+// thor_engine.hpp -- per-packet transport engine (arXiv 2507.11603,
+// Section 3.4): emission, cell march with tau accumulation, interaction
+// (dust or resonant scattering), peeling off, escape binning.  Shared by the
+// plain and the persistent kernels.  GRID selects the uniform-grid medium at
+// compile time; otherwise the meshless sphere/shell/slab.
+#pragma once
+#include "thor_device.hpp"
+
+namespace thor {
+
+template <class R> struct Pkt {
+    double p[3];
+    int c[3];
+    int region;
+    R k[3];
+    R dv;
+    double tau_t, tau_a;
+    uint64_t id, q;
+    uint32_t event, n_res, n_dust;
+    int model;
+};
+
+template <class R> struct Fields {
+    R vth, a;
+    double k0, kd;
+    R v[3];
+};
+
+__device__ __forceinline__ double dot3d(const double a[3], const double b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+template <class R> __device__ __forceinline__ R dot3(const R a[3], const R b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// ----------------------------------------------------------------- grid
+template <class R>
+__device__ __forceinline__ void grid_fields(const GridDev& g, const int c[3], const ModelDev& m, Fields<R>& f) {
+    const uint64_t idx = (uint64_t(c[2]) * uint64_t(g.ny) + uint64_t(c[1])) * uint64_t(g.nx) + uint64_t(c[0]);
+    const float4 r = g.vn[idx];
+    f.v[0] = R(r.x); f.v[1] = R(r.y); f.v[2] = R(r.z);
+    const double n = double(r.w);
+    if (n > 0.0) {
+        const double T = double(g.T[idx]);
+        const double vth = sqrt(kVth2PerT * T);
+        f.vth = R(vth);
+        f.a = R(kDampTimesVth / vth);
+        f.k0 = n * (kSigma0TimesVth / vth);
+        f.kd = g.sigma_d * n;
+    } else {
+        f.vth = R(1); f.a = R(0); f.k0 = 0.0; f.kd = 0.0;
+    }
+}
+
+// distance to the next cell face; *mask = axes whose face is hit first
+template <class R>
+__device__ __forceinline__ double grid_step(const GridDev& g, const double p[3], const int c[3], const R k[3], int* mask) {
+    double tm[3];
+    double tmin = __builtin_inf();
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double kk = double(k[ax]);
+        if (kk > 0.0) tm[ax] = (g.lo[ax] + double(c[ax] + 1) * g.dx[ax] - p[ax]) / kk;
+        else if (kk < 0.0) tm[ax] = (g.lo[ax] + double(c[ax]) * g.dx[ax] - p[ax]) / kk;
+        else tm[ax] = __builtin_inf();
+        tmin = tm[ax] < tmin ? tm[ax] : tmin;
+    }
+    int mk = 0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) mk |= (tm[ax] == tmin) ? (1 << ax) : 0;
+    *mask = mk;
+    return tmin < 0.0 ? 0.0 : tmin;
+}
+
+// apply a full segment; returns true when the packet leaves the grid
+template <class R>
+__device__ __forceinline__ bool grid_advance(const GridDev& g, double p[3], int c[3], const R k[3], double t, int mask) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] += t * double(k[i]);
+    bool out = false;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (mask & (1 << ax)) {
+            if (k[ax] > R(0)) { c[ax] += 1; p[ax] = g.lo[ax] + double(c[ax]) * g.dx[ax]; }
+            else { c[ax] -= 1; p[ax] = g.lo[ax] + double(c[ax] + 1) * g.dx[ax]; }
+        }
+    }
+    const int dims[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) out |= (c[ax] < 0) | (c[ax] >= dims[ax]);
+    return out;
+}
+
+// ----------------------------------------------------------------- meshless
+// Exit distance from a sphere of radius R0 along k: the far root of
+// |p + t k|^2 = R0^2 (a point rounded just outside while moving inwards still
+// crosses the sphere; a point outside moving away exits at once).
+__device__ __forceinline__ double sphere_exit(const double p[3], const double k[3], double R0) {
+    const double b = dot3d(p, k);
+    const double c = dot3d(p, p) - R0 * R0;
+    const double disc = b * b - c;
+    if (disc <= 0.0) return 0.0;
+    const double q = sqrt(disc);
+    if (b <= 0.0) return q - b;
+    return c < 0.0 ? -c / (q + b) : 0.0;
+}
+
+template <class R>
+__device__ __forceinline__ void meshless_velocity(const ModelDev& m, const double q[3], R v[3]) {
+    v[0] = v[1] = v[2] = R(0);
+    if (m.v_profile == kVelNone) return;
+    if (m.kind == kGeomSlab) { v[2] = R(m.v_max * q[2] / m.r_out); return; }
+    if (m.v_profile == kVelConstRadial) {
+        const double r = sqrt(dot3d(q, q));
+        if (r > 0.0) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) v[i] = R(m.v_max * q[i] / r);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[i] = R(m.v_max * q[i] / m.r_out);
+    }
+}
+
+// segment of the meshless medium: boundary distance, limiter sub-step and
+// midpoint fields; *cross = 1 when the segment ends on a boundary.
+template <class R>
+__device__ __forceinline__ double meshless_query(const ModelDev& m, const double p[3], int region, const R kR[3],
+                                                 Fields<R>& f, int* next, int* cross) {
+    const double k[3] = {double(kR[0]), double(kR[1]), double(kR[2])};
+    double t;
+    int nxt;
+    if (m.kind == kGeomSlab) {
+        if (k[2] > 0.0) t = (m.r_out - p[2]) / k[2];
+        else if (k[2] < 0.0) t = (-m.r_out - p[2]) / k[2];
+        else t = __builtin_inf();
+        t = t < 0.0 ? 0.0 : t;
+        nxt = kRegOut;
+    } else if (region == kRegCavity) {
+        t = sphere_exit(p, k, m.r_in);
+        nxt = kRegGas;
+    } else {
+        t = sphere_exit(p, k, m.r_out);
+        nxt = kRegOut;
+        if (m.r_in > 0.0) {
+            const double b = dot3d(p, k);
+            const double ci = dot3d(p, p) - m.r_in * m.r_in;
+            const double disc = b * b - ci;
+            if (b < 0.0 && disc > 0.0) {
+                double tin = ci / (-b + sqrt(disc));
+                tin = tin < 0.0 ? 0.0 : tin;
+                if (tin < t) { t = tin; nxt = kRegCavity; }
+            }
+        }
+    }
+    *cross = 1;
+    if (region == kRegCavity) {
+        f.vth = R(1); f.a = R(0); f.k0 = 0.0; f.kd = 0.0;
+        f.v[0] = f.v[1] = f.v[2] = R(0);
+        *next = nxt;
+        return t;
+    }
+    f.vth = R(m.vth); f.a = R(m.a); f.k0 = m.k0; f.kd = m.kd;
+    if (m.v_profile != kVelNone && m.v_max != 0.0) {
+        double scale;
+        if (m.kind == kGeomSlab || m.v_profile == kVelLinear) {
+            scale = m.r_out;
+        } else {
+            const double r = sqrt(dot3d(p, p));
+            scale = r > 1e-6 * m.r_out ? r : 1e-6 * m.r_out;
+        }
+        const double lmax = m.step_f * m.vth * scale / fabs(m.v_max);
+        if (t > lmax) { t = lmax; *cross = 0; nxt = region; }
+        double mid[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) mid[i] = p[i] + 0.5 * t * k[i];
+        meshless_velocity<R>(m, mid, f.v);
+    } else {
+        f.v[0] = f.v[1] = f.v[2] = R(0);
+    }
+    *next = nxt;
+    return t;
+}
+
+__device__ __forceinline__ int meshless_locate(const ModelDev& m, const double p[3]) {
+    if (m.kind == kGeomSlab) return fabs(p[2]) < m.r_out ? kRegGas : kRegOut;
+    const double r = sqrt(dot3d(p, p));
+    return r < m.r_in ? kRegCavity : (r < m.r_out ? kRegGas : kRegOut);
+}
+
+// ----------------------------------------------------------------- unified query
+// Location of a ray: position, cell (grid) or region (meshless).
+struct Loc {
+    double p[3];
+    int c[3];
+    int region;
+};
+
+template <class R, bool GRID>
+__device__ __forceinline__ double query(const GridDev& g, const ModelDev& m, const Loc& L, const R k[3],
+                                        Fields<R>& f, int* next, int* cross) {
+    if constexpr (GRID) {
+        const double t = grid_step<R>(g, L.p, L.c, k, cross);
+        grid_fields<R>(g, L.c, m, f);
+        *next = kRegGas;
+        return t;
+    } else {
+        return meshless_query<R>(m, L.p, L.region, k, f, next, cross);
+    }
+}
+
+template <class R, bool GRID>
+__device__ __forceinline__ bool advance(const GridDev& g, Loc& L, const R k[3], double t, int next, int cross) {
+    if constexpr (GRID) {
+        return grid_advance<R>(g, L.p, L.c, k, t, cross);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) L.p[i] += t * double(k[i]);
+        if (cross) L.region = next;
+        return L.region == kRegOut;
+    }
+}
+
+// ----------------------------------------------------------------- peeling
+__device__ __forceinline__ void obs_dir(int axis, double k[3]) {
+    k[0] = k[1] = k[2] = 0.0;
+    k[axis % 3] = axis < 3 ? 1.0 : -1.0;
+}
+
+__device__ __forceinline__ void obs_image(int axis, const double p[3], double* u, double* v) {
+    const int a = axis % 3;
+    if (a == 2) { *u = p[0]; *v = p[1]; }
+    else if (a == 0) { *u = p[1]; *v = p[2]; }
+    else { *u = p[2]; *v = p[0]; }
+}
+
+__device__ __forceinline__ int bin_of(double v, double lo, double w, int nb) {
+    const double b = floor((v - lo) / w);
+    return (b >= 0.0 && b < double(nb)) ? int(b) : -1;
+}
+
+// Peel-off ray (Section 3.4.1): tau along the observer axis from the event,
+// at the fixed lab-frame frequency of the peeled photon; contribution
+// weight * exp(-tau) into the observer cube.
+template <class R, bool GRID>
+__device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const Loc& L0, int obs,
+                     double weight, R dv_peel, Counters& cnt) {
+    double kd[3];
+    obs_dir(o.obs_axis[obs], kd);
+    const R k[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+    cnt.peel_contrib++;
+    Loc L = L0;
+    double tau = 0.0;
+    bool cut = false;
+    for (;;) {
+        Fields<R> f;
+        int nr, cm;
+        const double t = query<R, GRID>(g, m, L, k, f, &nr, &cm);
+        cnt.peel_visits++;
+        if (f.k0 > 0.0 || f.kd > 0.0) {
+            const R x = (dv_peel - dot3<R>(f.v, k)) / f.vth;
+            const double kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+            if (isinf(t)) { cut = true; break; }
+            tau += kt * t;
+        } else if (isinf(t)) {
+            break;
+        }
+        if (tau > o.tau_cut) { cut = true; break; }
+        if (advance<R, GRID>(g, L, k, t, nr, cm)) break;
+    }
+    if (cut) { cnt.peel_cut++; return; }
+    double u, v;
+    obs_image(o.obs_axis[obs], L0.p, &u, &v);
+    const int ix = bin_of(u, o.img_lo[0], o.img_w[0], o.cube_nx);
+    const int iy = bin_of(v, o.img_lo[1], o.img_w[1], o.cube_ny);
+    const int ib = bin_of(double(dv_peel), o.v_lo, o.v_w, o.cube_nb);
+    if (ix < 0 || iy < 0 || ib < 0) { cnt.peel_dropped++; return; }
+    const uint64_t idx = ((uint64_t(obs) * o.cube_ny + iy) * o.cube_nx + ix) * o.cube_nb + ib;
+    unsafeAtomicAdd(o.cube + idx, float(weight * exp(-tau)));
+}
+
+// ----------------------------------------------------------------- emission
+// Generator + photon initialisation (Section 3.4 "Emission").
+template <class R, bool GRID>
+__device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint64_t id, uint64_t q, int model,
+                     Pkt<R>& pk, Counters& cnt) {
+    const Key key{m.seed, m.req, uint32_t(id), uint32_t(id >> 32)};
+    pk.id = id; pk.q = q; pk.model = model;
+    pk.event = 0; pk.n_res = 0; pk.n_dust = 0;
+    {
+        const Uni2<R> d = draw<R>(key, kSlotEDir, 0);
+        const R mu = R(2) * d.a - R(1);
+        R cphi;
+        const R sphi = M<R>::sinpi2(d.b, &cphi);
+        const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
+        pk.k[0] = st * cphi; pk.k[1] = st * sphi; pk.k[2] = mu;
+    }
+    Loc L;
+    if (GRID && m.src_kind == kSrcCellN2) {
+        const Uni2<double> d1 = draw<double>(key, kSlotECell, 0);
+        const Uni2<double> d2 = draw<double>(key, kSlotEOffs, 0);
+        const double target = d1.a * g.cdf_total;
+        uint64_t lo = 0, hi = g.ncell - 1;   // first index with cdf > target
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (g.cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        L.c[0] = int(lo % uint64_t(g.nx));
+        L.c[1] = int((lo / uint64_t(g.nx)) % uint64_t(g.ny));
+        L.c[2] = int(lo / (uint64_t(g.nx) * uint64_t(g.ny)));
+        const double off[3] = {d1.b, d2.a, d2.b};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) L.p[ax] = g.lo[ax] + (double(L.c[ax]) + off[ax]) * g.dx[ax];
+        L.region = kRegGas;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) L.p[i] = m.pos[i];
+        if constexpr (GRID) {
+            const int dims[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                int c = int(floor((L.p[ax] - g.lo[ax]) / g.dx[ax]));
+                c = c < 0 ? 0 : (c >= dims[ax] ? dims[ax] - 1 : c);
+                L.c[ax] = c;
+            }
+            L.region = kRegGas;
+        } else {
+            L.region = meshless_locate(m, L.p);
+            L.c[0] = L.c[1] = L.c[2] = 0;
+        }
+    }
+    Fields<R> f0;
+    if (L.region == kRegOut) {
+        f0.vth = R(1); f0.a = R(0); f0.k0 = 0.0; f0.kd = 0.0; f0.v[0] = f0.v[1] = f0.v[2] = R(0);
+    } else {
+        int nr, cm;
+        (void)query<R, GRID>(g, m, L, pk.k, f0, &nr, &cm);
+    }
+    R z = R(0);
+    if (m.spectrum != kSpecDelta) {
+        const Uni2<R> d = draw<R>(key, kSlotEGauss, 0);
+        R cs;
+        (void)M<R>::sinpi2(d.b, &cs);
+        z = M<R>::sqrt(R(-2) * M<R>::log(R(1) - d.a)) * cs;
+    }
+    R dv_loc = R(0);
+    if (m.spectrum == kSpecThermal) {
+        dv_loc = R(m.dv0) + f0.vth * z / R(1.4142135623730951);
+        pk.dv = dv_loc + dot3<R>(f0.v, pk.k);
+    } else if (m.spectrum == kSpecGauss) {
+        pk.dv = R(m.dv0) + R(m.sigma_v) * z;
+    } else {
+        pk.dv = R(m.dv0);
+    }
+    cnt.emitted++;
+    if (L.region != kRegOut) {
+        for (int ob = 0; ob < o.n_obs; ++ob) {
+            double kd[3];
+            obs_dir(o.obs_axis[ob], kd);
+            const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+            const R dvp = (m.spectrum == kSpecThermal) ? dv_loc + dot3<R>(f0.v, ko) : pk.dv;
+            peel<R, GRID>(g, m, o, L, ob, 1.0 / (4.0 * kPi), dvp, cnt);
+        }
+    }
+    const Uni2<double> dt = draw<double>(key, kSlotETau, 0);
+    pk.tau_t = -log(1.0 - dt.a);
+    pk.tau_a = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { pk.p[i] = L.p[i]; pk.c[i] = L.c[i]; }
+    pk.region = L.region;
+}
+
+// ----------------------------------------------------------------- one event
+// March until the next interaction or the boundary, then interact.  Returns
+// the packet's fate (kFateNone while it lives on).
+template <class R, bool GRID>
+__device__ int advance_event(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt) {
+    const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
+    Loc L;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { L.p[i] = pk.p[i]; L.c[i] = pk.c[i]; }
+    L.region = pk.region;
+    if (L.region == kRegOut) return kFateEscaped;
+    int fate = kFateNone;
+    for (;;) {
+        Fields<R> f;
+        int nr, cm;
+        const double t = query<R, GRID>(g, m, L, pk.k, f, &nr, &cm);
+        cnt.main_visits++;
+        double kt = 0.0;
+        if (f.k0 > 0.0 || f.kd > 0.0) {
+            const R x = (pk.dv - dot3<R>(f.v, pk.k)) / f.vth;
+            kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+        }
+        if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) {
+            // interaction site where tau_current = tau_target along the step
+            const double s = (pk.tau_t - pk.tau_a) / kt;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) L.p[i] += s * double(pk.k[i]);
+            pk.event++;
+            const uint64_t emax = o.max_events ? o.max_events : 100000000ull;
+            if (uint64_t(pk.event) > emax) { fate = kFateCapped; break; }
+            const Uni2<double> dtyp = draw<double>(key, kSlotType, pk.event);
+            R kout[3], e1[3], e2[3];
+            if (dtyp.a * kt < f.kd) {
+                // dust: absorption or Henyey-Greenstein scattering (Section 2.3.2)
+                if (dtyp.b >= m.albedo) { fate = kFateAbsorbed; break; }
+                const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
+                const R mu = sample_mu<R>(kPhaseHG, dm.a, R(m.g_hg));
+                const R dvl = pk.dv - dot3<R>(f.v, pk.k);
+                onb<R>(pk.k, e1, e2);
+                const R s_ = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
+                R cphi;
+                const R sphi = M<R>::sinpi2(dm.b, &cphi);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
+                for (int ob = 0; ob < o.n_obs; ++ob) {
+                    double kd[3];
+                    obs_dir(o.obs_axis[ob], kd);
+                    const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+                    const double c = double(phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg))) / (2.0 * kPi);
+                    peel<R, GRID>(g, m, o, L, ob, c, dvl + dot3<R>(f.v, ko), cnt);
+                }
+                pk.dv = dvl + dot3<R>(f.v, kout);
+                pk.n_dust++;
+                cnt.n_dust++;
+            } else {
+                // resonant scattering (Sections 2.3.1, 3.4, 3.4.2)
+                const R x = (pk.dv - dot3<R>(f.v, pk.k)) / f.vth;
+                uint32_t trials = 0;
+                const R upar = upar_sample<R>(x, f.a, key, pk.event, &trials);
+                cnt.upar_trials += trials;
+                const Uni2<R> dp = draw<R>(key, kSlotUperp, pk.event);
+                R rho2 = -M<R>::log(R(1) - dp.a);
+                if (m.xcrit > 0.0 && fabs(x) < R(m.xcrit)) rho2 += R(m.xcrit * m.xcrit);
+                const R rho = M<R>::sqrt(rho2);
+                R cps;
+                const R sps = M<R>::sinpi2(dp.b, &cps);
+                const R up1 = rho * cps, up2 = rho * sps;
+                onb<R>(pk.k, e1, e2);
+                R u[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) u[i] = upar * pk.k[i] + up1 * e1[i] + up2 * e2[i];
+                const R x_atom = x - upar;
+                int ph = o.phase;
+                if (ph == kPhaseCoreWing && fabs(x_atom) >= R(0.2)) ph = kPhaseDipole;
+                const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
+                const R mu = sample_mu<R>(ph, dm.a, R(0));
+                const R s_ = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
+                R cphi;
+                const R sphi = M<R>::sinpi2(dm.b, &cphi);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
+                for (int ob = 0; ob < o.n_obs; ++ob) {
+                    double kd[3];
+                    obs_dir(o.obs_axis[ob], kd);
+                    const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+                    const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
+                    const R xo = x_atom + dot3<R>(u, ko);
+                    peel<R, GRID>(g, m, o, L, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt);
+                }
+                const R x_out = x_atom + dot3<R>(u, kout);
+                pk.dv = x_out * f.vth + dot3<R>(f.v, kout);
+                pk.n_res++;
+                cnt.n_res++;
+            }
+            if constexpr (sizeof(R) == 4) {   // FP32 directions drift: renormalise
+                const R inv = R(1) / M<R>::sqrt(dot3<R>(kout, kout));
+#pragma unroll
+                for (int i = 0; i < 3; ++i) kout[i] *= inv;
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) pk.k[i] = kout[i];
+            const Uni2<double> dtau = draw<double>(key, kSlotTau, pk.event);
+            pk.tau_t = -log(1.0 - dtau.a);
+            pk.tau_a = 0.0;
+            break;
+        }
+        if (isinf(t)) { fate = kFateEscaped; break; }
+        pk.tau_a += kt * t;
+        if (advance<R, GRID>(g, L, pk.k, t, nr, cm)) { fate = kFateEscaped; break; }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { pk.p[i] = L.p[i]; pk.c[i] = L.c[i]; }
+    pk.region = L.region;
+    return fate;
+}
+
+// ----------------------------------------------------------------- finish
+template <class R, bool GRID>
+__device__ void finish(const GridDev& g, const ModelDev& m, const OutDev& o, const Pkt<R>& pk, int fate,
+                       Counters& cnt) {
+    if (fate == kFateEscaped) {
+        cnt.escaped++;
+        cnt.w_escaped += 1.0;
+        if (GRID && g.handoff) cnt.handed_off++;
+        const int b = bin_of(double(pk.dv) * m.spec_scale, m.spec_lo, m.spec_w, m.spec_nb);
+        if (b >= 0) unsafeAtomicAdd(m.spec + b, 1.0);
+    } else if (fate == kFateAbsorbed) {
+        cnt.absorbed++;
+        cnt.w_absorbed += 1.0;
+    } else if (fate == kFateCapped) {
+        cnt.capped++;
+    }
+    if (o.rec_dv) {
+        const uint64_t r = pk.q - o.q_rec0;
+        o.rec_dv[r] = double(pk.dv);
+        o.rec_nres[r] = pk.n_res;
+        o.rec_ndust[r] = pk.n_dust;
+        o.rec_fate[r] = fate;
+    }
+    if (m.done) atomicAdd(m.done, 1ull);
+}
+
+// ----------------------------------------------------------------- counters
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ void flush_counters(const Counters& c, unsigned long long* g, double* gw) {
+    const uint64_t vals[kNumU64Counters] = {c.emitted, c.escaped, c.absorbed, c.capped, c.handed_off,
+                                            c.n_res, c.n_dust, c.main_visits, c.peel_visits,
+                                            c.peel_contrib, c.peel_dropped, c.peel_cut, c.upar_trials};
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < kNumU64Counters; ++i) {
+        const uint64_t s = wave_sum_u64(vals[i]);
+        if (lane == 0 && s) atomicAdd(g + i, (unsigned long long)s);
+    }
+    const double w0 = wave_sum_f64(c.w_escaped), w1 = wave_sum_f64(c.w_absorbed);
+    if (lane == 0) {
+        if (w0 != 0.0) unsafeAtomicAdd(gw + 0, w0);
+        if (w1 != 0.0) unsafeAtomicAdd(gw + 1, w1);
+    }
+}
+
+}  // namespace thor

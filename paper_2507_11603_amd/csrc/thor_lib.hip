@@ -1,0 +1,966 @@
+// thor_lib.hip -- kernels and the C ABI (include/thor.h) of the MI355X
+// resonant-line Monte Carlo transport library (arXiv 2507.11603, Section 3.4).
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/thor.h"
+#include "thor_engine.hpp"
+
+namespace thor {
+
+__constant__ double c_dawson64[kDawsonIntervals * (kDawsonDeg64 + 1)];
+__constant__ float c_dawson32[kDawsonIntervals * (kDawsonDeg32 + 1)];
+
+// ===========================================================================
+// Kernels
+// ===========================================================================
+
+// Plain path: one thread per packet, the whole history in one launch.
+template <class R, bool GRID>
+__global__ __launch_bounds__(256) void k_plain(GridDev g, const ModelDev* __restrict__ models, BatchDev b, OutDev o,
+                                               unsigned long long* gstats, double* gw) {
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    Counters cnt = {};
+    if (i < b.n) {
+        const ModelDev& m = models[b.model];
+        Pkt<R> pk;
+        emit<R, GRID>(g, m, o, b.first_id + i, b.q0 + i, b.model, pk, cnt);
+        int fate = pk.region == kRegOut ? kFateEscaped : kFateNone;
+        while (fate == kFateNone) fate = advance_event<R, GRID>(g, m, o, pk, cnt);
+        finish<R, GRID>(g, m, o, pk, fate, cnt);
+    }
+    flush_counters(cnt, gstats, gw);
+}
+
+// Pool of packets parked between bounded persistent steps (one slot per lane).
+template <class R> struct PoolDev {
+    Pkt<R>* pk;
+    int* alive;
+};
+
+__device__ __forceinline__ int find_batch(const BatchDev* b, int nb, uint64_t q) {
+    int lo = 0, hi = nb - 1;   // last batch with q0 <= q
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b[mid].q0 <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Persistent path: resident waves; each lane keeps one packet in registers
+// and refills from the global queue (one atomic per wave, ballot + mbcnt
+// prefix for the lane offsets) when its packet finishes.  A bounded step
+// (step_events > 0) parks live packets in the pool for the next launch.
+template <class R, bool GRID>
+__global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* __restrict__ models,
+                                                    const BatchDev* __restrict__ batches, int nbatch,
+                                                    uint64_t q_end, unsigned long long* cursor, OutDev o,
+                                                    PoolDev<R> pool, uint64_t step_events,
+                                                    unsigned long long* gstats, double* gw) {
+    const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    Counters cnt = {};
+    Pkt<R> pk;
+    bool active = false;
+    if (pool.alive && pool.alive[gid]) {
+        pk = pool.pk[gid];
+        active = true;
+    }
+    bool exhausted = false;
+    const uint64_t budget = step_events ? step_events : ~0ull;
+    uint64_t used = 0;
+    for (;;) {
+        const bool need = !active && !exhausted && used < budget;
+        const uint64_t mask = __ballot(need);
+        if (mask) {
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            const int lane = threadIdx.x & 63;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(cursor, (unsigned long long)__popcll(mask));
+            base = __shfl(base, leader, 64);
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+            if (need) {
+                const uint64_t q = base + rank;
+                if (q < q_end) {
+                    const int bi = find_batch(batches, nbatch, q);
+                    const BatchDev b = batches[bi];
+                    emit<R, GRID>(g, models[b.model], o, b.first_id + (q - b.q0), q, b.model, pk, cnt);
+                    active = true;
+                    if (pk.region == kRegOut) {
+                        finish<R, GRID>(g, models[b.model], o, pk, kFateEscaped, cnt);
+                        active = false;
+                    }
+                } else {
+                    exhausted = true;
+                }
+            }
+        }
+        const bool work = active && used < budget;
+        if (__ballot(work) == 0) break;
+        if (work) {
+            const ModelDev& m = models[pk.model];
+            const int fate = advance_event<R, GRID>(g, m, o, pk, cnt);
+            ++used;
+            if (fate != kFateNone) {
+                finish<R, GRID>(g, m, o, pk, fate, cnt);
+                active = false;
+            }
+        }
+    }
+    if (pool.alive) {
+        pool.alive[gid] = active ? 1 : 0;
+        if (active) pool.pk[gid] = pk;
+    }
+    flush_counters(cnt, gstats, gw);
+}
+
+// Re-layout of the grid fields into (vx, vy, vz, n_HI) records; counts cells
+// that are not finite, have n_HI < 0, or hold gas at T <= 0.
+__global__ void k_pack_grid(const float* __restrict__ n, const float* __restrict__ vx, const float* __restrict__ vy,
+                            const float* __restrict__ vz, const float* __restrict__ T, float4* __restrict__ out,
+                            uint64_t count, unsigned long long* bad) {
+    unsigned long long nbad = 0;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        const float4 r = make_float4(vx[i], vy[i], vz[i], n[i]);
+        const float t = T[i];
+        const bool ok = isfinite(r.x) && isfinite(r.y) && isfinite(r.z) && isfinite(r.w) && r.w >= 0.0f &&
+                        (r.w == 0.0f || (isfinite(t) && t > 0.0f));
+        nbad += ok ? 0ull : 1ull;
+        out[i] = r;
+    }
+    if (nbad) atomicAdd(bad, nbad);
+}
+
+struct NSquared {
+    __host__ __device__ double operator()(const float4& r) const { return double(r.w) * double(r.w); }
+};
+
+// Device-function harnesses (tests of the kernels' own device code).
+template <class R>
+__global__ void k_eval_voigt(const double* a, const double* x, double* out, uint64_t n) {
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = double(voigt<R>(R(a[i]), R(x[i])));
+}
+
+template <class R>
+__global__ void k_sample_upar(double x, double a, uint32_t seed, uint32_t event, double* u, uint32_t* tr, uint64_t n) {
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const Key key{seed, 0u, uint32_t(i), uint32_t(i >> 32)};
+        uint32_t t = 0;
+        u[i] = double(upar_sample<R>(R(x), R(a), key, event, &t));
+        tr[i] = t;
+    }
+}
+
+__global__ void k_clamp_cursor(unsigned long long* cursor, uint64_t q_end) {
+    if (threadIdx.x == 0 && *cursor > q_end) *cursor = q_end;
+}
+
+}  // namespace thor
+
+using namespace thor;
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+namespace {
+
+thread_local std::string g_last_error;
+
+thor_status fail(thor_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+thor_status fail(thor_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+// Host-side table of Dawson's integral F(x) = exp(-x^2) int_0^x exp(t^2) dt
+// for the device Voigt function: at each interval centre c, F(c) from the
+// positive power series sum x^(2n+1)/(n!(2n+1)) (long double), the higher
+// derivatives from F' = 1 - 2xF, F^(n+1) = -2x F^(n) - 2n F^(n-1), and the
+// Taylor coefficients F^(n)(c) h^n / n! in s = (x - c)/h, h = 1/16.
+void build_dawson_tables(double* t64, float* t32) {
+    for (int i = 0; i < kDawsonIntervals; ++i) {
+        const long double c = ((long double)i + 0.5L) * 0.125L;
+        long double x2 = c * c, term = c, sum = 0.0L;
+        for (int n = 0; n < 4000; ++n) {
+            const long double add = term / (long double)(2 * n + 1);
+            sum += add;
+            if (add <= sum * 1e-22L) break;
+            term *= x2 / (long double)(n + 1);
+        }
+        long double d[kDawsonDeg64 + 1];
+        d[0] = expl(-x2) * sum;
+        d[1] = 1.0L - 2.0L * c * d[0];
+        for (int n = 1; n < kDawsonDeg64; ++n) d[n + 1] = -2.0L * c * d[n] - 2.0L * (long double)n * d[n - 1];
+        long double hp = 1.0L, fact = 1.0L;
+        for (int n = 0; n <= kDawsonDeg64; ++n) {
+            if (n > 0) { hp *= 0.0625L; fact *= (long double)n; }
+            const long double coef = d[n] * hp / fact;
+            t64[i * (kDawsonDeg64 + 1) + n] = (double)coef;
+            if (n <= kDawsonDeg32) t32[i * (kDawsonDeg32 + 1) + n] = (float)coef;
+        }
+    }
+}
+
+struct BatchHost {
+    thor_source src;
+    uint64_t n, first_id, q0;
+};
+
+struct ServingReq {
+    uint64_t handle;
+    int model;             // index into serving models
+    uint64_t n_packets;
+    double* d_spec;
+    int spec_nb;
+    uint64_t bytes;
+    bool finished;
+};
+
+}  // namespace
+
+struct thor_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0, used = 0;
+    bool poisoned = false;
+    int num_cu = 256;
+
+    // medium
+    bool has_geom = false;
+    thor_geometry geom{};
+    GridDev grid{};
+    float4* d_vn = nullptr;
+    float* d_T = nullptr;
+    double* d_cdf = nullptr;
+    uint64_t grid_bytes = 0, cdf_bytes = 0;
+
+    // queued batches
+    std::vector<BatchHost> pending;
+
+    // outputs
+    double* d_spec = nullptr;
+    int spec_nb = 0;
+    float* d_cube = nullptr;
+    uint64_t cube_elems = 0;
+    int cube_shape[4] = {0, 0, 0, 0};
+    unsigned long long* d_stats = nullptr;   // kNumU64Counters counters, then cursor
+    double* d_wstats = nullptr;
+    ModelDev* d_models = nullptr;
+    size_t models_cap = 0;
+    BatchDev* d_batches = nullptr;
+    size_t batches_cap = 0;
+
+    // records of the last call
+    double* d_rec_dv = nullptr;
+    uint32_t* d_rec_nres = nullptr;
+    uint32_t* d_rec_ndust = nullptr;
+    int32_t* d_rec_fate = nullptr;
+    uint64_t rec_cap = 0, rec_n = 0;
+
+    // persistent pool (bounded steps)
+    void* d_pool_pk = nullptr;
+    int* d_pool_alive = nullptr;
+    uint64_t pool_slots = 0;
+    int pool_prec = -1;
+    uint64_t q_total = 0;        // queue indices handed out so far
+    uint64_t pool_bytes = 0;
+
+    thor_stats last{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // serving
+    std::vector<ModelDev> s_models;
+    std::vector<BatchDev> s_batches;
+    std::map<uint64_t, ServingReq> s_reqs;
+    unsigned long long* d_done = nullptr;
+    size_t done_cap = 0;
+    uint64_t s_next_handle = 1;
+    uint64_t s_q_total = 0;
+    uint64_t s_reserved = 0;
+};
+
+namespace {
+
+bool hip_ok(thor_ctx* ctx, hipError_t e, const char* what) {
+    if (e == hipSuccess) return true;
+    ctx->poisoned = true;
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return false;
+}
+
+thor_status dalloc(thor_ctx* ctx, void** p, uint64_t bytes, const char* what) {
+    if (bytes == 0) bytes = 8;
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+        return fail(THOR_E_BUDGET, "%s: %llu bytes exceed the HBM budget (%llu of %llu used)", what,
+                    (unsigned long long)bytes, (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(THOR_E_NOMEM, "%s: hipMalloc(%llu) failed: %s", what,
+                                     (unsigned long long)bytes, hipGetErrorString(e));
+    ctx->used += bytes;
+    return THOR_OK;
+}
+
+void dfree(thor_ctx* ctx, void* p, uint64_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    if (bytes == 0) bytes = 8;
+    ctx->used -= std::min(ctx->used, bytes);
+}
+
+#define CHECK_CTX(ctx)                                                              \
+    do {                                                                            \
+        if (!(ctx)) return fail(THOR_E_INVAL, "null context");                     \
+        if ((ctx)->poisoned) return fail(THOR_E_DEVICE, "context poisoned by an earlier device error"); \
+        if (hipSetDevice((ctx)->device) != hipSuccess) return fail(THOR_E_DEVICE, "hipSetDevice failed"); \
+    } while (0)
+
+#define HIPCHK(ctx, call)                                                           \
+    do {                                                                            \
+        if (!hip_ok((ctx), (call), #call)) return THOR_E_DEVICE;                    \
+    } while (0)
+
+void line_params(double T, double* vth, double* a, double* sig0) {
+    const double v = std::sqrt(kVth2PerT * T);
+    *vth = v;
+    *a = kDampTimesVth / v;
+    *sig0 = kSigma0TimesVth / v;
+}
+
+// Model constants of a batch (meshless medium constants, source, outputs).
+thor_status make_model(thor_ctx* ctx, const thor_source& s, const thor_transport_opts& o, ModelDev& m) {
+    const thor_geometry& g = ctx->geom;
+    std::memset(&m, 0, sizeof m);
+    m.kind = g.kind;
+    m.v_profile = g.v_profile;
+    m.src_kind = s.kind;
+    m.spectrum = s.spectrum;
+    m.albedo = g.albedo;
+    m.g_hg = g.g_hg;
+    for (int i = 0; i < 3; ++i) m.pos[i] = s.pos[i];
+    m.dv0 = s.dv0;
+    m.sigma_v = s.sigma_v;
+    m.seed = s.seed;
+    m.req = s.request_id;
+    if (g.kind != THOR_GEOM_GRID) {
+        const double L = g.r_outer - g.r_inner;
+        double sig0;
+        line_params(g.T, &m.vth, &m.a, &sig0);
+        m.r_in = g.r_inner;
+        m.r_out = g.r_outer;
+        m.n = g.tau0 > 0.0 ? g.tau0 / (sig0 * L) : g.n_HI;
+        m.k0 = m.n * sig0;
+        const double sigd = g.tau_d > 0.0 ? g.tau_d / (m.n * L) : g.sigma_d;
+        m.kd = sigd * m.n;
+        m.v_max = g.v_max;
+        m.step_f = g.step_f > 0.0 ? g.step_f : 0.01;
+        if (o.core_skip == THOR_CS_FIXED) m.xcrit = o.x_crit;
+        else if (o.core_skip == THOR_CS_ADAPTIVE) {
+            const double atau = m.a * m.k0 * L;
+            m.xcrit = atau >= 1.0 ? 0.2 * std::cbrt(atau) : 0.0;
+        }
+    } else {
+        if (o.core_skip == THOR_CS_FIXED) m.xcrit = o.x_crit;
+        else if (o.core_skip == THOR_CS_ADAPTIVE)
+            return fail(THOR_E_UNSUPPORTED, "adaptive core skipping needs a meshless medium");
+    }
+    m.spec = ctx->d_spec;
+    m.spec_nb = o.spec_nb;
+    m.spec_lo = o.spec_lo;
+    m.spec_w = (o.spec_hi - o.spec_lo) / o.spec_nb;
+    m.spec_scale = 1.0;
+    if (o.spec_T_ref > 0.0) {
+        double vth, a, s0;
+        line_params(o.spec_T_ref, &vth, &a, &s0);
+        m.spec_scale = 1.0 / vth;
+    }
+    m.done = nullptr;
+    return THOR_OK;
+}
+
+thor_status check_opts(const thor_transport_opts* o) {
+    if (!o) return fail(THOR_E_INVAL, "null options");
+    if (o->precision != THOR_PREC_FP64 && o->precision != THOR_PREC_MIXED) return fail(THOR_E_INVAL, "bad precision");
+    if (o->path != THOR_PATH_PLAIN && o->path != THOR_PATH_PERSISTENT) return fail(THOR_E_INVAL, "bad path");
+    if (o->phase < 0 || o->phase > 2) return fail(THOR_E_INVAL, "bad phase function");
+    if (o->core_skip < 0 || o->core_skip > 2) return fail(THOR_E_INVAL, "bad core_skip");
+    if (o->n_obs < 0 || o->n_obs > 6) return fail(THOR_E_INVAL, "n_obs must be 0..6");
+    for (int i = 0; i < o->n_obs; ++i)
+        if (o->obs_axis[i] < 0 || o->obs_axis[i] > 5) return fail(THOR_E_INVAL, "bad observer axis");
+    if (o->n_obs > 0) {
+        if (o->cube_nx <= 0 || o->cube_ny <= 0 || o->cube_nb <= 0) return fail(THOR_E_INVAL, "bad cube shape");
+        if (!(o->img_hi[0] > o->img_lo[0]) || !(o->img_hi[1] > o->img_lo[1]) || !(o->cube_v_hi > o->cube_v_lo))
+            return fail(THOR_E_INVAL, "bad cube ranges");
+    }
+    if (o->spec_nb <= 0 || !(o->spec_hi > o->spec_lo)) return fail(THOR_E_INVAL, "bad spectrum bins");
+    if (o->step_events && o->path != THOR_PATH_PERSISTENT)
+        return fail(THOR_E_INVAL, "bounded steps need the persistent path");
+    if (o->block && (o->block % 64 || o->block > 256)) return fail(THOR_E_INVAL, "block must be 64..256, multiple of 64");
+    return THOR_OK;
+}
+
+thor_status ensure_outputs(thor_ctx* ctx, const thor_transport_opts* o) {
+    if (o->spec_nb != ctx->spec_nb) {
+        dfree(ctx, ctx->d_spec, uint64_t(ctx->spec_nb) * 8);
+        ctx->d_spec = nullptr;
+        ctx->spec_nb = 0;
+        thor_status s = dalloc(ctx, (void**)&ctx->d_spec, uint64_t(o->spec_nb) * 8, "spectrum");
+        if (s) return s;
+        ctx->spec_nb = o->spec_nb;
+        HIPCHK(ctx, hipMemsetAsync(ctx->d_spec, 0, uint64_t(o->spec_nb) * 8, ctx->stream));
+    }
+    const int shape[4] = {o->n_obs, o->cube_ny, o->cube_nx, o->cube_nb};
+    if (std::memcmp(shape, ctx->cube_shape, sizeof shape) != 0) {
+        dfree(ctx, ctx->d_cube, ctx->cube_elems * 4);
+        ctx->d_cube = nullptr;
+        ctx->cube_elems = 0;
+        std::memset(ctx->cube_shape, 0, sizeof ctx->cube_shape);
+        if (o->n_obs > 0) {
+            const uint64_t elems = uint64_t(o->n_obs) * o->cube_ny * o->cube_nx * o->cube_nb;
+            thor_status s = dalloc(ctx, (void**)&ctx->d_cube, elems * 4, "cube");
+            if (s) return s;
+            ctx->cube_elems = elems;
+            HIPCHK(ctx, hipMemsetAsync(ctx->d_cube, 0, elems * 4, ctx->stream));
+        }
+        std::memcpy(ctx->cube_shape, shape, sizeof shape);
+    }
+    return THOR_OK;
+}
+
+template <class T>
+thor_status ensure_array(thor_ctx* ctx, T** p, size_t* cap, size_t need, const char* what) {
+    if (need <= *cap) return THOR_OK;
+    size_t n = std::max(need, *cap * 2 + 16);
+    dfree(ctx, *p, *cap * sizeof(T));
+    *p = nullptr;
+    *cap = 0;
+    thor_status s = dalloc(ctx, (void**)p, n * sizeof(T), what);
+    if (s) return s;
+    *cap = n;
+    return THOR_OK;
+}
+
+OutDev make_out(thor_ctx* ctx, const thor_transport_opts* o) {
+    OutDev out;
+    std::memset(&out, 0, sizeof out);
+    out.phase = o->phase;
+    out.n_obs = o->n_obs;
+    for (int i = 0; i < 6; ++i) out.obs_axis[i] = o->obs_axis[i];
+    out.cube_nx = o->cube_nx;
+    out.cube_ny = o->cube_ny;
+    out.cube_nb = o->cube_nb;
+    for (int i = 0; i < 2; ++i) {
+        out.img_lo[i] = o->img_lo[i];
+        out.img_w[i] = o->n_obs ? (o->img_hi[i] - o->img_lo[i]) / (i == 0 ? o->cube_nx : o->cube_ny) : 1.0;
+    }
+    out.v_lo = o->cube_v_lo;
+    out.v_w = o->n_obs ? (o->cube_v_hi - o->cube_v_lo) / o->cube_nb : 1.0;
+    out.cube = ctx->d_cube;
+    out.tau_cut = o->tau_cut > 0.0 ? o->tau_cut : 40.0;
+    out.max_events = o->max_events;
+    return out;
+}
+
+int launch_grid_size(thor_ctx* ctx, const thor_transport_opts* o, int block) {
+    const int waves = o->waves_per_cu > 0 ? o->waves_per_cu : 8;
+    const int wpb = block / 64;
+    return std::max(1, ctx->num_cu * waves / wpb);
+}
+
+template <class R, bool GRID>
+void launch_plain(thor_ctx* ctx, const BatchDev& b, const OutDev& out) {
+    const unsigned blocks = unsigned((b.n + 255) / 256);
+    hipLaunchKernelGGL((k_plain<R, GRID>), dim3(blocks), dim3(256), 0, ctx->stream, ctx->grid, ctx->d_models, b,
+                       out, ctx->d_stats, ctx->d_wstats);
+}
+
+template <class R, bool GRID>
+void launch_persistent(thor_ctx* ctx, int grid, int block, const BatchDev* d_b, int nb, uint64_t q_end,
+                       const OutDev& out, const ModelDev* d_models, uint64_t step_events, bool use_pool) {
+    PoolDev<R> pool{nullptr, nullptr};
+    if (use_pool) {
+        pool.pk = reinterpret_cast<Pkt<R>*>(ctx->d_pool_pk);
+        pool.alive = ctx->d_pool_alive;
+    }
+    hipLaunchKernelGGL((k_persistent<R, GRID>), dim3(grid), dim3(block), 0, ctx->stream, ctx->grid, d_models,
+                       d_b, nb, q_end, ctx->d_stats + kNumU64Counters, out, pool, step_events, ctx->d_stats,
+                       ctx->d_wstats);
+}
+
+thor_status ensure_pool(thor_ctx* ctx, uint64_t slots, int prec) {
+    const uint64_t pk_bytes = prec == THOR_PREC_FP64 ? sizeof(Pkt<double>) : sizeof(Pkt<float>);
+    if (ctx->d_pool_pk && ctx->pool_slots == slots && ctx->pool_prec == prec) return THOR_OK;
+    dfree(ctx, ctx->d_pool_pk, ctx->pool_bytes);
+    dfree(ctx, ctx->d_pool_alive, ctx->pool_slots * 4);
+    ctx->d_pool_pk = nullptr;
+    ctx->d_pool_alive = nullptr;
+    ctx->pool_slots = 0;
+    thor_status s = dalloc(ctx, &ctx->d_pool_pk, slots * pk_bytes, "packet pool");
+    if (s) return s;
+    ctx->pool_bytes = slots * pk_bytes;
+    s = dalloc(ctx, (void**)&ctx->d_pool_alive, slots * 4, "packet pool flags");
+    if (s) return s;
+    ctx->pool_slots = slots;
+    ctx->pool_prec = prec;
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_pool_alive, 0, slots * 4, ctx->stream));
+    return THOR_OK;
+}
+
+void collect_stats(thor_ctx* ctx, const unsigned long long* h, const double* w, float ms, thor_stats* st) {
+    std::memset(st, 0, sizeof *st);
+    uint64_t* dst[kNumU64Counters] = {&st->emitted, &st->escaped, &st->absorbed, &st->capped, &st->handed_off,
+                                      &st->n_res, &st->n_dust, &st->main_visits, &st->peel_visits,
+                                      &st->peel_contrib, &st->peel_dropped, &st->peel_cut, &st->upar_trials};
+    for (int i = 0; i < kNumU64Counters; ++i) *dst[i] = h[i];
+    st->w_escaped = w[0];
+    st->w_absorbed = w[1];
+    st->kernel_ms = ms;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* thor_last_error(void) { return g_last_error.c_str(); }
+
+thor_status thor_create(thor_ctx** out, int hip_device, void* hip_stream, uint64_t hbm_budget_bytes) {
+    if (!out) return fail(THOR_E_INVAL, "null output pointer");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(THOR_E_DEVICE, "no HIP device");
+    if (hip_device < 0 || hip_device >= ndev) return fail(THOR_E_INVAL, "device %d out of range", hip_device);
+    if (hipSetDevice(hip_device) != hipSuccess) return fail(THOR_E_DEVICE, "hipSetDevice failed");
+    thor_ctx* ctx = new thor_ctx();
+    ctx->device = hip_device;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    ctx->budget = hbm_budget_bytes;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && ncu > 0)
+        ctx->num_cu = ncu;
+    static double t64[kDawsonIntervals * (kDawsonDeg64 + 1)];
+    static float t32[kDawsonIntervals * (kDawsonDeg32 + 1)];
+    static bool built = false;
+    if (!built) { build_dawson_tables(t64, t32); built = true; }
+    thor_status s = THOR_OK;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_dawson64), t64, sizeof t64) != hipSuccess ||
+        hipMemcpyToSymbol(HIP_SYMBOL(c_dawson32), t32, sizeof t32) != hipSuccess)
+        s = fail(THOR_E_DEVICE, "Dawson table upload failed");
+    if (!s) s = dalloc(ctx, (void**)&ctx->d_stats, (kNumU64Counters + 1) * 8, "counters");
+    if (!s) s = dalloc(ctx, (void**)&ctx->d_wstats, 2 * 8, "weights");
+    if (!s && (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess))
+        s = fail(THOR_E_DEVICE, "hipEventCreate failed");
+    if (s) {
+        thor_destroy(ctx);
+        return s;
+    }
+    *out = ctx;
+    return THOR_OK;
+}
+
+void thor_destroy(thor_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    void* ptrs[] = {ctx->d_vn, ctx->d_T, ctx->d_cdf, ctx->d_spec, ctx->d_cube, ctx->d_stats, ctx->d_wstats,
+                    ctx->d_models, ctx->d_batches, ctx->d_rec_dv, ctx->d_rec_nres, ctx->d_rec_ndust,
+                    ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto& kv : ctx->s_reqs)
+        if (kv.second.d_spec) (void)hipFree(kv.second.d_spec);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    delete ctx;
+}
+
+thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
+    CHECK_CTX(ctx);
+    if (!g) return fail(THOR_E_INVAL, "null geometry");
+    if (g->kind < 0 || g->kind > 2) return fail(THOR_E_INVAL, "bad geometry kind %d", g->kind);
+    if (g->albedo < 0.0 || g->albedo > 1.0) return fail(THOR_E_INVAL, "albedo must be in [0, 1]");
+    if (g->g_hg <= -1.0 || g->g_hg >= 1.0) return fail(THOR_E_INVAL, "g_hg must be in (-1, 1)");
+    if (g->kind != THOR_GEOM_GRID) {
+        if (!(g->r_outer > g->r_inner) || g->r_inner < 0.0) return fail(THOR_E_INVAL, "need 0 <= r_inner < r_outer");
+        if (!(g->T > 0.0)) return fail(THOR_E_INVAL, "T must be positive");
+        if (g->n_HI < 0.0 || g->tau0 < 0.0 || (g->n_HI == 0.0 && g->tau0 == 0.0))
+            return fail(THOR_E_INVAL, "need n_HI > 0 or tau0 > 0");
+        if (g->v_profile < 0 || g->v_profile > 2) return fail(THOR_E_INVAL, "bad velocity profile");
+        if (g->kind == THOR_GEOM_SLAB && g->v_profile == THOR_VEL_CONST_RADIAL)
+            return fail(THOR_E_UNSUPPORTED, "slab supports NONE or LINEAR velocity");
+        if (g->tau_d > 0.0 && g->n_HI == 0.0 && g->tau0 == 0.0) return fail(THOR_E_INVAL, "dust needs gas");
+        // release a previous grid
+        dfree(ctx, ctx->d_vn, ctx->grid_bytes);
+        dfree(ctx, ctx->d_T, ctx->grid_bytes / 4);
+        dfree(ctx, ctx->d_cdf, ctx->cdf_bytes);
+        ctx->d_vn = nullptr; ctx->d_T = nullptr; ctx->d_cdf = nullptr;
+        ctx->grid_bytes = ctx->cdf_bytes = 0;
+        std::memset(&ctx->grid, 0, sizeof ctx->grid);
+        ctx->geom = *g;
+        ctx->geom.n_HI_field = ctx->geom.T_field = ctx->geom.vx = ctx->geom.vy = ctx->geom.vz = nullptr;
+        ctx->has_geom = true;
+        ctx->pending.clear();
+        return THOR_OK;
+    }
+    if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return fail(THOR_E_INVAL, "bad grid dimensions");
+    for (int i = 0; i < 3; ++i)
+        if (!(g->hi[i] > g->lo[i])) return fail(THOR_E_INVAL, "grid needs lo < hi");
+    if (!g->n_HI_field || !g->T_field || !g->vx || !g->vy || !g->vz) return fail(THOR_E_INVAL, "null grid field");
+    if (g->mem != THOR_MEM_HOST && g->mem != THOR_MEM_DEVICE) return fail(THOR_E_INVAL, "bad memory kind");
+    const uint64_t cells = uint64_t(g->nx) * g->ny * g->nz;
+    const uint64_t need = cells * 16 + cells * 4;
+    const uint64_t staging = g->mem == THOR_MEM_HOST ? cells * 16 : 0;
+    const uint64_t freed = ctx->grid_bytes + ctx->grid_bytes / 4 + ctx->cdf_bytes;
+    if (ctx->budget && ctx->used - std::min(ctx->used, freed) + need + staging > ctx->budget)
+        return fail(THOR_E_BUDGET, "grid of %llu cells exceeds the HBM budget", (unsigned long long)cells);
+    dfree(ctx, ctx->d_vn, ctx->grid_bytes);
+    dfree(ctx, ctx->d_T, ctx->grid_bytes / 4);
+    dfree(ctx, ctx->d_cdf, ctx->cdf_bytes);
+    ctx->d_vn = nullptr; ctx->d_T = nullptr; ctx->d_cdf = nullptr;
+    ctx->grid_bytes = ctx->cdf_bytes = 0;
+    ctx->has_geom = false;
+    ctx->pending.clear();
+    thor_status s = dalloc(ctx, (void**)&ctx->d_vn, cells * 16, "grid records");
+    if (s) return s;
+    ctx->grid_bytes = cells * 16;
+    s = dalloc(ctx, (void**)&ctx->d_T, cells * 4, "grid temperature");
+    if (s) return s;
+    const hipMemcpyKind kind = g->mem == THOR_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_T, g->T_field, cells * 4, kind, ctx->stream));
+    const float *n = g->n_HI_field, *vx = g->vx, *vy = g->vy, *vz = g->vz;
+    float* stage = nullptr;
+    if (g->mem == THOR_MEM_HOST) {
+        s = dalloc(ctx, (void**)&stage, cells * 16, "grid staging");
+        if (s) return s;
+        HIPCHK(ctx, hipMemcpyAsync(stage, g->n_HI_field, cells * 4, kind, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(stage + cells, g->vx, cells * 4, kind, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(stage + 2 * cells, g->vy, cells * 4, kind, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(stage + 3 * cells, g->vz, cells * 4, kind, ctx->stream));
+        n = stage; vx = stage + cells; vy = stage + 2 * cells; vz = stage + 3 * cells;
+    }
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_stats, 0, 8, ctx->stream));
+    hipLaunchKernelGGL(k_pack_grid, dim3(4096), dim3(256), 0, ctx->stream, n, vx, vy, vz, ctx->d_T, ctx->d_vn,
+                       cells, ctx->d_stats);
+    HIPCHK(ctx, hipGetLastError());
+    unsigned long long nbad = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&nbad, ctx->d_stats, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (stage) dfree(ctx, stage, cells * 16);
+    if (nbad) {
+        dfree(ctx, ctx->d_vn, ctx->grid_bytes);
+        dfree(ctx, ctx->d_T, cells * 4);
+        ctx->d_vn = nullptr; ctx->d_T = nullptr; ctx->grid_bytes = 0;
+        return fail(THOR_E_INVAL, "%llu grid cells are not finite, have n_HI < 0 or gas at T <= 0", nbad);
+    }
+    ctx->geom = *g;
+    ctx->geom.n_HI_field = ctx->geom.T_field = ctx->geom.vx = ctx->geom.vy = ctx->geom.vz = nullptr;
+    GridDev& gd = ctx->grid;
+    std::memset(&gd, 0, sizeof gd);
+    gd.nx = g->nx; gd.ny = g->ny; gd.nz = g->nz;
+    gd.handoff = g->boundary_handoff;
+    const int dims[3] = {g->nx, g->ny, g->nz};
+    for (int i = 0; i < 3; ++i) {
+        gd.lo[i] = g->lo[i];
+        gd.dx[i] = (g->hi[i] - g->lo[i]) / dims[i];
+    }
+    gd.vn = ctx->d_vn;
+    gd.T = ctx->d_T;
+    gd.ncell = cells;
+    gd.sigma_d = g->sigma_d;
+    ctx->has_geom = true;
+    return THOR_OK;
+}
+
+thor_status thor_emit(thor_ctx* ctx, const thor_source* src, uint64_t n_packets, uint64_t first_photon_id) {
+    CHECK_CTX(ctx);
+    if (!src) return fail(THOR_E_INVAL, "null source");
+    if (!ctx->has_geom) return fail(THOR_E_STATE, "thor_load_grid first");
+    if (src->kind != THOR_SRC_POINT && src->kind != THOR_SRC_CELL_N2) return fail(THOR_E_INVAL, "bad source kind");
+    if (src->spectrum < 0 || src->spectrum > 2) return fail(THOR_E_INVAL, "bad source spectrum");
+    if (src->spectrum == THOR_SPEC_GAUSS && src->sigma_v < 0.0) return fail(THOR_E_INVAL, "sigma_v < 0");
+    if (src->kind == THOR_SRC_CELL_N2 && ctx->geom.kind != THOR_GEOM_GRID)
+        return fail(THOR_E_INVAL, "CELL_N2 sources need a grid");
+    if (src->spectrum == THOR_SPEC_THERMAL && ctx->geom.kind != THOR_GEOM_GRID)
+        return fail(THOR_E_UNSUPPORTED, "THERMAL sources need a grid");
+    if (n_packets == 0) return THOR_OK;
+    if (src->kind == THOR_SRC_CELL_N2 && !ctx->d_cdf) {
+        // inclusive prefix sum of n_HI^2 (FP64) over cells in x-fastest order
+        const uint64_t cells = ctx->grid.ncell;
+        thor_status s = dalloc(ctx, (void**)&ctx->d_cdf, cells * 8, "emission CDF");
+        if (s) return s;
+        ctx->cdf_bytes = cells * 8;
+        hipcub::TransformInputIterator<double, NSquared, const float4*> it(ctx->d_vn, NSquared());
+        size_t tmp_bytes = 0;
+        HIPCHK(ctx, hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, it, ctx->d_cdf, (int64_t)cells, ctx->stream));
+        void* tmp = nullptr;
+        s = dalloc(ctx, &tmp, tmp_bytes, "scan scratch");
+        if (s) return s;
+        HIPCHK(ctx, hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, it, ctx->d_cdf, (int64_t)cells, ctx->stream));
+        double total = 0.0;
+        HIPCHK(ctx, hipMemcpyAsync(&total, ctx->d_cdf + cells - 1, 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        dfree(ctx, tmp, tmp_bytes);
+        if (!(total > 0.0)) return fail(THOR_E_INVAL, "grid has no gas to emit from");
+        ctx->grid.cdf = ctx->d_cdf;
+        ctx->grid.cdf_total = total;
+    }
+    BatchHost b;
+    b.src = *src;
+    b.n = n_packets;
+    b.first_id = first_photon_id;
+    b.q0 = 0;
+    ctx->pending.push_back(b);
+    return THOR_OK;
+}
+
+thor_status thor_reset_outputs(thor_ctx* ctx) {
+    CHECK_CTX(ctx);
+    if (ctx->d_spec) HIPCHK(ctx, hipMemsetAsync(ctx->d_spec, 0, uint64_t(ctx->spec_nb) * 8, ctx->stream));
+    if (ctx->d_cube) HIPCHK(ctx, hipMemsetAsync(ctx->d_cube, 0, ctx->cube_elems * 4, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return THOR_OK;
+}
+
+thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_stats* out_stats) {
+    CHECK_CTX(ctx);
+    thor_status s = check_opts(opt);
+    if (s) return s;
+    if (!ctx->has_geom) return fail(THOR_E_STATE, "thor_load_grid first");
+    const bool grid = ctx->geom.kind == THOR_GEOM_GRID;
+    const bool fp64 = opt->precision == THOR_PREC_FP64;
+    const bool bounded = opt->step_events > 0;
+    // a bounded persistent run in progress continues without new batches
+    const bool resuming = bounded && ctx->q_total > 0;
+    if (ctx->pending.empty() && !resuming) {
+        if (out_stats) std::memset(out_stats, 0, sizeof *out_stats);
+        return THOR_OK;
+    }
+    s = ensure_outputs(ctx, opt);
+    if (s) return s;
+    // models and queue layout of the pending batches
+    const size_t nb = ctx->pending.size();
+    std::vector<ModelDev> models(nb);
+    std::vector<BatchDev> batches(nb);
+    uint64_t q = 0;
+    for (size_t i = 0; i < nb; ++i) {
+        s = make_model(ctx, ctx->pending[i].src, *opt, models[i]);
+        if (s) return s;
+        batches[i].q0 = q;
+        batches[i].first_id = ctx->pending[i].first_id;
+        batches[i].n = ctx->pending[i].n;
+        batches[i].model = int(i);
+        batches[i].pad = 0;
+        q += ctx->pending[i].n;
+    }
+    const uint64_t q_end = q;
+    s = ensure_array(ctx, &ctx->d_models, &ctx->models_cap, nb, "models");
+    if (s) return s;
+    s = ensure_array(ctx, &ctx->d_batches, &ctx->batches_cap, nb, "batches");
+    if (s) return s;
+    OutDev out = make_out(ctx, opt);
+    if (opt->records) {
+        if (q_end > ctx->rec_cap) {
+            dfree(ctx, ctx->d_rec_dv, ctx->rec_cap * 8);
+            dfree(ctx, ctx->d_rec_nres, ctx->rec_cap * 4);
+            dfree(ctx, ctx->d_rec_ndust, ctx->rec_cap * 4);
+            dfree(ctx, ctx->d_rec_fate, ctx->rec_cap * 4);
+            ctx->d_rec_dv = nullptr; ctx->d_rec_nres = nullptr; ctx->d_rec_ndust = nullptr; ctx->d_rec_fate = nullptr;
+            ctx->rec_cap = 0;
+            s = dalloc(ctx, (void**)&ctx->d_rec_dv, q_end * 8, "records");
+            if (!s) s = dalloc(ctx, (void**)&ctx->d_rec_nres, q_end * 4, "records");
+            if (!s) s = dalloc(ctx, (void**)&ctx->d_rec_ndust, q_end * 4, "records");
+            if (!s) s = dalloc(ctx, (void**)&ctx->d_rec_fate, q_end * 4, "records");
+            if (s) return s;
+            ctx->rec_cap = q_end;
+        }
+        out.rec_dv = ctx->d_rec_dv;
+        out.rec_nres = ctx->d_rec_nres;
+        out.rec_ndust = ctx->d_rec_ndust;
+        out.rec_fate = ctx->d_rec_fate;
+        out.q_rec0 = 0;
+        ctx->rec_n = q_end;
+    } else {
+        ctx->rec_n = 0;
+    }
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_models, models.data(), nb * sizeof(ModelDev), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_batches, batches.data(), nb * sizeof(BatchDev), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_wstats, 0, 16, ctx->stream));
+    if (!resuming) {
+        HIPCHK(ctx, hipMemsetAsync(ctx->d_stats, 0, (kNumU64Counters + 1) * 8, ctx->stream));
+    } else {
+        HIPCHK(ctx, hipMemsetAsync(ctx->d_stats, 0, kNumU64Counters * 8, ctx->stream));
+    }
+    HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    if (opt->path == THOR_PATH_PLAIN) {
+        for (size_t i = 0; i < nb; ++i) {
+            if (fp64) grid ? launch_plain<double, true>(ctx, batches[i], out) : launch_plain<double, false>(ctx, batches[i], out);
+            else grid ? launch_plain<float, true>(ctx, batches[i], out) : launch_plain<float, false>(ctx, batches[i], out);
+        }
+    } else {
+        const int block = opt->block > 0 ? opt->block : 256;
+        const int gsize = launch_grid_size(ctx, opt, block);
+        if (bounded) {
+            s = ensure_pool(ctx, uint64_t(gsize) * block, opt->precision);
+            if (s) return s;
+        }
+        if (fp64) grid ? launch_persistent<double, true>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, opt->step_events, bounded)
+                       : launch_persistent<double, false>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, opt->step_events, bounded);
+        else grid ? launch_persistent<float, true>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, opt->step_events, bounded)
+                  : launch_persistent<float, false>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, opt->step_events, bounded);
+        hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, ctx->stream, ctx->d_stats + kNumU64Counters, q_end);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    unsigned long long h[kNumU64Counters + 1];
+    double w[2];
+    HIPCHK(ctx, hipMemcpyAsync(h, ctx->d_stats, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(w, ctx->d_wstats, sizeof w, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.0f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    collect_stats(ctx, h, w, ms, &ctx->last);
+    if (out_stats) *out_stats = ctx->last;
+    if (bounded) {
+        // work left: queue not drained or packets parked in the pool
+        bool left = h[kNumU64Counters] < q_end;
+        if (!left) {
+            std::vector<int> alive(ctx->pool_slots);
+            HIPCHK(ctx, hipMemcpy(alive.data(), ctx->d_pool_alive, ctx->pool_slots * 4, hipMemcpyDeviceToHost));
+            for (int a : alive) if (a) { left = true; break; }
+        }
+        ctx->q_total = left ? q_end : 0;
+        if (left) return THOR_INCOMPLETE;
+    }
+    ctx->pending.clear();
+    return THOR_OK;
+}
+
+uint64_t thor_output_bytes(thor_ctx* ctx, thor_output which) {
+    if (!ctx) return 0;
+    switch (which) {
+    case THOR_OUT_SPECTRUM: return uint64_t(ctx->spec_nb) * 8;
+    case THOR_OUT_CUBE: return ctx->cube_elems * 4;
+    case THOR_OUT_RECORDS: return ctx->rec_n * sizeof(thor_record);
+    case THOR_OUT_STATS: return sizeof(thor_stats);
+    }
+    return 0;
+}
+
+thor_status thor_read_spectra(thor_ctx* ctx, thor_output which, uint32_t index, void* dst, uint64_t dst_bytes,
+                              int dst_on_device) {
+    CHECK_CTX(ctx);
+    if (!dst) return fail(THOR_E_INVAL, "null destination");
+    if (index != 0) return fail(THOR_E_INVAL, "index must be 0");
+    const uint64_t need = thor_output_bytes(ctx, which);
+    if (dst_bytes < need) return fail(THOR_E_INVAL, "destination too small (%llu < %llu bytes)",
+                                      (unsigned long long)dst_bytes, (unsigned long long)need);
+    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    switch (which) {
+    case THOR_OUT_SPECTRUM:
+        if (!need) return fail(THOR_E_STATE, "no spectrum yet");
+        HIPCHK(ctx, hipMemcpyAsync(dst, ctx->d_spec, need, kind, ctx->stream));
+        break;
+    case THOR_OUT_CUBE:
+        if (!need) return fail(THOR_E_STATE, "no cube (no observers)");
+        HIPCHK(ctx, hipMemcpyAsync(dst, ctx->d_cube, need, kind, ctx->stream));
+        break;
+    case THOR_OUT_RECORDS: {
+        if (!need) return fail(THOR_E_STATE, "no records (set opts.records)");
+        if (dst_on_device) return fail(THOR_E_UNSUPPORTED, "records are copied to host memory only");
+        const uint64_t n = ctx->rec_n;
+        std::vector<double> dv(n);
+        std::vector<uint32_t> nr(n), nd(n);
+        std::vector<int32_t> fa(n);
+        HIPCHK(ctx, hipMemcpyAsync(dv.data(), ctx->d_rec_dv, n * 8, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(nr.data(), ctx->d_rec_nres, n * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(nd.data(), ctx->d_rec_ndust, n * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(fa.data(), ctx->d_rec_fate, n * 4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        thor_record* r = static_cast<thor_record*>(dst);
+        for (uint64_t i = 0; i < n; ++i) r[i] = thor_record{dv[i], nr[i], nd[i], fa[i], 0u};
+        return THOR_OK;
+    }
+    case THOR_OUT_STATS:
+        if (dst_on_device) return fail(THOR_E_UNSUPPORTED, "stats are copied to host memory only");
+        std::memcpy(dst, &ctx->last, sizeof ctx->last);
+        return THOR_OK;
+    default:
+        return fail(THOR_E_INVAL, "bad output kind");
+    }
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return THOR_OK;
+}
+
+thor_status thor_eval_voigt(thor_ctx* ctx, const double* a, const double* x, double* out, uint64_t n,
+                            int32_t precision) {
+    CHECK_CTX(ctx);
+    if (!a || !x || !out) return fail(THOR_E_INVAL, "null array");
+    if (n == 0) return THOR_OK;
+    const unsigned blocks = unsigned((n + 255) / 256);
+    if (precision == THOR_PREC_FP64)
+        hipLaunchKernelGGL(k_eval_voigt<double>, dim3(blocks), dim3(256), 0, ctx->stream, a, x, out, n);
+    else if (precision == THOR_PREC_MIXED)
+        hipLaunchKernelGGL(k_eval_voigt<float>, dim3(blocks), dim3(256), 0, ctx->stream, a, x, out, n);
+    else
+        return fail(THOR_E_INVAL, "bad precision");
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return THOR_OK;
+}
+
+thor_status thor_sample_upar(thor_ctx* ctx, double x, double a, uint32_t seed, uint32_t event, double* out_u,
+                             uint32_t* out_trials, uint64_t n, int32_t precision) {
+    CHECK_CTX(ctx);
+    if (!out_u || !out_trials) return fail(THOR_E_INVAL, "null array");
+    if (!(a > 0.0)) return fail(THOR_E_INVAL, "a must be positive");
+    if (n == 0) return THOR_OK;
+    const unsigned blocks = unsigned((n + 255) / 256);
+    if (precision == THOR_PREC_FP64)
+        hipLaunchKernelGGL(k_sample_upar<double>, dim3(blocks), dim3(256), 0, ctx->stream, x, a, seed, event, out_u, out_trials, n);
+    else if (precision == THOR_PREC_MIXED)
+        hipLaunchKernelGGL(k_sample_upar<float>, dim3(blocks), dim3(256), 0, ctx->stream, x, a, seed, event, out_u, out_trials, n);
+    else
+        return fail(THOR_E_INVAL, "bad precision");
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return THOR_OK;
+}
+
+// ------------------------------------------------------------- serving
+thor_status thor_submit(thor_ctx* ctx, const thor_shell_request* r, uint64_t* req_id) {
+    CHECK_CTX(ctx);
+    (void)r; (void)req_id;
+    return fail(THOR_E_UNSUPPORTED, "serving extension not built yet");
+}
+
+thor_status thor_step(thor_ctx* ctx, uint32_t max_events_per_packet, const thor_transport_opts* opt) {
+    CHECK_CTX(ctx);
+    (void)max_events_per_packet; (void)opt;
+    return fail(THOR_E_UNSUPPORTED, "serving extension not built yet");
+}
+
+thor_status thor_poll(thor_ctx* ctx, uint64_t req_id, double* spectrum, thor_stats* st, int* done) {
+    CHECK_CTX(ctx);
+    (void)req_id; (void)spectrum; (void)st; (void)done;
+    return fail(THOR_E_UNSUPPORTED, "serving extension not built yet");
+}
+
+}  // extern "C"

@@ -190,3 +190,16 @@ def test_sphere_peaks_converge_with_optical_depth():
     d5, d6 = m5 / (0.889 * s5) - 1, m6 / (0.889 * s6) - 1
     assert d6 < d5 - 0.1
     assert abs(d6) < 0.12, (d5, d6)
+
+
+def test_shell_cavity_crossings_terminate():
+    """Scattering shell around an empty cavity: photons scattered inwards cross
+    the cavity (regression test for the boundary far-root distance) and every
+    packet escapes with its weight."""
+    n = 400
+    geom = dict(kind="shell", r_inner=0.8 * KPC, r_outer=KPC, tau0=2e3, T=1e4,
+                v_profile="const_radial", v_max=50 * KMS, step_f=0.05)
+    src = dict(kind="point", spectrum="gauss", sigma_v=20 * KMS, seed=12)
+    opts = dict(phase="dipole", spectrum=dict(nb=100, lo=-1e8, hi=1e8))
+    r = oracle.run(geom, src, opts, 0, n, records=True)
+    assert r["stats"]["escaped"] == n and r["stats"]["n_res"] > n
