@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=2, help="steps of the plain FP64 path (0: skip)")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--turn-visits", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=400000, help="packets of the oracle sample")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -45,19 +46,20 @@ def parse():
 
 
 def run_steps(T, wl, n, steps, first_id, **kw):
+    """Queue `steps` batches of n packets (distinct photon ids) and transport
+    them with one thor_transport call: the persistent path runs all batches
+    in one launch of resident waves, the plain path one launch per batch."""
     import torch
-    tot = dict(n_res=0, n_dust=0, emitted=0, main_visits=0, peel_visits=0, kernel_ms=0.0,
-               escaped=0, absorbed=0, peel_contrib=0)
+    T.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
-        T.reset()
         T.emit(wl["src"], n, first_id + s * n)
-        code, st = T.transport(wl["opts"], **kw)
-        for k in tot:
-            tot[k] += st[k]
+    code, st = T.transport(wl["opts"], **kw)
     torch.cuda.synchronize()
-    return time.perf_counter() - t0, tot
+    dt = time.perf_counter() - t0
+    assert st["emitted"] == n * steps
+    return dt, st
 
 
 def cpu_baseline(wl, n):
@@ -101,7 +103,8 @@ def main():
         del x, y
     T = thor.Transport(0)
     T.load(wl["geom"])
-    kw = dict(precision=a.precision, path=a.path, waves_per_cu=a.waves_per_cu, block=a.block)
+    kw = dict(precision=a.precision, path=a.path, waves_per_cu=a.waves_per_cu, block=a.block,
+              visits_per_turn=a.turn_visits)
     if a.warmup:
         run_steps(T, wl, a.packets, a.warmup, 10**12, **kw)
     dt, tot = run_steps(T, wl, a.packets, a.steps, 0, **kw)
@@ -126,14 +129,16 @@ def main():
         "config": {"workload": "expanding shell r in [0.8, 1] on a %d^3 grid, N_HI 1e19, v_exp 200 km/s, "
                                "tau_d 0.5 (albedo 0.3), Gaussian source 20 km/s, dipole, +z peel cube "
                                "%dx%dx256" % (a.grid, a.grid, a.grid),
-                   "packets_per_step": a.packets, "precision": a.precision, "path": a.path},
+                   "packets_per_step": a.packets, "precision": a.precision, "path": a.path,
+                   "waves_per_cu": a.waves_per_cu, "block": a.block, "visits_per_turn": a.turn_visits},
         "packets_per_s": tot["emitted"] / dt,
         "scatterings_per_packet": scat / max(tot["emitted"], 1),
         "cell_visits_per_s": visits / dt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_persistent<float,true>" if a.path == "persistent" else "k_plain",
-                     "kernel_ms_per_step": tot["kernel_ms"] / a.steps,
+                     "kernel_ms_per_step": tot["kernel_ms"] / a.steps, "upar_trials_per_scattering":
+                         tot["upar_trials"] / max(tot["n_res"], 1),
                      "bytes_per_visit": BYTES_PER_VISIT, "visits_per_step": visits / a.steps},
     }
     if a.plain_steps:

@@ -145,7 +145,9 @@ typedef enum { THOR_OBS_PX = 0, THOR_OBS_PY = 1, THOR_OBS_PZ = 2,
  *   step_events: PERSISTENT only: 0 = run to completion; else each call
  *              advances every resident packet by at most this many
  *              interactions and returns THOR_INCOMPLETE while work is left.
- *   waves_per_cu, block: PERSISTENT launch shape (0 = automatic). */
+ *   waves_per_cu, block: PERSISTENT launch shape (0 = automatic);
+ *              visits_per_turn: march segments a lane advances its packet
+ *              before the wave refills finished lanes (0 = 256). */
 typedef struct {
     int32_t precision;
     int32_t path;
@@ -164,6 +166,7 @@ typedef struct {
     uint64_t step_events;
     int32_t waves_per_cu;
     int32_t block;
+    int32_t visits_per_turn;    /* PERSISTENT: march segments per lane turn (0 = 256) */
     int32_t records;            /* 1: keep per-packet records of this call */
 } thor_transport_opts;
 

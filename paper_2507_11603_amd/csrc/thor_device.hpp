@@ -505,11 +505,14 @@ struct OutDev {
     uint64_t q_rec0;
 };
 
-// Per-lane counters, reduced per wave at the end of a launch.
+// Per-lane counters, reduced per wave at the end of a launch.  Event counts
+// are 32-bit per lane (a lane handles far fewer than 2^32 events in one
+// launch); visit and trial counts are 64-bit.  Packet weights are always 1,
+// so escaped / absorbed weights equal the counts.
 struct Counters {
-    uint64_t emitted, escaped, absorbed, capped, handed_off, n_res, n_dust;
-    uint64_t main_visits, peel_visits, peel_contrib, peel_dropped, peel_cut, upar_trials;
-    double w_escaped, w_absorbed;
+    uint32_t emitted, escaped, absorbed, capped, handed_off, n_res, n_dust;
+    uint32_t peel_contrib, peel_dropped, peel_cut;
+    uint64_t main_visits, peel_visits, upar_trials;
 };
 constexpr int kNumU64Counters = 13;
 

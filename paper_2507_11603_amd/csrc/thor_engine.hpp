@@ -3,6 +3,13 @@
 // (dust or resonant scattering), peeling off, escape binning.  Shared by the
 // plain and the persistent kernels.  GRID selects the uniform-grid medium at
 // compile time; otherwise the meshless sphere/shell/slab.
+//
+// The FP64 instantiation evaluates the march, interaction and peel formulas
+// in the same order as the CPU reference, so same-seed runs follow the same
+// histories.  The FP32 (mixed) instantiation keeps positions, distances and
+// optical depths in FP64 but derives cell quantities, directions, frequency
+// redistribution and the Voigt function in FP32 and marches with the
+// reciprocal direction.
 #pragma once
 #include "thor_device.hpp"
 
@@ -33,35 +40,64 @@ template <class R> __device__ __forceinline__ R dot3(const R a[3], const R b[3])
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// sin and cos of 2 pi u
+template <class R> __device__ __forceinline__ R sincos2pi(R u, R* c);
+template <> __device__ __forceinline__ double sincos2pi<double>(double u, double* c) {
+    double s;
+    ::sincos(2.0 * kPi * u, &s, c);
+    return s;
+}
+template <> __device__ __forceinline__ float sincos2pi<float>(float u, float* c) {
+    // v_sin_f32 / v_cos_f32 take their argument in revolutions
+    *c = __builtin_amdgcn_cosf(u);
+    return __builtin_amdgcn_sinf(u);
+}
+
 // ----------------------------------------------------------------- grid
 template <class R>
-__device__ __forceinline__ void grid_fields(const GridDev& g, const int c[3], const ModelDev& m, Fields<R>& f) {
+__device__ __forceinline__ void grid_fields(const GridDev& g, const int c[3], Fields<R>& f) {
     const uint64_t idx = (uint64_t(c[2]) * uint64_t(g.ny) + uint64_t(c[1])) * uint64_t(g.nx) + uint64_t(c[0]);
     const float4 r = g.vn[idx];
     f.v[0] = R(r.x); f.v[1] = R(r.y); f.v[2] = R(r.z);
-    const double n = double(r.w);
-    if (n > 0.0) {
-        const double T = double(g.T[idx]);
-        const double vth = sqrt(kVth2PerT * T);
-        f.vth = R(vth);
-        f.a = R(kDampTimesVth / vth);
-        f.k0 = n * (kSigma0TimesVth / vth);
-        f.kd = g.sigma_d * n;
+    if constexpr (sizeof(R) == 8) {
+        const double n = double(r.w);
+        if (n > 0.0) {
+            const double T = double(g.T[idx]);
+            const double vth = sqrt(kVth2PerT * T);
+            f.vth = vth;
+            f.a = kDampTimesVth / vth;
+            f.k0 = n * (kSigma0TimesVth / vth);
+            f.kd = g.sigma_d * n;
+        } else {
+            f.vth = 1.0; f.a = 0.0; f.k0 = 0.0; f.kd = 0.0;
+        }
     } else {
-        f.vth = R(1); f.a = R(0); f.k0 = 0.0; f.kd = 0.0;
+        const float n = r.w;
+        if (n > 0.0f) {
+            const float vth = sqrtf(float(kVth2PerT) * g.T[idx]);
+            const float inv = __builtin_amdgcn_rcpf(vth);
+            f.vth = vth;
+            f.a = float(kDampTimesVth) * inv;
+            f.k0 = double(n * (float(kSigma0TimesVth) * inv));
+            f.kd = g.sigma_d * double(n);
+        } else {
+            f.vth = 1.0f; f.a = 0.0f; f.k0 = 0.0; f.kd = 0.0;
+        }
     }
 }
 
-// distance to the next cell face; *mask = axes whose face is hit first
+// distance to the next cell face; *mask = axes whose face is hit first.
+// FP64: (face - p) / k as in the reference; FP32 path: (face - p) * (1/k).
 template <class R>
-__device__ __forceinline__ double grid_step(const GridDev& g, const double p[3], const int c[3], const R k[3], int* mask) {
+__device__ __forceinline__ double grid_step(const GridDev& g, const double p[3], const int c[3], const R k[3],
+                                            const double ik[3], int* mask) {
     double tm[3];
     double tmin = __builtin_inf();
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         const double kk = double(k[ax]);
-        if (kk > 0.0) tm[ax] = (g.lo[ax] + double(c[ax] + 1) * g.dx[ax] - p[ax]) / kk;
-        else if (kk < 0.0) tm[ax] = (g.lo[ax] + double(c[ax]) * g.dx[ax] - p[ax]) / kk;
+        const double face = kk > 0.0 ? g.lo[ax] + double(c[ax] + 1) * g.dx[ax] : g.lo[ax] + double(c[ax]) * g.dx[ax];
+        if (kk != 0.0) tm[ax] = sizeof(R) == 8 ? (face - p[ax]) / kk : (face - p[ax]) * ik[ax];
         else tm[ax] = __builtin_inf();
         tmin = tm[ax] < tmin ? tm[ax] : tmin;
     }
@@ -188,36 +224,26 @@ __device__ __forceinline__ int meshless_locate(const ModelDev& m, const double p
     return r < m.r_in ? kRegCavity : (r < m.r_out ? kRegGas : kRegOut);
 }
 
-// ----------------------------------------------------------------- unified query
-// Location of a ray: position, cell (grid) or region (meshless).
+// ----------------------------------------------------------------- ray location
 struct Loc {
     double p[3];
     int c[3];
     int region;
 };
 
-template <class R, bool GRID>
-__device__ __forceinline__ double query(const GridDev& g, const ModelDev& m, const Loc& L, const R k[3],
-                                        Fields<R>& f, int* next, int* cross) {
-    if constexpr (GRID) {
-        const double t = grid_step<R>(g, L.p, L.c, k, cross);
-        grid_fields<R>(g, L.c, m, f);
-        *next = kRegGas;
-        return t;
-    } else {
-        return meshless_query<R>(m, L.p, L.region, k, f, next, cross);
-    }
-}
+// Fields of the cell a grid ray is in, reused while it stays there.
+template <class R> struct CellCache {
+    int c[3];
+    bool valid;
+    Fields<R> f;
+};
 
-template <class R, bool GRID>
-__device__ __forceinline__ bool advance(const GridDev& g, Loc& L, const R k[3], double t, int next, int cross) {
-    if constexpr (GRID) {
-        return grid_advance<R>(g, L.p, L.c, k, t, cross);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) L.p[i] += t * double(k[i]);
-        if (cross) L.region = next;
-        return L.region == kRegOut;
+template <class R>
+__device__ __forceinline__ void cached_fields(const GridDev& g, const int c[3], CellCache<R>& cc) {
+    if (!(cc.valid && cc.c[0] == c[0] && cc.c[1] == c[1] && cc.c[2] == c[2])) {
+        grid_fields<R>(g, c, cc.f);
+        cc.c[0] = c[0]; cc.c[1] = c[1]; cc.c[2] = c[2];
+        cc.valid = true;
     }
 }
 
@@ -241,36 +267,69 @@ __device__ __forceinline__ int bin_of(double v, double lo, double w, int nb) {
 
 // Peel-off ray (Section 3.4.1): tau along the observer axis from the event,
 // at the fixed lab-frame frequency of the peeled photon; contribution
-// weight * exp(-tau) into the observer cube.
+// weight * exp(-tau) into the observer cube.  On a grid the ray is axis
+// aligned, so only one axis steps; `f0` holds the fields of the event's
+// cell (the first segment).
 template <class R, bool GRID>
-__device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const Loc& L0, int obs,
-                     double weight, R dv_peel, Counters& cnt) {
-    double kd[3];
-    obs_dir(o.obs_axis[obs], kd);
-    const R k[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+__device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const Loc& L0, const Fields<R>& f0,
+                     int obs, double weight, R dv_peel, Counters& cnt) {
+    const int axis = o.obs_axis[obs];
     cnt.peel_contrib++;
-    Loc L = L0;
     double tau = 0.0;
     bool cut = false;
-    for (;;) {
-        Fields<R> f;
-        int nr, cm;
-        const double t = query<R, GRID>(g, m, L, k, f, &nr, &cm);
-        cnt.peel_visits++;
-        if (f.k0 > 0.0 || f.kd > 0.0) {
-            const R x = (dv_peel - dot3<R>(f.v, k)) / f.vth;
-            const double kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
-            if (isinf(t)) { cut = true; break; }
-            tau += kt * t;
-        } else if (isinf(t)) {
-            break;
+    if constexpr (GRID) {
+        const int a = axis % 3;
+        const bool pos = axis < 3;
+        const int dims[3] = {g.nx, g.ny, g.nz};
+        int ca = L0.c[a];
+        double pa = L0.p[a];
+        int cell[3] = {L0.c[0], L0.c[1], L0.c[2]};
+        Fields<R> f = f0;
+        for (bool first = true;; first = false) {
+            if (!first) grid_fields<R>(g, cell, f);
+            const double face = pos ? g.lo[a] + double(ca + 1) * g.dx[a] : g.lo[a] + double(ca) * g.dx[a];
+            double t = pos ? face - pa : pa - face;
+            t = t < 0.0 ? 0.0 : t;
+            cnt.peel_visits++;
+            if (f.k0 > 0.0 || f.kd > 0.0) {
+                const R x = (dv_peel - (pos ? f.v[a] : -f.v[a])) / f.vth;
+                const double kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+                tau += kt * t;
+                if (tau > o.tau_cut) { cut = true; break; }
+            }
+            pa = face;
+            ca += pos ? 1 : -1;
+            if (ca < 0 || ca >= dims[a]) break;
+            cell[a] = ca;
         }
-        if (tau > o.tau_cut) { cut = true; break; }
-        if (advance<R, GRID>(g, L, k, t, nr, cm)) break;
+    } else {
+        double kd[3];
+        obs_dir(axis, kd);
+        const R k[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+        Loc L = L0;
+        for (;;) {
+            Fields<R> f;
+            int nr, cm;
+            const double t = meshless_query<R>(m, L.p, L.region, k, f, &nr, &cm);
+            cnt.peel_visits++;
+            if (f.k0 > 0.0 || f.kd > 0.0) {
+                const R x = (dv_peel - dot3<R>(f.v, k)) / f.vth;
+                const double kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+                if (isinf(t)) { cut = true; break; }
+                tau += kt * t;
+            } else if (isinf(t)) {
+                break;
+            }
+            if (tau > o.tau_cut) { cut = true; break; }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) L.p[i] += t * kd[i];
+            if (cm) L.region = nr;
+            if (L.region == kRegOut) break;
+        }
     }
     if (cut) { cnt.peel_cut++; return; }
     double u, v;
-    obs_image(o.obs_axis[obs], L0.p, &u, &v);
+    obs_image(axis, L0.p, &u, &v);
     const int ix = bin_of(u, o.img_lo[0], o.img_w[0], o.cube_nx);
     const int iy = bin_of(v, o.img_lo[1], o.img_w[1], o.cube_ny);
     const int ib = bin_of(double(dv_peel), o.v_lo, o.v_w, o.cube_nb);
@@ -291,7 +350,7 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
         const Uni2<R> d = draw<R>(key, kSlotEDir, 0);
         const R mu = R(2) * d.a - R(1);
         R cphi;
-        const R sphi = M<R>::sinpi2(d.b, &cphi);
+        const R sphi = sincos2pi<R>(d.b, &cphi);
         const R st = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
         pk.k[0] = st * cphi; pk.k[1] = st * sphi; pk.k[2] = mu;
     }
@@ -332,15 +391,17 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
     Fields<R> f0;
     if (L.region == kRegOut) {
         f0.vth = R(1); f0.a = R(0); f0.k0 = 0.0; f0.kd = 0.0; f0.v[0] = f0.v[1] = f0.v[2] = R(0);
+    } else if constexpr (GRID) {
+        grid_fields<R>(g, L.c, f0);
     } else {
         int nr, cm;
-        (void)query<R, GRID>(g, m, L, pk.k, f0, &nr, &cm);
+        (void)meshless_query<R>(m, L.p, L.region, pk.k, f0, &nr, &cm);
     }
     R z = R(0);
     if (m.spectrum != kSpecDelta) {
         const Uni2<R> d = draw<R>(key, kSlotEGauss, 0);
         R cs;
-        (void)M<R>::sinpi2(d.b, &cs);
+        (void)sincos2pi<R>(d.b, &cs);
         z = M<R>::sqrt(R(-2) * M<R>::log(R(1) - d.a)) * cs;
     }
     R dv_loc = R(0);
@@ -359,33 +420,140 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
             obs_dir(o.obs_axis[ob], kd);
             const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
             const R dvp = (m.spectrum == kSpecThermal) ? dv_loc + dot3<R>(f0.v, ko) : pk.dv;
-            peel<R, GRID>(g, m, o, L, ob, 1.0 / (4.0 * kPi), dvp, cnt);
+            peel<R, GRID>(g, m, o, L, f0, ob, 1.0 / (4.0 * kPi), dvp, cnt);
         }
     }
     const Uni2<double> dt = draw<double>(key, kSlotETau, 0);
-    pk.tau_t = -log(1.0 - dt.a);
+    pk.tau_t = sizeof(R) == 8 ? -log(1.0 - dt.a) : double(-__logf(float(1.0 - dt.a)));
     pk.tau_a = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) { pk.p[i] = L.p[i]; pk.c[i] = L.c[i]; }
     pk.region = L.region;
 }
 
-// ----------------------------------------------------------------- one event
-// March until the next interaction or the boundary, then interact.  Returns
-// the packet's fate (kFateNone while it lives on).
+// ----------------------------------------------------------------- interaction
+// Dust (Section 2.3.2) or resonant scattering (Sections 2.3.1, 3.4, 3.4.2)
+// at location L in a cell with fields f; kt is the total opacity there.
+// Returns kFateAbsorbed or kFateNone; peels off to every observer.
 template <class R, bool GRID>
-__device__ int advance_event(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt) {
+__device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk,
+                                        const Loc& L, const Fields<R>& f, double kt, const Key& key,
+                                        Counters& cnt) {
+    const Uni2<double> dtyp = draw<double>(key, kSlotType, pk.event);
+    R kout[3], e1[3], e2[3];
+    if (dtyp.a * kt < f.kd) {
+        if (dtyp.b >= m.albedo) return kFateAbsorbed;
+        const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
+        const R mu = sample_mu<R>(kPhaseHG, dm.a, R(m.g_hg));
+        const R dvl = pk.dv - dot3<R>(f.v, pk.k);
+        onb<R>(pk.k, e1, e2);
+        const R s_ = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
+        R cphi;
+        const R sphi = sincos2pi<R>(dm.b, &cphi);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
+        for (int ob = 0; ob < o.n_obs; ++ob) {
+            double kd[3];
+            obs_dir(o.obs_axis[ob], kd);
+            const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+            const double c = double(phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg))) / (2.0 * kPi);
+            peel<R, GRID>(g, m, o, L, f, ob, c, dvl + dot3<R>(f.v, ko), cnt);
+        }
+        pk.dv = dvl + dot3<R>(f.v, kout);
+        pk.n_dust++;
+        cnt.n_dust++;
+    } else {
+        const R x = (pk.dv - dot3<R>(f.v, pk.k)) / f.vth;
+        uint32_t trials = 0;
+        const R upar = upar_sample<R>(x, f.a, key, pk.event, &trials);
+        cnt.upar_trials += trials;
+        const Uni2<R> dp = draw<R>(key, kSlotUperp, pk.event);
+        R rho2 = -M<R>::log(R(1) - dp.a);
+        if (m.xcrit > 0.0 && fabs(x) < R(m.xcrit)) rho2 += R(m.xcrit * m.xcrit);
+        const R rho = M<R>::sqrt(rho2);
+        R cps;
+        const R sps = sincos2pi<R>(dp.b, &cps);
+        const R up1 = rho * cps, up2 = rho * sps;
+        onb<R>(pk.k, e1, e2);
+        R u[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) u[i] = upar * pk.k[i] + up1 * e1[i] + up2 * e2[i];
+        const R x_atom = x - upar;
+        int ph = o.phase;
+        if (ph == kPhaseCoreWing && fabs(x_atom) >= R(0.2)) ph = kPhaseDipole;
+        const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
+        const R mu = sample_mu<R>(ph, dm.a, R(0));
+        const R s_ = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
+        R cphi;
+        const R sphi = sincos2pi<R>(dm.b, &cphi);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
+        for (int ob = 0; ob < o.n_obs; ++ob) {
+            double kd[3];
+            obs_dir(o.obs_axis[ob], kd);
+            const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+            const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
+            const R xo = x_atom + dot3<R>(u, ko);
+            peel<R, GRID>(g, m, o, L, f, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt);
+        }
+        const R x_out = x_atom + dot3<R>(u, kout);
+        pk.dv = x_out * f.vth + dot3<R>(f.v, kout);
+        pk.n_res++;
+        cnt.n_res++;
+    }
+    if constexpr (sizeof(R) == 4) {   // FP32 directions drift: renormalise
+        const R inv = rsqrtf(dot3<R>(kout, kout));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) kout[i] *= inv;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pk.k[i] = kout[i];
+    const Uni2<double> dtau = draw<double>(key, kSlotTau, pk.event);
+    pk.tau_t = sizeof(R) == 8 ? -log(1.0 - dtau.a) : double(-__logf(float(1.0 - dtau.a)));
+    pk.tau_a = 0.0;
+    return kFateNone;
+}
+
+// ----------------------------------------------------------------- march
+// Advance a packet by at most `max_visits` march segments and `max_events`
+// interactions (propagation, Section 3.4: piecewise-linear tau integration
+// until tau_current = tau_target, then the interaction).  Returns the fate
+// (kFateNone while it lives on); the packet state is complete on return, so
+// a later call resumes it exactly.
+template <class R, bool GRID>
+__device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt,
+                       uint32_t max_visits, uint32_t max_events, uint32_t* events_done) {
     const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
     Loc L;
 #pragma unroll
     for (int i = 0; i < 3; ++i) { L.p[i] = pk.p[i]; L.c[i] = pk.c[i]; }
     L.region = pk.region;
     if (L.region == kRegOut) return kFateEscaped;
+    CellCache<R> cc;
+    cc.valid = false;
+    double ik[3];
+    auto set_inverse = [&]() {
+        if constexpr (sizeof(R) == 4) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ik[i] = pk.k[i] != R(0) ? 1.0 / double(pk.k[i]) : 0.0;
+        }
+    };
+    set_inverse();
+    const uint64_t emax = o.max_events ? o.max_events : 100000000ull;
     int fate = kFateNone;
-    for (;;) {
-        Fields<R> f;
+    uint32_t ev = 0;
+    for (uint32_t vis = 0; vis < max_visits && ev < max_events; ++vis) {
         int nr, cm;
-        const double t = query<R, GRID>(g, m, L, pk.k, f, &nr, &cm);
+        double t;
+        Fields<R> fl;
+        if constexpr (GRID) {
+            t = grid_step<R>(g, L.p, L.c, pk.k, ik, &cm);
+            cached_fields<R>(g, L.c, cc);
+            nr = kRegGas;
+        } else {
+            t = meshless_query<R>(m, L.p, L.region, pk.k, fl, &nr, &cm);
+        }
+        const Fields<R>& f = GRID ? cc.f : fl;
         cnt.main_visits++;
         double kt = 0.0;
         if (f.k0 > 0.0 || f.kd > 0.0) {
@@ -398,91 +566,30 @@ __device__ int advance_event(const GridDev& g, const ModelDev& m, const OutDev& 
 #pragma unroll
             for (int i = 0; i < 3; ++i) L.p[i] += s * double(pk.k[i]);
             pk.event++;
-            const uint64_t emax = o.max_events ? o.max_events : 100000000ull;
+            ++ev;
             if (uint64_t(pk.event) > emax) { fate = kFateCapped; break; }
-            const Uni2<double> dtyp = draw<double>(key, kSlotType, pk.event);
-            R kout[3], e1[3], e2[3];
-            if (dtyp.a * kt < f.kd) {
-                // dust: absorption or Henyey-Greenstein scattering (Section 2.3.2)
-                if (dtyp.b >= m.albedo) { fate = kFateAbsorbed; break; }
-                const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
-                const R mu = sample_mu<R>(kPhaseHG, dm.a, R(m.g_hg));
-                const R dvl = pk.dv - dot3<R>(f.v, pk.k);
-                onb<R>(pk.k, e1, e2);
-                const R s_ = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
-                R cphi;
-                const R sphi = M<R>::sinpi2(dm.b, &cphi);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
-                for (int ob = 0; ob < o.n_obs; ++ob) {
-                    double kd[3];
-                    obs_dir(o.obs_axis[ob], kd);
-                    const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
-                    const double c = double(phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg))) / (2.0 * kPi);
-                    peel<R, GRID>(g, m, o, L, ob, c, dvl + dot3<R>(f.v, ko), cnt);
-                }
-                pk.dv = dvl + dot3<R>(f.v, kout);
-                pk.n_dust++;
-                cnt.n_dust++;
-            } else {
-                // resonant scattering (Sections 2.3.1, 3.4, 3.4.2)
-                const R x = (pk.dv - dot3<R>(f.v, pk.k)) / f.vth;
-                uint32_t trials = 0;
-                const R upar = upar_sample<R>(x, f.a, key, pk.event, &trials);
-                cnt.upar_trials += trials;
-                const Uni2<R> dp = draw<R>(key, kSlotUperp, pk.event);
-                R rho2 = -M<R>::log(R(1) - dp.a);
-                if (m.xcrit > 0.0 && fabs(x) < R(m.xcrit)) rho2 += R(m.xcrit * m.xcrit);
-                const R rho = M<R>::sqrt(rho2);
-                R cps;
-                const R sps = M<R>::sinpi2(dp.b, &cps);
-                const R up1 = rho * cps, up2 = rho * sps;
-                onb<R>(pk.k, e1, e2);
-                R u[3];
-#pragma unroll
-                for (int i = 0; i < 3; ++i) u[i] = upar * pk.k[i] + up1 * e1[i] + up2 * e2[i];
-                const R x_atom = x - upar;
-                int ph = o.phase;
-                if (ph == kPhaseCoreWing && fabs(x_atom) >= R(0.2)) ph = kPhaseDipole;
-                const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
-                const R mu = sample_mu<R>(ph, dm.a, R(0));
-                const R s_ = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
-                R cphi;
-                const R sphi = M<R>::sinpi2(dm.b, &cphi);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
-                for (int ob = 0; ob < o.n_obs; ++ob) {
-                    double kd[3];
-                    obs_dir(o.obs_axis[ob], kd);
-                    const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
-                    const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
-                    const R xo = x_atom + dot3<R>(u, ko);
-                    peel<R, GRID>(g, m, o, L, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt);
-                }
-                const R x_out = x_atom + dot3<R>(u, kout);
-                pk.dv = x_out * f.vth + dot3<R>(f.v, kout);
-                pk.n_res++;
-                cnt.n_res++;
-            }
-            if constexpr (sizeof(R) == 4) {   // FP32 directions drift: renormalise
-                const R inv = R(1) / M<R>::sqrt(dot3<R>(kout, kout));
-#pragma unroll
-                for (int i = 0; i < 3; ++i) kout[i] *= inv;
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i) pk.k[i] = kout[i];
-            const Uni2<double> dtau = draw<double>(key, kSlotTau, pk.event);
-            pk.tau_t = -log(1.0 - dtau.a);
-            pk.tau_a = 0.0;
-            break;
+            fate = interact<R, GRID>(g, m, o, pk, L, f, kt, key, cnt);
+            if (fate != kFateNone) break;
+            set_inverse();
+            continue;
         }
         if (isinf(t)) { fate = kFateEscaped; break; }
         pk.tau_a += kt * t;
-        if (advance<R, GRID>(g, L, pk.k, t, nr, cm)) { fate = kFateEscaped; break; }
+        bool out;
+        if constexpr (GRID) {
+            out = grid_advance<R>(g, L.p, L.c, pk.k, t, cm);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) L.p[i] += t * double(pk.k[i]);
+            if (cm) L.region = nr;
+            out = L.region == kRegOut;
+        }
+        if (out) { fate = kFateEscaped; break; }
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) { pk.p[i] = L.p[i]; pk.c[i] = L.c[i]; }
     pk.region = L.region;
+    *events_done += ev;
     return fate;
 }
 
@@ -492,13 +599,11 @@ __device__ void finish(const GridDev& g, const ModelDev& m, const OutDev& o, con
                        Counters& cnt) {
     if (fate == kFateEscaped) {
         cnt.escaped++;
-        cnt.w_escaped += 1.0;
         if (GRID && g.handoff) cnt.handed_off++;
         const int b = bin_of(double(pk.dv) * m.spec_scale, m.spec_lo, m.spec_w, m.spec_nb);
         if (b >= 0) unsafeAtomicAdd(m.spec + b, 1.0);
     } else if (fate == kFateAbsorbed) {
         cnt.absorbed++;
-        cnt.w_absorbed += 1.0;
     } else if (fate == kFateCapped) {
         cnt.capped++;
     }
@@ -518,13 +623,8 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
-__device__ __forceinline__ void flush_counters(const Counters& c, unsigned long long* g, double* gw) {
+__device__ __forceinline__ void flush_counters(const Counters& c, unsigned long long* g) {
     const uint64_t vals[kNumU64Counters] = {c.emitted, c.escaped, c.absorbed, c.capped, c.handed_off,
                                             c.n_res, c.n_dust, c.main_visits, c.peel_visits,
                                             c.peel_contrib, c.peel_dropped, c.peel_cut, c.upar_trials};
@@ -533,11 +633,6 @@ __device__ __forceinline__ void flush_counters(const Counters& c, unsigned long 
     for (int i = 0; i < kNumU64Counters; ++i) {
         const uint64_t s = wave_sum_u64(vals[i]);
         if (lane == 0 && s) atomicAdd(g + i, (unsigned long long)s);
-    }
-    const double w0 = wave_sum_f64(c.w_escaped), w1 = wave_sum_f64(c.w_absorbed);
-    if (lane == 0) {
-        if (w0 != 0.0) unsafeAtomicAdd(gw + 0, w0);
-        if (w1 != 0.0) unsafeAtomicAdd(gw + 1, w1);
     }
 }
 

@@ -27,18 +27,19 @@ __constant__ float c_dawson32[kDawsonIntervals * (kDawsonDeg32 + 1)];
 // Plain path: one thread per packet, the whole history in one launch.
 template <class R, bool GRID>
 __global__ __launch_bounds__(256) void k_plain(GridDev g, const ModelDev* __restrict__ models, BatchDev b, OutDev o,
-                                               unsigned long long* gstats, double* gw) {
+                                               unsigned long long* gstats) {
     const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     Counters cnt = {};
     if (i < b.n) {
         const ModelDev& m = models[b.model];
         Pkt<R> pk;
         emit<R, GRID>(g, m, o, b.first_id + i, b.q0 + i, b.model, pk, cnt);
+        uint32_t ev = 0;
         int fate = pk.region == kRegOut ? kFateEscaped : kFateNone;
-        while (fate == kFateNone) fate = advance_event<R, GRID>(g, m, o, pk, cnt);
+        while (fate == kFateNone) fate = advance<R, GRID>(g, m, o, pk, cnt, ~0u, ~0u, &ev);
         finish<R, GRID>(g, m, o, pk, fate, cnt);
     }
-    flush_counters(cnt, gstats, gw);
+    flush_counters(cnt, gstats);
 }
 
 // Pool of packets parked between bounded persistent steps (one slot per lane).
@@ -58,14 +59,17 @@ __device__ __forceinline__ int find_batch(const BatchDev* b, int nb, uint64_t q)
 
 // Persistent path: resident waves; each lane keeps one packet in registers
 // and refills from the global queue (one atomic per wave, ballot + mbcnt
-// prefix for the lane offsets) when its packet finishes.  A bounded step
-// (step_events > 0) parks live packets in the pool for the next launch.
+// prefix for the lane offsets) when its packet finishes.  Each turn a lane
+// advances its packet by at most `turn_visits` march segments, so lanes with
+// short flights (packets trapped near line centre) make progress at the
+// pace of their neighbours' long flights.  A bounded step (step_events > 0)
+// parks live packets in the pool for the next launch.
 template <class R, bool GRID>
 __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* __restrict__ models,
                                                     const BatchDev* __restrict__ batches, int nbatch,
                                                     uint64_t q_end, unsigned long long* cursor, OutDev o,
-                                                    PoolDev<R> pool, uint64_t step_events,
-                                                    unsigned long long* gstats, double* gw) {
+                                                    PoolDev<R> pool, uint32_t step_events, uint32_t turn_visits,
+                                                    unsigned long long* gstats) {
     const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     Counters cnt = {};
     Pkt<R> pk;
@@ -75,8 +79,8 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
         active = true;
     }
     bool exhausted = false;
-    const uint64_t budget = step_events ? step_events : ~0ull;
-    uint64_t used = 0;
+    const uint32_t budget = step_events ? step_events : ~0u;
+    uint32_t used = 0;
     for (;;) {
         const bool need = !active && !exhausted && used < budget;
         const uint64_t mask = __ballot(need);
@@ -108,8 +112,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
         if (__ballot(work) == 0) break;
         if (work) {
             const ModelDev& m = models[pk.model];
-            const int fate = advance_event<R, GRID>(g, m, o, pk, cnt);
-            ++used;
+            const int fate = advance<R, GRID>(g, m, o, pk, cnt, turn_visits, budget - used, &used);
             if (fate != kFateNone) {
                 finish<R, GRID>(g, m, o, pk, fate, cnt);
                 active = false;
@@ -120,7 +123,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
         pool.alive[gid] = active ? 1 : 0;
         if (active) pool.pk[gid] = pk;
     }
-    flush_counters(cnt, gstats, gw);
+    flush_counters(cnt, gstats);
 }
 
 // Re-layout of the grid fields into (vx, vy, vz, n_HI) records; counts cells
@@ -261,7 +264,6 @@ struct thor_ctx {
     uint64_t cube_elems = 0;
     int cube_shape[4] = {0, 0, 0, 0};
     unsigned long long* d_stats = nullptr;   // kNumU64Counters counters, then cursor
-    double* d_wstats = nullptr;
     ModelDev* d_models = nullptr;
     size_t models_cap = 0;
     BatchDev* d_batches = nullptr;
@@ -487,20 +489,21 @@ template <class R, bool GRID>
 void launch_plain(thor_ctx* ctx, const BatchDev& b, const OutDev& out) {
     const unsigned blocks = unsigned((b.n + 255) / 256);
     hipLaunchKernelGGL((k_plain<R, GRID>), dim3(blocks), dim3(256), 0, ctx->stream, ctx->grid, ctx->d_models, b,
-                       out, ctx->d_stats, ctx->d_wstats);
+                       out, ctx->d_stats);
 }
 
 template <class R, bool GRID>
 void launch_persistent(thor_ctx* ctx, int grid, int block, const BatchDev* d_b, int nb, uint64_t q_end,
-                       const OutDev& out, const ModelDev* d_models, uint64_t step_events, bool use_pool) {
+                       const OutDev& out, const ModelDev* d_models, uint32_t step_events, uint32_t turn_visits,
+                       bool use_pool) {
     PoolDev<R> pool{nullptr, nullptr};
     if (use_pool) {
         pool.pk = reinterpret_cast<Pkt<R>*>(ctx->d_pool_pk);
         pool.alive = ctx->d_pool_alive;
     }
     hipLaunchKernelGGL((k_persistent<R, GRID>), dim3(grid), dim3(block), 0, ctx->stream, ctx->grid, d_models,
-                       d_b, nb, q_end, ctx->d_stats + kNumU64Counters, out, pool, step_events, ctx->d_stats,
-                       ctx->d_wstats);
+                       d_b, nb, q_end, ctx->d_stats + kNumU64Counters, out, pool, step_events, turn_visits,
+                       ctx->d_stats);
 }
 
 thor_status ensure_pool(thor_ctx* ctx, uint64_t slots, int prec) {
@@ -522,14 +525,14 @@ thor_status ensure_pool(thor_ctx* ctx, uint64_t slots, int prec) {
     return THOR_OK;
 }
 
-void collect_stats(thor_ctx* ctx, const unsigned long long* h, const double* w, float ms, thor_stats* st) {
+void collect_stats(thor_ctx* ctx, const unsigned long long* h, float ms, thor_stats* st) {
     std::memset(st, 0, sizeof *st);
     uint64_t* dst[kNumU64Counters] = {&st->emitted, &st->escaped, &st->absorbed, &st->capped, &st->handed_off,
                                       &st->n_res, &st->n_dust, &st->main_visits, &st->peel_visits,
                                       &st->peel_contrib, &st->peel_dropped, &st->peel_cut, &st->upar_trials};
     for (int i = 0; i < kNumU64Counters; ++i) *dst[i] = h[i];
-    st->w_escaped = w[0];
-    st->w_absorbed = w[1];
+    st->w_escaped = double(st->escaped);     // packet weights are 1
+    st->w_absorbed = double(st->absorbed);
     st->kernel_ms = ms;
 }
 
@@ -565,7 +568,6 @@ thor_status thor_create(thor_ctx** out, int hip_device, void* hip_stream, uint64
         hipMemcpyToSymbol(HIP_SYMBOL(c_dawson32), t32, sizeof t32) != hipSuccess)
         s = fail(THOR_E_DEVICE, "Dawson table upload failed");
     if (!s) s = dalloc(ctx, (void**)&ctx->d_stats, (kNumU64Counters + 1) * 8, "counters");
-    if (!s) s = dalloc(ctx, (void**)&ctx->d_wstats, 2 * 8, "weights");
     if (!s && (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess))
         s = fail(THOR_E_DEVICE, "hipEventCreate failed");
     if (s) {
@@ -580,7 +582,7 @@ void thor_destroy(thor_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    void* ptrs[] = {ctx->d_vn, ctx->d_T, ctx->d_cdf, ctx->d_spec, ctx->d_cube, ctx->d_stats, ctx->d_wstats,
+    void* ptrs[] = {ctx->d_vn, ctx->d_T, ctx->d_cdf, ctx->d_spec, ctx->d_cube, ctx->d_stats,
                     ctx->d_models, ctx->d_batches, ctx->d_rec_dv, ctx->d_rec_nres, ctx->d_rec_ndust,
                     ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done};
     for (void* p : ptrs)
@@ -802,7 +804,6 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
     }
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_models, models.data(), nb * sizeof(ModelDev), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(ctx->d_batches, batches.data(), nb * sizeof(BatchDev), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemsetAsync(ctx->d_wstats, 0, 16, ctx->stream));
     if (!resuming) {
         HIPCHK(ctx, hipMemsetAsync(ctx->d_stats, 0, (kNumU64Counters + 1) * 8, ctx->stream));
     } else {
@@ -817,26 +818,26 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
     } else {
         const int block = opt->block > 0 ? opt->block : 256;
         const int gsize = launch_grid_size(ctx, opt, block);
+        const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
+        if (opt->step_events > 0xFFFFFFFFull) return fail(THOR_E_INVAL, "step_events must fit 32 bits");
         if (bounded) {
             s = ensure_pool(ctx, uint64_t(gsize) * block, opt->precision);
             if (s) return s;
         }
-        if (fp64) grid ? launch_persistent<double, true>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, opt->step_events, bounded)
-                       : launch_persistent<double, false>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, opt->step_events, bounded);
-        else grid ? launch_persistent<float, true>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, opt->step_events, bounded)
-                  : launch_persistent<float, false>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, opt->step_events, bounded);
+        if (fp64) grid ? launch_persistent<double, true>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, uint32_t(opt->step_events), turn, bounded)
+                       : launch_persistent<double, false>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, uint32_t(opt->step_events), turn, bounded);
+        else grid ? launch_persistent<float, true>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, uint32_t(opt->step_events), turn, bounded)
+                  : launch_persistent<float, false>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, uint32_t(opt->step_events), turn, bounded);
         hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, ctx->stream, ctx->d_stats + kNumU64Counters, q_end);
     }
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     unsigned long long h[kNumU64Counters + 1];
-    double w[2];
     HIPCHK(ctx, hipMemcpyAsync(h, ctx->d_stats, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(w, ctx->d_wstats, sizeof w, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     float ms = 0.0f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-    collect_stats(ctx, h, w, ms, &ctx->last);
+    collect_stats(ctx, h, ms, &ctx->last);
     if (out_stats) *out_stats = ctx->last;
     if (bounded) {
         // work left: queue not drained or packets parked in the pool
