@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--turn-visits", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=400000, help="packets of the oracle sample")
+    ap.add_argument("--autotune", type=int, default=1, help="pick launch knobs with the autotuner")
+    ap.add_argument("--serving", type=int, default=300, help="requests of the serving stream (0: skip)")
+    ap.add_argument("--serving-warmup", type=int, default=60)
+    ap.add_argument("--serving-rate", type=float, default=200.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (PMC calibration)")
     return ap.parse_args()
@@ -76,6 +80,27 @@ def cpu_baseline(wl, n):
                 packets_per_s=n / dt)
 
 
+def serving(a, kw):
+    """Open-loop stream of shell-model requests through the continuous-batching
+    server: p50/p99 latency (completion - arrival) and sustained throughput."""
+    import workloads as W
+    from paper_2507_11603_amd import serve
+    stream = W.request_stream(a.serving + a.serving_warmup, rate_hz=a.serving_rate)
+    srv = serve.ShellServer(precision=a.precision, step_events=64,
+                            waves_per_cu=kw.get("waves_per_cu", 0), visits_per_turn=kw.get("visits_per_turn", 0))
+    try:
+        r = srv.run_stream(stream, warmup=a.serving_warmup)
+    finally:
+        srv.close()
+    pk = sum(q["n_packets"] for q in stream)
+    span = stream[-1]["t_arrival"] - stream[0]["t_arrival"]
+    return {"requests": a.serving, "warmup_requests": a.serving_warmup, "rate_hz": a.serving_rate,
+            "p50_ms": r["p50_s"] * 1e3, "p99_ms": r["p99_s"] * 1e3,
+            "offered_packets_per_s": pk / span, "sustained_packets_per_s": pk / r["wall_s"],
+            "sustained_scatterings_per_s": r["scatterings"] / r["wall_s"], "wall_s": r["wall_s"],
+            "steps": r["steps"], "budget_deferrals": r["deferrals"], "graph_steps": True}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -105,6 +130,12 @@ def main():
     T.load(wl["geom"])
     kw = dict(precision=a.precision, path=a.path, waves_per_cu=a.waves_per_cu, block=a.block,
               visits_per_turn=a.turn_visits)
+    tuned = None
+    if a.autotune and a.path == "persistent" and not (a.waves_per_cu or a.block or a.turn_visits):
+        from paper_2507_11603_amd import autotune
+        tuned, _ = autotune.tune(T, wl, "shell%d" % a.grid, a.precision,
+                                 log=lambda m: print(m, file=sys.stderr, flush=True))
+        kw.update(tuned)
     if a.warmup:
         run_steps(T, wl, a.packets, a.warmup, 10**12, **kw)
     dt, tot = run_steps(T, wl, a.packets, a.steps, 0, **kw)
@@ -130,7 +161,8 @@ def main():
                                "tau_d 0.5 (albedo 0.3), Gaussian source 20 km/s, dipole, +z peel cube "
                                "%dx%dx256" % (a.grid, a.grid, a.grid),
                    "packets_per_step": a.packets, "precision": a.precision, "path": a.path,
-                   "waves_per_cu": a.waves_per_cu, "block": a.block, "visits_per_turn": a.turn_visits},
+                   "waves_per_cu": kw["waves_per_cu"], "block": kw["block"],
+                   "visits_per_turn": kw["visits_per_turn"], "autotuned": tuned is not None},
         "packets_per_s": tot["emitted"] / dt,
         "scatterings_per_packet": scat / max(tot["emitted"], 1),
         "cell_visits_per_s": visits / dt,
@@ -148,6 +180,8 @@ def main():
                              "packets_per_s": ptot["emitted"] / pdt}
         out["speedup_vs_plain_fp64"] = value / pval
     T.close()
+    if a.serving:
+        out["serving"] = serving(a, kw)
     if cpu:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

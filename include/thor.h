@@ -167,6 +167,7 @@ typedef struct {
     int32_t waves_per_cu;
     int32_t block;
     int32_t visits_per_turn;    /* PERSISTENT: march segments per lane turn (0 = 256) */
+    int32_t use_graph;          /* thor_step: replay one captured hipGraph per step */
     int32_t records;            /* 1: keep per-packet records of this call */
 } thor_transport_opts;
 

@@ -488,6 +488,16 @@ struct BatchDev {
     int pad;
 };
 
+// Scalars of one persistent launch, read from device memory so that a
+// captured graph can be replayed with new values.
+struct StepDesc {
+    uint64_t q_end;        // queue indices [0, q_end) exist
+    int nbatch;
+    uint32_t step_events;  // 0 = run to completion
+    uint32_t turn_visits;
+    uint32_t pad;
+};
+
 struct OutDev {
     int phase;
     int n_obs;

@@ -66,11 +66,15 @@ __device__ __forceinline__ int find_batch(const BatchDev* b, int nb, uint64_t q)
 // parks live packets in the pool for the next launch.
 template <class R, bool GRID>
 __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* __restrict__ models,
-                                                    const BatchDev* __restrict__ batches, int nbatch,
-                                                    uint64_t q_end, unsigned long long* cursor, OutDev o,
-                                                    PoolDev<R> pool, uint32_t step_events, uint32_t turn_visits,
+                                                    const BatchDev* __restrict__ batches,
+                                                    const StepDesc* __restrict__ desc,
+                                                    unsigned long long* cursor, OutDev o, PoolDev<R> pool,
                                                     unsigned long long* gstats) {
     const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t q_end = desc->q_end;
+    const int nbatch = desc->nbatch;
+    const uint32_t step_events = desc->step_events;
+    const uint32_t turn_visits = desc->turn_visits;
     Counters cnt = {};
     Pkt<R> pk;
     bool active = false;
@@ -166,8 +170,12 @@ __global__ void k_sample_upar(double x, double a, uint32_t seed, uint32_t event,
     }
 }
 
-__global__ void k_clamp_cursor(unsigned long long* cursor, uint64_t q_end) {
-    if (threadIdx.x == 0 && *cursor > q_end) *cursor = q_end;
+__global__ void k_clamp_cursor(unsigned long long* cursor, const StepDesc* desc) {
+    if (threadIdx.x == 0 && *cursor > desc->q_end) *cursor = desc->q_end;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+    if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
 
 }  // namespace thor
@@ -227,14 +235,16 @@ struct BatchHost {
 };
 
 struct ServingReq {
-    uint64_t handle;
-    int model;             // index into serving models
+    int model;             // slot in the serving model table
     uint64_t n_packets;
     double* d_spec;
     int spec_nb;
-    uint64_t bytes;
+    uint64_t reserved;     // packet-state bytes reserved against the budget
     bool finished;
 };
+
+constexpr int kServingMaxModels = 1 << 16;
+constexpr int kServingMaxBatches = 1 << 14;
 
 }  // namespace
 
@@ -286,16 +296,37 @@ struct thor_ctx {
 
     thor_stats last{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    StepDesc* d_desc = nullptr;            // step descriptor of the transport path
+    StepDesc* h_desc = nullptr;            // pinned
+    StepDesc* d_s_desc = nullptr;          // step descriptor of the serving path
+    StepDesc* h_s_desc = nullptr;          // pinned
+    BatchDev* h_s_batches = nullptr;       // pinned mirror, kServingMaxBatches entries
+    unsigned long long* h_s_done = nullptr;    // pinned mirror of d_done
+    unsigned long long* h_s_misc = nullptr;    // pinned: counters then cursor
+    hipStream_t cap_stream = nullptr;      // private stream for graph capture
+    hipGraphExec_t s_graph = nullptr;
+    int s_graph_prec = -1, s_graph_grid = 0, s_graph_block = 0;
 
-    // serving
-    std::vector<ModelDev> s_models;
-    std::vector<BatchDev> s_batches;
+    // serving (continuous batching of shell-model requests)
+    bool s_init = false;
+    std::vector<ModelDev> s_models;        // host copy of the model table
+    std::vector<int> s_free;               // recycled model slots
+    int s_next_slot = 0;
+    std::vector<BatchDev> s_batches;       // queue ranges of live requests, by q0
     std::map<uint64_t, ServingReq> s_reqs;
-    unsigned long long* d_done = nullptr;
-    size_t done_cap = 0;
+    ModelDev* d_s_models = nullptr;
+    BatchDev* d_s_batches = nullptr;
+    size_t s_batches_cap = 0;
+    unsigned long long* d_done = nullptr;  // finished packets per model slot
+    unsigned long long* d_s_cursor = nullptr;
+    void* d_s_pool = nullptr;
+    int* d_s_alive = nullptr;
+    uint64_t s_pool_slots = 0, s_pool_bytes = 0;
+    int s_pool_prec = -1;
     uint64_t s_next_handle = 1;
-    uint64_t s_q_total = 0;
+    uint64_t s_q_total = 0, s_cursor = 0;
     uint64_t s_reserved = 0;
+    bool s_dirty = false;
 };
 
 namespace {
@@ -493,17 +524,12 @@ void launch_plain(thor_ctx* ctx, const BatchDev& b, const OutDev& out) {
 }
 
 template <class R, bool GRID>
-void launch_persistent(thor_ctx* ctx, int grid, int block, const BatchDev* d_b, int nb, uint64_t q_end,
-                       const OutDev& out, const ModelDev* d_models, uint32_t step_events, uint32_t turn_visits,
-                       bool use_pool) {
-    PoolDev<R> pool{nullptr, nullptr};
-    if (use_pool) {
-        pool.pk = reinterpret_cast<Pkt<R>*>(ctx->d_pool_pk);
-        pool.alive = ctx->d_pool_alive;
-    }
-    hipLaunchKernelGGL((k_persistent<R, GRID>), dim3(grid), dim3(block), 0, ctx->stream, ctx->grid, d_models,
-                       d_b, nb, q_end, ctx->d_stats + kNumU64Counters, out, pool, step_events, turn_visits,
-                       ctx->d_stats);
+void launch_persistent(thor_ctx* ctx, hipStream_t stream, int grid, int block, const BatchDev* d_b,
+                       const StepDesc* d_desc, unsigned long long* cursor, const OutDev& out,
+                       const ModelDev* d_models, void* pool_pk, int* pool_alive) {
+    PoolDev<R> pool{reinterpret_cast<Pkt<R>*>(pool_pk), pool_alive};
+    hipLaunchKernelGGL((k_persistent<R, GRID>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models, d_b,
+                       d_desc, cursor, out, pool, ctx->d_stats);
 }
 
 thor_status ensure_pool(thor_ctx* ctx, uint64_t slots, int prec) {
@@ -570,6 +596,9 @@ thor_status thor_create(thor_ctx** out, int hip_device, void* hip_stream, uint64
     if (!s) s = dalloc(ctx, (void**)&ctx->d_stats, (kNumU64Counters + 1) * 8, "counters");
     if (!s && (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess))
         s = fail(THOR_E_DEVICE, "hipEventCreate failed");
+    if (!s) s = dalloc(ctx, (void**)&ctx->d_desc, sizeof(StepDesc), "step descriptor");
+    if (!s && hipHostMalloc((void**)&ctx->h_desc, sizeof(StepDesc)) != hipSuccess)
+        s = fail(THOR_E_NOMEM, "pinned host allocation failed");
     if (s) {
         thor_destroy(ctx);
         return s;
@@ -584,11 +613,20 @@ void thor_destroy(thor_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     void* ptrs[] = {ctx->d_vn, ctx->d_T, ctx->d_cdf, ctx->d_spec, ctx->d_cube, ctx->d_stats,
                     ctx->d_models, ctx->d_batches, ctx->d_rec_dv, ctx->d_rec_nres, ctx->d_rec_ndust,
-                    ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done};
+                    ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done,
+                    ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& kv : ctx->s_reqs)
         if (kv.second.d_spec) (void)hipFree(kv.second.d_spec);
+    void* dev2[] = {ctx->d_desc, ctx->d_s_desc};
+    for (void* p : dev2)
+        if (p) (void)hipFree(p);
+    void* pinned[] = {ctx->h_desc, ctx->h_s_desc, ctx->h_s_batches, ctx->h_s_done, ctx->h_s_misc};
+    for (void* p : pinned)
+        if (p) (void)hipHostFree(p);
+    if (ctx->s_graph) (void)hipGraphExecDestroy(ctx->s_graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     delete ctx;
@@ -820,15 +858,20 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         const int gsize = launch_grid_size(ctx, opt, block);
         const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
         if (opt->step_events > 0xFFFFFFFFull) return fail(THOR_E_INVAL, "step_events must fit 32 bits");
+        *ctx->h_desc = StepDesc{q_end, int(nb), uint32_t(opt->step_events), turn, 0u};
+        HIPCHK(ctx, hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(StepDesc), hipMemcpyHostToDevice, ctx->stream));
         if (bounded) {
             s = ensure_pool(ctx, uint64_t(gsize) * block, opt->precision);
             if (s) return s;
         }
-        if (fp64) grid ? launch_persistent<double, true>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, uint32_t(opt->step_events), turn, bounded)
-                       : launch_persistent<double, false>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, uint32_t(opt->step_events), turn, bounded);
-        else grid ? launch_persistent<float, true>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, uint32_t(opt->step_events), turn, bounded)
-                  : launch_persistent<float, false>(ctx, gsize, block, ctx->d_batches, int(nb), q_end, out, ctx->d_models, uint32_t(opt->step_events), turn, bounded);
-        hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, ctx->stream, ctx->d_stats + kNumU64Counters, q_end);
+        void* ppk = bounded ? ctx->d_pool_pk : nullptr;
+        int* pal = bounded ? ctx->d_pool_alive : nullptr;
+        unsigned long long* cur = ctx->d_stats + kNumU64Counters;
+        if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal)
+                       : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal);
+        else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal)
+                  : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal);
+        hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, ctx->stream, cur, ctx->d_desc);
     }
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
@@ -946,22 +989,255 @@ thor_status thor_sample_upar(thor_ctx* ctx, double x, double a, uint32_t seed, u
 }
 
 // ------------------------------------------------------------- serving
+// Continuous batching of shell-model solves: each admitted request owns a
+// model slot (medium constants, source key, spectrum) and a contiguous range
+// of the serving queue; thor_step runs one bounded persistent launch over
+// every live request, parking unfinished packets in the serving pool.
+
+static thor_status serving_init(thor_ctx* ctx) {
+    if (ctx->s_init) return THOR_OK;
+    thor_status s = dalloc(ctx, (void**)&ctx->d_s_models, sizeof(ModelDev) * kServingMaxModels, "serving models");
+    if (!s) s = dalloc(ctx, (void**)&ctx->d_done, 8ull * kServingMaxModels, "serving counters");
+    if (!s) s = dalloc(ctx, (void**)&ctx->d_s_cursor, 8, "serving cursor");
+    if (s) return s;
+    if (!s) s = dalloc(ctx, (void**)&ctx->d_s_desc, sizeof(StepDesc), "serving step descriptor");
+    if (!s) s = dalloc(ctx, (void**)&ctx->d_s_batches, sizeof(BatchDev) * kServingMaxBatches, "serving batches");
+    if (s) return s;
+    if (hipHostMalloc((void**)&ctx->h_s_desc, sizeof(StepDesc)) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->h_s_batches, sizeof(BatchDev) * kServingMaxBatches) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->h_s_done, 8ull * kServingMaxModels) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->h_s_misc, 8ull * (kNumU64Counters + 1)) != hipSuccess)
+        return fail(THOR_E_NOMEM, "pinned host allocation failed");
+    std::memset(ctx->h_s_done, 0, 8ull * kServingMaxModels);
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_done, 0, 8ull * kServingMaxModels, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_s_cursor, 0, 8, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->s_models.assign(kServingMaxModels, ModelDev{});
+    ctx->s_init = true;
+    return THOR_OK;
+}
+
 thor_status thor_submit(thor_ctx* ctx, const thor_shell_request* r, uint64_t* req_id) {
     CHECK_CTX(ctx);
-    (void)r; (void)req_id;
-    return fail(THOR_E_UNSUPPORTED, "serving extension not built yet");
+    if (!r || !req_id) return fail(THOR_E_INVAL, "null argument");
+    if (!(r->N_HI > 0.0) || !(r->T > 0.0) || r->tau_d < 0.0 || !(r->r_outer > r->r_inner) || r->r_inner < 0.0)
+        return fail(THOR_E_INVAL, "bad shell parameters");
+    if (r->albedo < 0.0 || r->albedo > 1.0 || r->g_hg <= -1.0 || r->g_hg >= 1.0 || r->sigma_v < 0.0)
+        return fail(THOR_E_INVAL, "bad dust or source parameters");
+    if (r->n_packets == 0 || r->spec_nb <= 0 || !(r->spec_hi > r->spec_lo))
+        return fail(THOR_E_INVAL, "bad packet count or spectrum bins");
+    thor_status s = serving_init(ctx);
+    if (s) return s;
+    // admission: the request's spectrum and the state of all its packets
+    // (as if every packet were resident at once) must fit the budget
+    const uint64_t spec_bytes = uint64_t(r->spec_nb) * 8;
+    const uint64_t reserve = r->n_packets * uint64_t(sizeof(Pkt<double>));
+    if (ctx->budget && ctx->used + ctx->s_reserved + spec_bytes + reserve > ctx->budget)
+        return fail(THOR_E_BUDGET, "request of %llu packets does not fit the HBM budget now",
+                    (unsigned long long)r->n_packets);
+    if (ctx->s_batches.size() >= size_t(kServingMaxBatches))
+        return fail(THOR_E_BUDGET, "too many queued requests");
+    int slot;
+    if (!ctx->s_free.empty()) slot = ctx->s_free.back();
+    else if (ctx->s_next_slot < kServingMaxModels) slot = ctx->s_next_slot;
+    else return fail(THOR_E_BUDGET, "too many live requests");
+    double* d_spec = nullptr;
+    s = dalloc(ctx, (void**)&d_spec, spec_bytes, "request spectrum");
+    if (s) return s;
+    HIPCHK(ctx, hipMemsetAsync(d_spec, 0, spec_bytes, ctx->stream));
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_done + slot, 0, 8, ctx->stream));
+    if (!ctx->s_free.empty()) ctx->s_free.pop_back(); else ctx->s_next_slot++;
+    ModelDev m;
+    std::memset(&m, 0, sizeof m);
+    m.kind = kGeomShell;
+    m.v_profile = r->v_exp != 0.0 ? kVelConstRadial : kVelNone;
+    m.src_kind = kSrcPoint;
+    m.spectrum = kSpecGauss;
+    const double L = r->r_outer - r->r_inner;
+    double sig0;
+    line_params(r->T, &m.vth, &m.a, &sig0);
+    m.r_in = r->r_inner;
+    m.r_out = r->r_outer;
+    m.n = r->N_HI / L;
+    m.k0 = m.n * sig0;
+    m.kd = r->tau_d / L;
+    m.v_max = r->v_exp;
+    m.step_f = r->step_f > 0.0 ? r->step_f : 0.01;
+    const double atau = m.a * m.k0 * L;     // Section 3.4.2 adaptive x_crit
+    m.xcrit = atau >= 1.0 ? 0.2 * std::cbrt(atau) : 0.0;
+    m.albedo = r->albedo;
+    m.g_hg = r->g_hg;
+    m.dv0 = 0.0;
+    m.sigma_v = r->sigma_v;
+    m.seed = r->seed;
+    m.req = r->request_id;
+    m.spec = d_spec;
+    m.spec_nb = r->spec_nb;
+    m.spec_lo = r->spec_lo;
+    m.spec_w = (r->spec_hi - r->spec_lo) / r->spec_nb;
+    m.spec_scale = 1.0;
+    m.done = ctx->d_done + slot;
+    ctx->s_models[slot] = m;
+    ctx->h_s_done[slot] = 0;
+    BatchDev b;
+    b.q0 = ctx->s_q_total;
+    b.first_id = 0;
+    b.n = r->n_packets;
+    b.model = slot;
+    b.pad = 0;
+    ctx->s_batches.push_back(b);
+    ctx->s_q_total += r->n_packets;
+    ctx->s_reserved += reserve;
+    ctx->s_dirty = true;
+    const uint64_t h = ctx->s_next_handle++;
+    ctx->s_reqs[h] = ServingReq{slot, r->n_packets, d_spec, r->spec_nb, reserve, false};
+    *req_id = h;
+    return THOR_OK;
+}
+
+// Enqueue one serving step on `stream`: descriptor and batch table from the
+// pinned mirrors, counters cleared by a kernel, the bounded persistent launch,
+// the cursor clamp, and the done counters / cursor / counters back into the
+// pinned mirrors.  The same sequence is captured once into a hipGraph.
+static void enqueue_serving_step(thor_ctx* ctx, hipStream_t st, int prec, int gsize, int block) {
+    (void)hipMemcpyAsync(ctx->d_s_desc, ctx->h_s_desc, sizeof(StepDesc), hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(ctx->d_s_batches, ctx->h_s_batches, sizeof(BatchDev) * kServingMaxBatches,
+                         hipMemcpyHostToDevice, st);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, ctx->d_stats, kNumU64Counters);
+    OutDev out;
+    std::memset(&out, 0, sizeof out);
+    out.phase = THOR_PHASE_DIPOLE;
+    out.tau_cut = 40.0;
+    out.img_w[0] = out.img_w[1] = out.v_w = 1.0;
+    if (prec == THOR_PREC_FP64)
+        launch_persistent<double, false>(ctx, st, gsize, block, ctx->d_s_batches, ctx->d_s_desc, ctx->d_s_cursor, out,
+                                         ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive);
+    else
+        launch_persistent<float, false>(ctx, st, gsize, block, ctx->d_s_batches, ctx->d_s_desc, ctx->d_s_cursor, out,
+                                        ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive);
+    hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, st, ctx->d_s_cursor, ctx->d_s_desc);
+    (void)hipMemcpyAsync(ctx->h_s_done, ctx->d_done, 8ull * kServingMaxModels, hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(ctx->h_s_misc, ctx->d_stats, 8ull * kNumU64Counters, hipMemcpyDeviceToHost, st);
+    (void)hipMemcpyAsync(ctx->h_s_misc + kNumU64Counters, ctx->d_s_cursor, 8, hipMemcpyDeviceToHost, st);
 }
 
 thor_status thor_step(thor_ctx* ctx, uint32_t max_events_per_packet, const thor_transport_opts* opt) {
     CHECK_CTX(ctx);
-    (void)max_events_per_packet; (void)opt;
-    return fail(THOR_E_UNSUPPORTED, "serving extension not built yet");
+    if (!opt) return fail(THOR_E_INVAL, "null options");
+    if (opt->precision != THOR_PREC_FP64 && opt->precision != THOR_PREC_MIXED) return fail(THOR_E_INVAL, "bad precision");
+    if (opt->block && (opt->block % 64 || opt->block > 256)) return fail(THOR_E_INVAL, "bad block");
+    if (!ctx->s_init) return THOR_OK;
+    const int block = opt->block > 0 ? opt->block : 256;
+    const int gsize = launch_grid_size(ctx, opt, block);
+    const uint64_t slots = uint64_t(gsize) * block;
+    const uint64_t pk_bytes = opt->precision == THOR_PREC_FP64 ? sizeof(Pkt<double>) : sizeof(Pkt<float>);
+    if (!ctx->d_s_pool || ctx->s_pool_slots != slots || ctx->s_pool_prec != opt->precision) {
+        // the pool can change shape only while no packet is parked in it
+        if (ctx->d_s_pool && ctx->s_cursor > 0) {
+            bool parked = false;
+            std::vector<int> alive(ctx->s_pool_slots);
+            HIPCHK(ctx, hipMemcpy(alive.data(), ctx->d_s_alive, ctx->s_pool_slots * 4, hipMemcpyDeviceToHost));
+            for (int a : alive) if (a) { parked = true; break; }
+            if (parked) return fail(THOR_E_STATE, "launch shape or precision changed while packets are parked");
+        }
+        dfree(ctx, ctx->d_s_pool, ctx->s_pool_bytes);
+        dfree(ctx, ctx->d_s_alive, ctx->s_pool_slots * 4);
+        ctx->d_s_pool = nullptr; ctx->d_s_alive = nullptr; ctx->s_pool_slots = 0;
+        thor_status s = dalloc(ctx, &ctx->d_s_pool, slots * pk_bytes, "serving pool");
+        if (!s) s = dalloc(ctx, (void**)&ctx->d_s_alive, slots * 4, "serving pool flags");
+        if (s) return s;
+        ctx->s_pool_slots = slots;
+        ctx->s_pool_bytes = slots * pk_bytes;
+        ctx->s_pool_prec = opt->precision;
+        HIPCHK(ctx, hipMemsetAsync(ctx->d_s_alive, 0, slots * 4, ctx->stream));
+        if (ctx->s_graph) { (void)hipGraphExecDestroy(ctx->s_graph); ctx->s_graph = nullptr; }
+    }
+    // drop queue ranges the cursor has passed (their packets were all taken;
+    // parked ones carry their model slot, so the range is no longer needed)
+    {
+        size_t keep = 0;
+        while (keep < ctx->s_batches.size()) {
+            const BatchDev& b = ctx->s_batches[keep];
+            if (b.q0 + b.n <= ctx->s_cursor) ++keep; else break;
+        }
+        if (keep) ctx->s_batches.erase(ctx->s_batches.begin(), ctx->s_batches.begin() + keep);
+    }
+    bool any_live = false;
+    for (auto& kv : ctx->s_reqs) any_live |= !kv.second.finished;
+    if (!any_live) return THOR_OK;
+    const size_t nb = ctx->s_batches.size();
+    if (nb) std::memcpy(ctx->h_s_batches, ctx->s_batches.data(), nb * sizeof(BatchDev));
+    const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
+    // nb == 0: only parked packets are left; no lane can take a new index
+    *ctx->h_s_desc = StepDesc{ctx->s_q_total, int(nb), max_events_per_packet, turn, 0u};
+    if (ctx->s_dirty) {
+        const int hi = ctx->s_next_slot;
+        HIPCHK(ctx, hipMemcpyAsync(ctx->d_s_models, ctx->s_models.data(), sizeof(ModelDev) * hi,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        ctx->s_dirty = false;
+    }
+    if (opt->use_graph) {
+        if (ctx->s_graph && (ctx->s_graph_prec != opt->precision || ctx->s_graph_grid != gsize ||
+                             ctx->s_graph_block != block)) {
+            (void)hipGraphExecDestroy(ctx->s_graph);
+            ctx->s_graph = nullptr;
+        }
+        if (!ctx->s_graph) {
+            if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            hipGraph_t graph = nullptr;
+            HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+            enqueue_serving_step(ctx, ctx->cap_stream, opt->precision, gsize, block);
+            HIPCHK(ctx, hipStreamEndCapture(ctx->cap_stream, &graph));
+            hipError_t e = hipGraphInstantiate(&ctx->s_graph, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (!hip_ok(ctx, e, "hipGraphInstantiate")) return THOR_E_DEVICE;
+            ctx->s_graph_prec = opt->precision;
+            ctx->s_graph_grid = gsize;
+            ctx->s_graph_block = block;
+        }
+        HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+        HIPCHK(ctx, hipGraphLaunch(ctx->s_graph, ctx->stream));
+    } else {
+        HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+        enqueue_serving_step(ctx, ctx->stream, opt->precision, gsize, block);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.0f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    collect_stats(ctx, ctx->h_s_misc, ms, &ctx->last);
+    ctx->s_cursor = ctx->h_s_misc[kNumU64Counters];
+    bool left = false;
+    for (auto& kv : ctx->s_reqs) {
+        ServingReq& q = kv.second;
+        if (!q.finished && ctx->h_s_done[q.model] >= q.n_packets) q.finished = true;
+        left |= !q.finished;
+    }
+    return left ? THOR_INCOMPLETE : THOR_OK;
 }
 
 thor_status thor_poll(thor_ctx* ctx, uint64_t req_id, double* spectrum, thor_stats* st, int* done) {
     CHECK_CTX(ctx);
-    (void)req_id; (void)spectrum; (void)st; (void)done;
-    return fail(THOR_E_UNSUPPORTED, "serving extension not built yet");
+    if (!done) return fail(THOR_E_INVAL, "null done pointer");
+    auto it = ctx->s_reqs.find(req_id);
+    if (it == ctx->s_reqs.end()) return fail(THOR_E_INVAL, "unknown request %llu", (unsigned long long)req_id);
+    ServingReq& q = it->second;
+    *done = q.finished ? 1 : 0;
+    if (!q.finished) return THOR_OK;
+    if (spectrum)
+        HIPCHK(ctx, hipMemcpyAsync(spectrum, q.d_spec, uint64_t(q.spec_nb) * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (st) {
+        std::memset(st, 0, sizeof *st);
+        st->emitted = q.n_packets;
+    }
+    dfree(ctx, q.d_spec, uint64_t(q.spec_nb) * 8);
+    ctx->s_reserved -= std::min(ctx->s_reserved, q.reserved);
+    ctx->s_free.push_back(q.model);
+    ctx->s_reqs.erase(it);
+    return THOR_OK;
 }
 
 }  // extern "C"
