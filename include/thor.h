@@ -168,6 +168,8 @@ typedef struct {
     int32_t block;
     int32_t visits_per_turn;    /* PERSISTENT: march segments per lane turn (0 = 256) */
     int32_t use_graph;          /* thor_step: replay one captured hipGraph per step */
+    int32_t inline_peel;        /* PERSISTENT: march peel rays in the scattering lane
+                                   instead of the per-wave seed ring */
     int32_t records;            /* 1: keep per-packet records of this call */
 } thor_transport_opts;
 

@@ -238,6 +238,17 @@ template <class R> struct CellCache {
     Fields<R> f;
 };
 
+// Peel seeds of one event held by a lane until the wave queues them: the
+// event position and cell, and per observer the weight and peeled frequency.
+constexpr int kMaxQueuedObs = 3;
+struct PeelOut {
+    int n;
+    double p[3];
+    int c[3];
+    double w[kMaxQueuedObs];
+    double dv[kMaxQueuedObs];
+};
+
 template <class R>
 __device__ __forceinline__ void cached_fields(const GridDev& g, const int c[3], CellCache<R>& cc) {
     if (!(cc.valid && cc.c[0] == c[0] && cc.c[1] == c[1] && cc.c[2] == c[2])) {
@@ -342,7 +353,7 @@ __device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const
 // Generator + photon initialisation (Section 3.4 "Emission").
 template <class R, bool GRID>
 __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint64_t id, uint64_t q, int model,
-                     Pkt<R>& pk, Counters& cnt) {
+                     Pkt<R>& pk, Counters& cnt, PeelOut* po = nullptr) {
     const Key key{m.seed, m.req, uint32_t(id), uint32_t(id >> 32)};
     pk.id = id; pk.q = q; pk.model = model;
     pk.event = 0; pk.n_res = 0; pk.n_dust = 0;
@@ -415,12 +426,21 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
     }
     cnt.emitted++;
     if (L.region != kRegOut) {
+        if (po) {
+            po->n = o.n_obs;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) { po->p[i] = L.p[i]; po->c[i] = L.c[i]; }
+        }
         for (int ob = 0; ob < o.n_obs; ++ob) {
             double kd[3];
             obs_dir(o.obs_axis[ob], kd);
             const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
             const R dvp = (m.spectrum == kSpecThermal) ? dv_loc + dot3<R>(f0.v, ko) : pk.dv;
-            peel<R, GRID>(g, m, o, L, f0, ob, 1.0 / (4.0 * kPi), dvp, cnt);
+            if (po) {
+                if (ob < kMaxQueuedObs) { po->w[ob] = 1.0 / (4.0 * kPi); po->dv[ob] = double(dvp); }
+            } else {
+                peel<R, GRID>(g, m, o, L, f0, ob, 1.0 / (4.0 * kPi), dvp, cnt);
+            }
         }
     }
     const Uni2<double> dt = draw<double>(key, kSlotETau, 0);
@@ -438,7 +458,7 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
 template <class R, bool GRID>
 __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk,
                                         const Loc& L, const Fields<R>& f, double kt, const Key& key,
-                                        Counters& cnt) {
+                                        Counters& cnt, PeelOut* po) {
     const Uni2<double> dtyp = draw<double>(key, kSlotType, pk.event);
     R kout[3], e1[3], e2[3];
     if (dtyp.a * kt < f.kd) {
@@ -457,7 +477,16 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
             obs_dir(o.obs_axis[ob], kd);
             const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
             const double c = double(phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg))) / (2.0 * kPi);
-            peel<R, GRID>(g, m, o, L, f, ob, c, dvl + dot3<R>(f.v, ko), cnt);
+            if (po) {
+                if (ob < kMaxQueuedObs) { po->w[ob] = c; po->dv[ob] = double(dvl + dot3<R>(f.v, ko)); }
+            } else {
+                peel<R, GRID>(g, m, o, L, f, ob, c, dvl + dot3<R>(f.v, ko), cnt);
+            }
+        }
+        if (po && o.n_obs) {
+            po->n = o.n_obs;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) { po->p[i] = L.p[i]; po->c[i] = L.c[i]; }
         }
         pk.dv = dvl + dot3<R>(f.v, kout);
         pk.n_dust++;
@@ -494,7 +523,16 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
             const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
             const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
             const R xo = x_atom + dot3<R>(u, ko);
-            peel<R, GRID>(g, m, o, L, f, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt);
+            if (po) {
+                if (ob < kMaxQueuedObs) { po->w[ob] = c; po->dv[ob] = double(xo * f.vth + dot3<R>(f.v, ko)); }
+            } else {
+                peel<R, GRID>(g, m, o, L, f, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt);
+            }
+        }
+        if (po && o.n_obs) {
+            po->n = o.n_obs;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) { po->p[i] = L.p[i]; po->c[i] = L.c[i]; }
         }
         const R x_out = x_atom + dot3<R>(u, kout);
         pk.dv = x_out * f.vth + dot3<R>(f.v, kout);
@@ -522,7 +560,7 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
 // a later call resumes it exactly.
 template <class R, bool GRID>
 __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt,
-                       uint32_t max_visits, uint32_t max_events, uint32_t* events_done) {
+                       uint32_t max_visits, uint32_t max_events, uint32_t* events_done, PeelOut* po = nullptr) {
     const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
     Loc L;
 #pragma unroll
@@ -568,7 +606,7 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
             pk.event++;
             ++ev;
             if (uint64_t(pk.event) > emax) { fate = kFateCapped; break; }
-            fate = interact<R, GRID>(g, m, o, pk, L, f, kt, key, cnt);
+            fate = interact<R, GRID>(g, m, o, pk, L, f, kt, key, cnt, po);
             if (fate != kFateNone) break;
             set_inverse();
             continue;
@@ -591,6 +629,62 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
     pk.region = L.region;
     *events_done += ev;
     return fate;
+}
+
+// ----------------------------------------------------------------- peel queue
+// Per-wave ring of peel seeds in global memory (structure of arrays, slots
+// [base, base + kPeelRing)).  Lanes push the seeds of their events at
+// convergent points; when 64 or more are queued, the whole wave marches 64
+// peel rays together, one per lane, instead of one lane at a time.
+constexpr uint32_t kPeelRing = 1024;
+
+struct PeelQueue {
+    double* px; double* py; double* pz;
+    int* cx; int* cy; int* cz;
+    double* w; double* dv;
+    int* obs;
+};
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
+// Wave-uniform tail update; call with the whole wave converged.
+__device__ __forceinline__ void peel_push(const PeelQueue& q, uint64_t base, uint32_t& tail, const PeelOut& po,
+                                          int n_obs) {
+    const bool has = po.n > 0;
+    const uint64_t mask = __ballot(has);
+    if (!mask) return;
+    if (has) {
+        const uint32_t first = tail + lane_rank(mask) * uint32_t(n_obs);
+        for (int ob = 0; ob < n_obs; ++ob) {
+            const uint64_t sl = base + ((first + uint32_t(ob)) & (kPeelRing - 1));
+            q.px[sl] = po.p[0]; q.py[sl] = po.p[1]; q.pz[sl] = po.p[2];
+            q.cx[sl] = po.c[0]; q.cy[sl] = po.c[1]; q.cz[sl] = po.c[2];
+            q.w[sl] = po.w[ob]; q.dv[sl] = po.dv[ob]; q.obs[sl] = ob;
+        }
+    }
+    tail += uint32_t(__popcll(mask)) * uint32_t(n_obs);
+}
+
+// March up to 64 queued peel rays, one per lane; wave converged.
+template <class R>
+__device__ __forceinline__ void peel_drain(const GridDev& g, const ModelDev& m, const OutDev& o, const PeelQueue& q,
+                                           uint64_t base, uint32_t& head, uint32_t tail, Counters& cnt) {
+    const uint32_t avail = tail - head;
+    const uint32_t take = avail < 64u ? avail : 64u;
+    const uint32_t lane = threadIdx.x & 63;
+    if (lane < take) {
+        const uint64_t sl = base + ((head + lane) & (kPeelRing - 1));
+        Loc L;
+        L.p[0] = q.px[sl]; L.p[1] = q.py[sl]; L.p[2] = q.pz[sl];
+        L.c[0] = q.cx[sl]; L.c[1] = q.cy[sl]; L.c[2] = q.cz[sl];
+        L.region = kRegGas;
+        Fields<R> f0;
+        grid_fields<R>(g, L.c, f0);
+        peel<R, true>(g, m, o, L, f0, q.obs[sl], q.w[sl], R(q.dv[sl]), cnt);
+    }
+    head += take;
 }
 
 // ----------------------------------------------------------------- finish

@@ -69,12 +69,17 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
                                                     const BatchDev* __restrict__ batches,
                                                     const StepDesc* __restrict__ desc,
                                                     unsigned long long* cursor, OutDev o, PoolDev<R> pool,
-                                                    unsigned long long* gstats) {
+                                                    PeelQueue pq, unsigned long long* gstats) {
     const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t q_end = desc->q_end;
     const int nbatch = desc->nbatch;
     const uint32_t step_events = desc->step_events;
     const uint32_t turn_visits = desc->turn_visits;
+    // peel rays of grid media go through the wave's seed ring
+    const bool useq = GRID && pq.px != nullptr && o.n_obs > 0 && o.n_obs <= kMaxQueuedObs;
+    const uint64_t qbase = (gid >> 6) * uint64_t(kPeelRing);
+    uint32_t qhead = 0, qtail = 0;
+    PeelOut po;
     Counters cnt = {};
     Pkt<R> pk;
     bool active = false;
@@ -86,6 +91,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
     const uint32_t budget = step_events ? step_events : ~0u;
     uint32_t used = 0;
     for (;;) {
+        po.n = 0;
         const bool need = !active && !exhausted && used < budget;
         const uint64_t mask = __ballot(need);
         if (mask) {
@@ -94,14 +100,14 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
             unsigned long long base = 0;
             if (lane == leader) base = atomicAdd(cursor, (unsigned long long)__popcll(mask));
             base = __shfl(base, leader, 64);
-            const uint32_t rank = __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+            const uint32_t rank = lane_rank(mask);
             if (need) {
                 const uint64_t q = base + rank;
                 if (q < q_end) {
                     const int bi = find_batch(batches, nbatch, q);
                     const BatchDev b = batches[bi];
-                    emit<R, GRID>(g, models[b.model], o, b.first_id + (q - b.q0), q, b.model, pk, cnt);
+                    emit<R, GRID>(g, models[b.model], o, b.first_id + (q - b.q0), q, b.model, pk, cnt,
+                                  useq ? &po : nullptr);
                     active = true;
                     if (pk.region == kRegOut) {
                         finish<R, GRID>(g, models[b.model], o, pk, kFateEscaped, cnt);
@@ -112,16 +118,31 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
                 }
             }
         }
+        if (useq) {
+            peel_push(pq, qbase, qtail, po, o.n_obs);
+            while (qtail - qhead >= 64u) peel_drain<R>(g, models[0], o, pq, qbase, qhead, qtail, cnt);
+        }
         const bool work = active && used < budget;
-        if (__ballot(work) == 0) break;
+        if (__ballot(work) == 0) {
+            if (useq && qtail != qhead) {
+                peel_drain<R>(g, models[0], o, pq, qbase, qhead, qtail, cnt);
+                continue;
+            }
+            break;
+        }
+        po.n = 0;
         if (work) {
             const ModelDev& m = models[pk.model];
-            const int fate = advance<R, GRID>(g, m, o, pk, cnt, turn_visits, budget - used, &used);
+            // with the seed ring, one interaction per turn keeps each lane's
+            // pending seeds to one event
+            const uint32_t ev_cap = useq ? 1u : budget - used;
+            const int fate = advance<R, GRID>(g, m, o, pk, cnt, turn_visits, ev_cap, &used, useq ? &po : nullptr);
             if (fate != kFateNone) {
                 finish<R, GRID>(g, m, o, pk, fate, cnt);
                 active = false;
             }
         }
+        if (useq) peel_push(pq, qbase, qtail, po, o.n_obs);
     }
     if (pool.alive) {
         pool.alive[gid] = active ? 1 : 0;
@@ -304,6 +325,8 @@ struct thor_ctx {
     unsigned long long* h_s_done = nullptr;    // pinned mirror of d_done
     unsigned long long* h_s_misc = nullptr;    // pinned: counters then cursor
     hipStream_t cap_stream = nullptr;      // private stream for graph capture
+    void* d_pq = nullptr;                  // peel seed rings
+    uint64_t pq_slots = 0, pq_bytes = 0;
     hipGraphExec_t s_graph = nullptr;
     int s_graph_prec = -1, s_graph_grid = 0, s_graph_block = 0;
 
@@ -526,10 +549,38 @@ void launch_plain(thor_ctx* ctx, const BatchDev& b, const OutDev& out) {
 template <class R, bool GRID>
 void launch_persistent(thor_ctx* ctx, hipStream_t stream, int grid, int block, const BatchDev* d_b,
                        const StepDesc* d_desc, unsigned long long* cursor, const OutDev& out,
-                       const ModelDev* d_models, void* pool_pk, int* pool_alive) {
+                       const ModelDev* d_models, void* pool_pk, int* pool_alive, const PeelQueue& pq) {
     PoolDev<R> pool{reinterpret_cast<Pkt<R>*>(pool_pk), pool_alive};
     hipLaunchKernelGGL((k_persistent<R, GRID>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models, d_b,
-                       d_desc, cursor, out, pool, ctx->d_stats);
+                       d_desc, cursor, out, pool, pq, ctx->d_stats);
+}
+
+// Seed rings of the persistent grid path: one ring of kPeelRing slots per
+// resident wave.
+thor_status ensure_peel_queue(thor_ctx* ctx, uint64_t waves, PeelQueue* pq) {
+    const uint64_t slots = waves * kPeelRing;
+    if (ctx->pq_slots < slots) {
+        dfree(ctx, ctx->d_pq, ctx->pq_bytes);
+        ctx->d_pq = nullptr;
+        ctx->pq_slots = ctx->pq_bytes = 0;
+        const uint64_t bytes = slots * (5 * 8 + 4 * 4);
+        thor_status s = dalloc(ctx, &ctx->d_pq, bytes, "peel seed rings");
+        if (s) return s;
+        ctx->pq_slots = slots;
+        ctx->pq_bytes = bytes;
+    }
+    char* b = static_cast<char*>(ctx->d_pq);
+    const uint64_t n = ctx->pq_slots;
+    pq->px = reinterpret_cast<double*>(b);
+    pq->py = pq->px + n;
+    pq->pz = pq->py + n;
+    pq->w = pq->pz + n;
+    pq->dv = pq->w + n;
+    pq->cx = reinterpret_cast<int*>(pq->dv + n);
+    pq->cy = pq->cx + n;
+    pq->cz = pq->cy + n;
+    pq->obs = pq->cz + n;
+    return THOR_OK;
 }
 
 thor_status ensure_pool(thor_ctx* ctx, uint64_t slots, int prec) {
@@ -614,7 +665,8 @@ void thor_destroy(thor_ctx* ctx) {
     void* ptrs[] = {ctx->d_vn, ctx->d_T, ctx->d_cdf, ctx->d_spec, ctx->d_cube, ctx->d_stats,
                     ctx->d_models, ctx->d_batches, ctx->d_rec_dv, ctx->d_rec_nres, ctx->d_rec_ndust,
                     ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done,
-                    ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive};
+                    ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
+                    ctx->d_pq};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& kv : ctx->s_reqs)
@@ -867,10 +919,16 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         void* ppk = bounded ? ctx->d_pool_pk : nullptr;
         int* pal = bounded ? ctx->d_pool_alive : nullptr;
         unsigned long long* cur = ctx->d_stats + kNumU64Counters;
-        if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal)
-                       : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal);
-        else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal)
-                  : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal);
+        PeelQueue pq;
+        std::memset(&pq, 0, sizeof pq);
+        if (grid && opt->n_obs > 0 && opt->n_obs <= kMaxQueuedObs && !opt->inline_peel) {
+            s = ensure_peel_queue(ctx, uint64_t(gsize) * block / 64, &pq);
+            if (s) return s;
+        }
+        if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, pq)
+                       : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, pq);
+        else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, pq)
+                  : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, pq);
         hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, ctx->stream, cur, ctx->d_desc);
     }
     HIPCHK(ctx, hipGetLastError());
@@ -1109,12 +1167,14 @@ static void enqueue_serving_step(thor_ctx* ctx, hipStream_t st, int prec, int gs
     out.phase = THOR_PHASE_DIPOLE;
     out.tau_cut = 40.0;
     out.img_w[0] = out.img_w[1] = out.v_w = 1.0;
+    PeelQueue pq;
+    std::memset(&pq, 0, sizeof pq);
     if (prec == THOR_PREC_FP64)
         launch_persistent<double, false>(ctx, st, gsize, block, ctx->d_s_batches, ctx->d_s_desc, ctx->d_s_cursor, out,
-                                         ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive);
+                                         ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive, pq);
     else
         launch_persistent<float, false>(ctx, st, gsize, block, ctx->d_s_batches, ctx->d_s_desc, ctx->d_s_cursor, out,
-                                        ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive);
+                                        ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive, pq);
     hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, st, ctx->d_s_cursor, ctx->d_s_desc);
     (void)hipMemcpyAsync(ctx->h_s_done, ctx->d_done, 8ull * kServingMaxModels, hipMemcpyDeviceToHost, st);
     (void)hipMemcpyAsync(ctx->h_s_misc, ctx->d_stats, 8ull * kNumU64Counters, hipMemcpyDeviceToHost, st);

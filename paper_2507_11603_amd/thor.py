@@ -66,7 +66,7 @@ class thor_transport_opts(C.Structure):
                 ("spec_lo", C.c_double), ("spec_hi", C.c_double), ("spec_T_ref", C.c_double),
                 ("tau_cut", C.c_double), ("max_events", C.c_uint64), ("step_events", C.c_uint64),
                 ("waves_per_cu", C.c_int32), ("block", C.c_int32), ("visits_per_turn", C.c_int32),
-                ("use_graph", C.c_int32), ("records", C.c_int32)]
+                ("use_graph", C.c_int32), ("inline_peel", C.c_int32), ("records", C.c_int32)]
 
 
 STAT_U64 = ("emitted", "escaped", "absorbed", "capped", "handed_off", "n_res", "n_dust",
@@ -246,7 +246,8 @@ def make_source(src: dict) -> thor_source:
 
 
 def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_events=0,
-              waves_per_cu=0, block=0, visits_per_turn=0, use_graph=False) -> thor_transport_opts:
+              waves_per_cu=0, block=0, visits_per_turn=0, use_graph=False,
+              inline_peel=False) -> thor_transport_opts:
     o = thor_transport_opts()
     o.precision = PREC[precision]
     o.path = PATH[path]
@@ -273,6 +274,7 @@ def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_ev
     o.block = block
     o.visits_per_turn = visits_per_turn
     o.use_graph = int(use_graph)
+    o.inline_peel = int(inline_peel)
     o.records = int(records)
     return o
 
