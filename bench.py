@@ -38,12 +38,16 @@ def parse():
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--turn-visits", type=int, default=0)
+    ap.add_argument("--inline-peel", type=int, default=0, help="march peel rays in the scattering lane")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=400000, help="packets of the oracle sample")
     ap.add_argument("--autotune", type=int, default=1, help="pick launch knobs with the autotuner")
     ap.add_argument("--serving", type=int, default=300, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serving-warmup", type=int, default=60)
     ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--web-grid", type=int, default=0,
+                    help="also measure the cosmic-web box at this grid size (fields generated on the GPU)")
+    ap.add_argument("--web-packets", type=int, default=100_000)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (PMC calibration)")
     return ap.parse_args()
@@ -101,6 +105,36 @@ def serving(a, kw):
             "steps": r["steps"], "budget_deferrals": r["deferrals"], "graph_steps": True}
 
 
+def web_box(a, kw):
+    """Cosmic-web box (n_HI^2 thermal emission, x_crit = 3, three observers):
+    cell visits per second and the HBM-gather fraction at 20 B per visit."""
+    import torch
+
+    import workloads as W
+    from paper_2507_11603_amd import thor
+    f = W.web_fields_torch(a.web_grid)
+    wl = W.web(n_grid=a.web_grid, fields=f)
+    T = thor.Transport(0)
+    try:
+        T.load(wl["geom"])
+        del f, wl["geom"]["n_HI_field"], wl["geom"]["T_field"], wl["geom"]["vx"], wl["geom"]["vy"], wl["geom"]["vz"]
+        torch.cuda.empty_cache()
+        wkw = {k: v for k, v in kw.items() if k != "visits_per_turn"}
+        run_steps(T, wl, a.web_packets // 10, 1, 10**13, **wkw)           # warm-up (CDF, caches)
+        dt, st = run_steps(T, wl, a.web_packets, 1, 0, **wkw)
+    finally:
+        T.close()
+    visits = st["main_visits"] + st["peel_visits"]
+    ks = st["kernel_ms"] / 1e3
+    ach = BYTES_PER_VISIT * visits / ks / 1e9
+    return {"grid": a.web_grid, "packets": a.web_packets, "seconds": dt, "kernel_ms": st["kernel_ms"],
+            "scatterings_per_s": (st["n_res"] + st["n_dust"]) / dt, "packets_per_s": st["emitted"] / dt,
+            "main_visits": st["main_visits"], "peel_visits": st["peel_visits"],
+            "cell_visits_per_s": visits / ks,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None}}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -129,9 +163,9 @@ def main():
     T = thor.Transport(0)
     T.load(wl["geom"])
     kw = dict(precision=a.precision, path=a.path, waves_per_cu=a.waves_per_cu, block=a.block,
-              visits_per_turn=a.turn_visits)
+              visits_per_turn=a.turn_visits, inline_peel=bool(a.inline_peel))
     tuned = None
-    if a.autotune and a.path == "persistent" and not (a.waves_per_cu or a.block or a.turn_visits):
+    if a.autotune and a.path == "persistent" and not (a.waves_per_cu or a.block or a.turn_visits or a.inline_peel):
         from paper_2507_11603_amd import autotune
         tuned, _ = autotune.tune(T, wl, "shell%d" % a.grid, a.precision,
                                  log=lambda m: print(m, file=sys.stderr, flush=True))
@@ -182,6 +216,8 @@ def main():
     T.close()
     if a.serving:
         out["serving"] = serving(a, kw)
+    if a.web_grid:
+        out["web"] = web_box(a, kw)
     if cpu:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

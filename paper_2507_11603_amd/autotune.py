@@ -49,7 +49,7 @@ def tune(T, wl: dict, workload: str, precision: str = "mixed", sample: int = 200
     name = torch.cuda.get_device_name(T.device)
     key = _key(name, workload, precision)
     cache = load_cache()
-    if use_cache and key in cache:
+    if use_cache and key in cache and cache[key].get("version") == 2:
         return cache[key]["best"], cache[key]["table"]
     space = space or DEFAULT_SPACE
     table = []
@@ -69,7 +69,7 @@ def tune(T, wl: dict, workload: str, precision: str = "mixed", sample: int = 200
                 if log:
                     log("autotune %s: %.1f ms" % (knobs, dt * 1e3))
     best = min(table, key=lambda r: r[1])[0]
-    cache[key] = dict(best=best, table=table, sample=sample, batches=batches)
+    cache[key] = dict(best=best, table=table, sample=sample, batches=batches, version=2)
     save_cache(cache)
     T.reset()
     return best, table

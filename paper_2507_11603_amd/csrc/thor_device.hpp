@@ -56,10 +56,11 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        // one 32x32 -> 64-bit product gives both halves (v_mad_u64_u32)
+        const uint64_t p0 = uint64_t(c0) * 0xD2511F53u;
+        const uint64_t p1 = uint64_t(c2) * 0xCD9E8D57u;
+        const uint32_t n0 = uint32_t(p1 >> 32) ^ c1 ^ k0, n2 = uint32_t(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0; c1 = uint32_t(p1); c2 = n2; c3 = uint32_t(p0);
         k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
     }
     return Words{c0, c1, c2, c3};
@@ -88,6 +89,10 @@ template <> __device__ __forceinline__ Uni2<float> draw<float>(const Key& k, uin
 // Slot map: event 0 = emission, event e >= 1 = e-th interaction.
 enum : uint32_t { kSlotEDir = 0, kSlotEGauss = 1, kSlotECell = 2, kSlotEOffs = 3, kSlotETau = 4 };
 enum : uint32_t { kSlotType = 0, kSlotUperp = 1, kSlotMu = 2, kSlotTau = 3, kSlotUpar = 4 };
+
+// Division: IEEE in FP64; reciprocal-based (about 1 ulp) in the FP32 path.
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float fdiv(float a, float b) { return __fdividef(a, b); }
 
 // ---------------------------------------------------------------------------
 // math shims per precision
@@ -219,12 +224,12 @@ __device__ __forceinline__ float voigt32(float a, float x) {
     float tr = ax, ti = a;
 #pragma unroll
     for (int k = 6; k >= 1; --k) {
-        const float inv = 1.0f / (tr * tr + ti * ti);
+        const float inv = __builtin_amdgcn_rcpf(tr * tr + ti * ti);
         const float h = 0.5f * float(k);
         tr = ax - h * tr * inv;
         ti = a + h * ti * inv;
     }
-    float h = ti / ((tr * tr + ti * ti) * float(kSqrtPi));
+    float h = __fdividef(ti, (tr * tr + ti * ti) * float(kSqrtPi));
     if (ax < 9.0f) h += __expf(-ax * ax);
     return h;
 }
@@ -333,12 +338,12 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
         float u0 = xa;
         for (int it = 0; it < 2; ++it) {
             if (u0 <= 0.0f) break;
-            u0 = xa - sqrtf(a * expm1f(u0 * u0) / (2.0f * pi * u0));
+            u0 = xa - sqrtf(__fdividef(a * expm1f(u0 * u0), 2.0f * pi * u0));
             u0 = fminf(fmaxf(u0, 0.0f), xa);
         }
         const float d = xa - u0;                    // >= 0
-        const float p1 = d > 0.0f ? atanf(a / d) : hpi;           // theta0 + pi/2
-        const float q2 = d > 0.0f ? pi - atanf(a / d) : hpi;      // pi/2 - theta0
+        const float p1 = d > 0.0f ? atanf(__fdividef(a, d)) : hpi;   // theta0 + pi/2
+        const float q2 = d > 0.0f ? pi - p1 : hpi;                  // pi/2 - theta0
         const float e0 = __expf(-u0 * u0);
         const float m = fmaf(e0, q2, p1);
         for (;;) {
@@ -347,30 +352,30 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
             ++n;
             const float r = r12.a * m;
             if (r < p1) {
-                u = xa - a / tanf(r);                   // tan(r - pi/2) = -1/tan(r)
+                u = xa - __fdividef(a, tanf(r));        // tan(r - pi/2) = -1/tan(r)
                 if (r12.b < __expf(-u * u)) break;
             } else {
-                u = xa + a / tanf(q2 - (r - p1) / e0);  // tan(pi/2 - psi) = 1/tan(psi)
+                u = xa + __fdividef(a, tanf(q2 - __fdividef(r - p1, e0)));  // tan(pi/2 - psi) = 1/tan(psi)
                 if (r12.b < __expf((u0 - u) * (u0 + u))) break;
             }
         }
     } else {
-        float u0 = sqrtf(__logf(float(kSqrtPi) * xa * xa / a) + 3.0f);
-        u0 = fminf(u0, xa - 0.3f / xa);
-        const float t0 = u0 / xa;
+        float u0 = sqrtf(__logf(__fdividef(float(kSqrtPi) * xa * xa, a)) + 3.0f);
+        u0 = fminf(u0, xa - __fdividef(0.3f, xa));
+        const float t0 = __fdividef(u0, xa);
         float c;
         if (t0 < 0.125f) {   // h(t) = sum_{k>=2} 2 t^(k-2) / k
             c = 1.0f + t0 * (2.0f / 3.0f + t0 * (0.5f + t0 * (0.4f + t0 * (1.0f / 3.0f + t0 * (2.0f / 7.0f + t0 * 0.25f)))));
             c *= 1.0f + 1e-5f;   // keeps the envelope a strict bound after truncation
         } else {
-            c = (-2.0f * log1pf(-t0) - 2.0f * t0) / (t0 * t0) * (1.0f + 1e-5f);
+            c = __fdividef(-2.0f * log1pf(-t0) - 2.0f * t0, t0 * t0) * (1.0f + 1e-5f);
         }
-        const float p = 1.0f - c / (xa * xa), mu = 1.0f / (xa * p);
-        const float za = __expf(p * mu * mu) * sqrtf(pi / p) / (xa * xa);
+        const float p = 1.0f - __fdividef(c, xa * xa), mu = __builtin_amdgcn_rcpf(xa * p);
+        const float za = __fdividef(__expf(p * mu * mu) * sqrtf(__fdividef(pi, p)), xa * xa);
         const float d = xa - u0;
-        const float q2 = pi - atanf(a / d);
+        const float q2 = pi - atanf(__fdividef(a, d));
         const float e0 = __expf(-u0 * u0);
-        const float zb = e0 * q2 / a;
+        const float zb = __fdividef(e0 * q2, a);
         for (;;) {
             if (n >= kUparMaxTrials) break;
             const Uni2<float> r12 = draw<float>(key, kSlotUpar + 2u * n, event);
@@ -380,15 +385,15 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
                 ++n;
                 float sn, cs;
                 sincospif(2.0f * r34.b, &sn, &cs);
-                u = mu + sqrtf(-__logf(1.0f - r34.a) / p) * cs;
+                u = mu + sqrtf(__fdividef(-__logf(1.0f - r34.a), p)) * cs;
                 if (u > u0) continue;
-                const float t = u / xa;
-                const float env = __expf(fmaf(c * t, t, 2.0f * t)) / (xa * xa);
-                const float tgt = 1.0f / fmaf(xa - u, xa - u, a * a);
+                const float t = __fdividef(u, xa);
+                const float env = __fdividef(__expf(fmaf(c * t, t, 2.0f * t)), xa * xa);
+                const float tgt = __builtin_amdgcn_rcpf(fmaf(xa - u, xa - u, a * a));
                 if (r12.b * env < tgt) break;
             } else {
                 ++n;
-                u = xa + a / tanf(q2 - (r - za) * a / e0);
+                u = xa + __fdividef(a, tanf(q2 - __fdividef((r - za) * a, e0)));
                 if (r12.b < __expf((u0 - u) * (u0 + u))) break;
             }
         }
@@ -414,9 +419,9 @@ enum : int { kPhaseIso = 0, kPhaseDipole = 1, kPhaseCoreWing = 2, kPhaseHG = 3 }
 
 template <class R> __device__ __forceinline__ R cubic_root_mu(R p, R q) {
     // real root of mu^3 + p mu = q (Cardano, p > 0)
-    const R disc = M<R>::sqrt(q * q / R(4) + p * p * p / R(27));
-    const R s = M<R>::cbrt(q / R(2) + disc);
-    return s - p / (R(3) * s);
+    const R disc = M<R>::sqrt(q * q * R(0.25) + fdiv(p * p * p, R(27)));
+    const R s = M<R>::cbrt(q * R(0.5) + disc);
+    return s - fdiv(p, R(3) * s);
 }
 
 template <class R> __device__ __forceinline__ R sample_mu(int phase, R U, R g) {
@@ -455,11 +460,18 @@ enum : int { kSpecDelta = 0, kSpecGauss = 1, kSpecThermal = 2 };
 enum : int { kFateNone = 0, kFateEscaped = 1, kFateAbsorbed = 2, kFateCapped = 3 };
 enum : int { kRegCavity = 0, kRegGas = 1, kRegOut = 2 };
 
+// Grid cell record (32 B, one aligned half cache line): gas velocity and
+// density, then the temperature and the FP32 line quantities the mixed path
+// uses (thermal speed, Voigt a, line-centre opacity k0 = n_HI sigma0).
+struct CellRec {
+    float4 lo;   // vx, vy, vz, n_HI
+    float4 hi;   // T, v_th, a, k0
+};
+
 struct GridDev {
     int nx, ny, nz, handoff;
     double lo[3], dx[3];
-    const float4* vn;     // (vx, vy, vz, n_HI) per cell, [z][y][x]
-    const float* T;       // temperature per cell
+    const CellRec* rec;   // [z][y][x]
     const double* cdf;    // inclusive prefix of n_HI^2 (CELL_N2 sources)
     double cdf_total;
     uint64_t ncell;

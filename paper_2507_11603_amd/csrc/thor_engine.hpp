@@ -13,6 +13,11 @@
 #pragma once
 #include "thor_device.hpp"
 
+// cells of a grid peel ray whose records are fetched together
+#ifndef THOR_PEEL_LOOKAHEAD
+#define THOR_PEEL_LOOKAHEAD 2
+#endif
+
 namespace thor {
 
 template <class R> struct Pkt {
@@ -55,14 +60,12 @@ template <> __device__ __forceinline__ float sincos2pi<float>(float u, float* c)
 
 // ----------------------------------------------------------------- grid
 template <class R>
-__device__ __forceinline__ void grid_fields(const GridDev& g, const int c[3], Fields<R>& f) {
-    const uint64_t idx = (uint64_t(c[2]) * uint64_t(g.ny) + uint64_t(c[1])) * uint64_t(g.nx) + uint64_t(c[0]);
-    const float4 r = g.vn[idx];
-    f.v[0] = R(r.x); f.v[1] = R(r.y); f.v[2] = R(r.z);
+__device__ __forceinline__ void fields_from_rec(const GridDev& g, const CellRec& r, Fields<R>& f) {
+    f.v[0] = R(r.lo.x); f.v[1] = R(r.lo.y); f.v[2] = R(r.lo.z);
     if constexpr (sizeof(R) == 8) {
-        const double n = double(r.w);
+        const double n = double(r.lo.w);
         if (n > 0.0) {
-            const double T = double(g.T[idx]);
+            const double T = double(r.hi.x);
             const double vth = sqrt(kVth2PerT * T);
             f.vth = vth;
             f.a = kDampTimesVth / vth;
@@ -72,18 +75,30 @@ __device__ __forceinline__ void grid_fields(const GridDev& g, const int c[3], Fi
             f.vth = 1.0; f.a = 0.0; f.k0 = 0.0; f.kd = 0.0;
         }
     } else {
-        const float n = r.w;
+        const float n = r.lo.w;
         if (n > 0.0f) {
-            const float vth = sqrtf(float(kVth2PerT) * g.T[idx]);
-            const float inv = __builtin_amdgcn_rcpf(vth);
-            f.vth = vth;
-            f.a = float(kDampTimesVth) * inv;
-            f.k0 = double(n * (float(kSigma0TimesVth) * inv));
+            f.vth = r.hi.y;
+            f.a = r.hi.z;
+            f.k0 = double(r.hi.w);
             f.kd = g.sigma_d * double(n);
         } else {
             f.vth = 1.0f; f.a = 0.0f; f.k0 = 0.0; f.kd = 0.0;
         }
     }
+}
+
+__device__ __forceinline__ uint64_t cell_index(const GridDev& g, const int c[3]) {
+    return (uint64_t(c[2]) * uint64_t(g.ny) + uint64_t(c[1])) * uint64_t(g.nx) + uint64_t(c[0]);
+}
+
+template <class R>
+__device__ __forceinline__ void grid_fields(const GridDev& g, const int c[3], Fields<R>& f) {
+    fields_from_rec<R>(g, g.rec[cell_index(g, c)], f);
+}
+
+// choose among three values without indexing a private array
+template <class T> __device__ __forceinline__ T sel3(int a, T x, T y, T z) {
+    return a == 0 ? x : (a == 1 ? y : z);
 }
 
 // distance to the next cell face; *mask = axes whose face is hit first.
@@ -260,15 +275,17 @@ __device__ __forceinline__ void cached_fields(const GridDev& g, const int c[3], 
 
 // ----------------------------------------------------------------- peeling
 __device__ __forceinline__ void obs_dir(int axis, double k[3]) {
-    k[0] = k[1] = k[2] = 0.0;
-    k[axis % 3] = axis < 3 ? 1.0 : -1.0;
+    const int a = axis % 3;
+    const double s = axis < 3 ? 1.0 : -1.0;
+    k[0] = a == 0 ? s : 0.0;
+    k[1] = a == 1 ? s : 0.0;
+    k[2] = a == 2 ? s : 0.0;
 }
 
 __device__ __forceinline__ void obs_image(int axis, const double p[3], double* u, double* v) {
     const int a = axis % 3;
-    if (a == 2) { *u = p[0]; *v = p[1]; }
-    else if (a == 0) { *u = p[1]; *v = p[2]; }
-    else { *u = p[2]; *v = p[0]; }
+    *u = sel3(a, p[1], p[2], p[0]);
+    *v = sel3(a, p[2], p[0], p[1]);
 }
 
 __device__ __forceinline__ int bin_of(double v, double lo, double w, int nb) {
@@ -289,29 +306,62 @@ __device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const
     double tau = 0.0;
     bool cut = false;
     if constexpr (GRID) {
+        // the ray runs along axis a; its cells are known in advance, so the
+        // records of up to kLook cells are fetched together
+        constexpr int kLook = THOR_PEEL_LOOKAHEAD;
         const int a = axis % 3;
         const bool pos = axis < 3;
-        const int dims[3] = {g.nx, g.ny, g.nz};
-        int ca = L0.c[a];
-        double pa = L0.p[a];
-        int cell[3] = {L0.c[0], L0.c[1], L0.c[2]};
-        Fields<R> f = f0;
-        for (bool first = true;; first = false) {
-            if (!first) grid_fields<R>(g, cell, f);
-            const double face = pos ? g.lo[a] + double(ca + 1) * g.dx[a] : g.lo[a] + double(ca) * g.dx[a];
+        const int dim = sel3(a, g.nx, g.ny, g.nz);
+        const double lo = sel3(a, g.lo[0], g.lo[1], g.lo[2]);
+        const double dx = sel3(a, g.dx[0], g.dx[1], g.dx[2]);
+        const int64_t stride = (a == 0 ? int64_t(1) : (a == 1 ? int64_t(g.nx) : int64_t(g.nx) * int64_t(g.ny))) *
+                               (pos ? 1 : -1);
+        int ca = sel3(a, L0.c[0], L0.c[1], L0.c[2]);
+        double pa = sel3(a, L0.p[0], L0.p[1], L0.p[2]);
+        int64_t idx = int64_t(cell_index(g, L0.c));
+        // first segment: from the event to the face, fields of the event's cell
+        {
+            const double face = pos ? lo + double(ca + 1) * dx : lo + double(ca) * dx;
             double t = pos ? face - pa : pa - face;
             t = t < 0.0 ? 0.0 : t;
             cnt.peel_visits++;
-            if (f.k0 > 0.0 || f.kd > 0.0) {
-                const R x = (dv_peel - (pos ? f.v[a] : -f.v[a])) / f.vth;
-                const double kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
-                tau += kt * t;
-                if (tau > o.tau_cut) { cut = true; break; }
+            if (f0.k0 > 0.0 || f0.kd > 0.0) {
+                const R va = sel3(a, f0.v[0], f0.v[1], f0.v[2]);
+                const R x = fdiv(dv_peel - (pos ? va : -va), f0.vth);
+                tau += (f0.k0 * double(voigt<R>(f0.a, x)) + f0.kd) * t;
+                cut = tau > o.tau_cut;
             }
             pa = face;
             ca += pos ? 1 : -1;
-            if (ca < 0 || ca >= dims[a]) break;
-            cell[a] = ca;
+            idx += stride;
+        }
+        while (!cut) {
+            const int left = pos ? dim - ca : ca + 1;
+            if (left <= 0) break;
+            const int m = left < kLook ? left : kLook;
+            CellRec r[kLook];
+#pragma unroll
+            for (int j = 0; j < kLook; ++j)
+                if (j < m) r[j] = g.rec[idx + int64_t(j) * stride];
+#pragma unroll
+            for (int j = 0; j < kLook; ++j) {
+                if (j >= m || cut) break;
+                const int cj = ca + (pos ? j : -j);
+                const double face = pos ? lo + double(cj + 1) * dx : lo + double(cj) * dx;
+                const double t = pos ? face - pa : pa - face;
+                cnt.peel_visits++;
+                Fields<R> f;
+                fields_from_rec<R>(g, r[j], f);
+                if (f.k0 > 0.0 || f.kd > 0.0) {
+                    const R va = sel3(a, f.v[0], f.v[1], f.v[2]);
+                    const R x = fdiv(dv_peel - (pos ? va : -va), f.vth);
+                    tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
+                    cut = tau > o.tau_cut;
+                }
+                pa = face;
+            }
+            ca += pos ? m : -m;
+            idx += int64_t(m) * stride;
         }
     } else {
         double kd[3];
@@ -324,7 +374,7 @@ __device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const
             const double t = meshless_query<R>(m, L.p, L.region, k, f, &nr, &cm);
             cnt.peel_visits++;
             if (f.k0 > 0.0 || f.kd > 0.0) {
-                const R x = (dv_peel - dot3<R>(f.v, k)) / f.vth;
+                const R x = fdiv(dv_peel - dot3<R>(f.v, k), f.vth);
                 const double kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
                 if (isinf(t)) { cut = true; break; }
                 tau += kt * t;
@@ -492,7 +542,7 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
         pk.n_dust++;
         cnt.n_dust++;
     } else {
-        const R x = (pk.dv - dot3<R>(f.v, pk.k)) / f.vth;
+        const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
         uint32_t trials = 0;
         const R upar = upar_sample<R>(x, f.a, key, pk.event, &trials);
         cnt.upar_trials += trials;
@@ -595,7 +645,7 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
         cnt.main_visits++;
         double kt = 0.0;
         if (f.k0 > 0.0 || f.kd > 0.0) {
-            const R x = (pk.dv - dot3<R>(f.v, pk.k)) / f.vth;
+            const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
             kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
         }
         if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) {

@@ -123,7 +123,8 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
             while (qtail - qhead >= 64u) peel_drain<R>(g, models[0], o, pq, qbase, qhead, qtail, cnt);
         }
         const bool work = active && used < budget;
-        if (__ballot(work) == 0) {
+        const uint64_t wmask = __ballot(work);
+        if (wmask == 0) {
             if (useq && qtail != qhead) {
                 peel_drain<R>(g, models[0], o, pq, qbase, qhead, qtail, cnt);
                 continue;
@@ -131,12 +132,15 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
             break;
         }
         po.n = 0;
+        // the ring pays off while many lanes march; a few long-lived packets
+        // (the tail) peel inline and run many interactions per turn
+        const bool qnow = useq && __popcll(wmask) > 8;
         if (work) {
             const ModelDev& m = models[pk.model];
             // with the seed ring, one interaction per turn keeps each lane's
             // pending seeds to one event
-            const uint32_t ev_cap = useq ? 1u : budget - used;
-            const int fate = advance<R, GRID>(g, m, o, pk, cnt, turn_visits, ev_cap, &used, useq ? &po : nullptr);
+            const uint32_t ev_cap = qnow ? 1u : budget - used;
+            const int fate = advance<R, GRID>(g, m, o, pk, cnt, turn_visits, ev_cap, &used, qnow ? &po : nullptr);
             if (fate != kFateNone) {
                 finish<R, GRID>(g, m, o, pk, fate, cnt);
                 active = false;
@@ -151,10 +155,11 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
     flush_counters(cnt, gstats);
 }
 
-// Re-layout of the grid fields into (vx, vy, vz, n_HI) records; counts cells
+// Re-layout of the grid fields into 32-byte cell records (see CellRec), with
+// the FP32 line quantities derived in FP64 and rounded once; counts cells
 // that are not finite, have n_HI < 0, or hold gas at T <= 0.
 __global__ void k_pack_grid(const float* __restrict__ n, const float* __restrict__ vx, const float* __restrict__ vy,
-                            const float* __restrict__ vz, const float* __restrict__ T, float4* __restrict__ out,
+                            const float* __restrict__ vz, const float* __restrict__ T, CellRec* __restrict__ out,
                             uint64_t count, unsigned long long* bad) {
     unsigned long long nbad = 0;
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
@@ -164,13 +169,21 @@ __global__ void k_pack_grid(const float* __restrict__ n, const float* __restrict
         const bool ok = isfinite(r.x) && isfinite(r.y) && isfinite(r.z) && isfinite(r.w) && r.w >= 0.0f &&
                         (r.w == 0.0f || (isfinite(t) && t > 0.0f));
         nbad += ok ? 0ull : 1ull;
-        out[i] = r;
+        float4 h = make_float4(t, 1.0f, 0.0f, 0.0f);
+        if (ok && r.w > 0.0f) {
+            const double vth = sqrt(kVth2PerT * double(t));
+            h = make_float4(t, float(vth), float(kDampTimesVth / vth), float(double(r.w) * (kSigma0TimesVth / vth)));
+        }
+        CellRec c;
+        c.lo = r;
+        c.hi = h;
+        out[i] = c;
     }
     if (nbad) atomicAdd(bad, nbad);
 }
 
 struct NSquared {
-    __host__ __device__ double operator()(const float4& r) const { return double(r.w) * double(r.w); }
+    __host__ __device__ double operator()(const CellRec& r) const { return double(r.lo.w) * double(r.lo.w); }
 };
 
 // Device-function harnesses (tests of the kernels' own device code).
@@ -280,8 +293,7 @@ struct thor_ctx {
     bool has_geom = false;
     thor_geometry geom{};
     GridDev grid{};
-    float4* d_vn = nullptr;
-    float* d_T = nullptr;
+    CellRec* d_rec = nullptr;
     double* d_cdf = nullptr;
     uint64_t grid_bytes = 0, cdf_bytes = 0;
 
@@ -662,7 +674,7 @@ void thor_destroy(thor_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    void* ptrs[] = {ctx->d_vn, ctx->d_T, ctx->d_cdf, ctx->d_spec, ctx->d_cube, ctx->d_stats,
+    void* ptrs[] = {ctx->d_rec, ctx->d_cdf, ctx->d_spec, ctx->d_cube, ctx->d_stats,
                     ctx->d_models, ctx->d_batches, ctx->d_rec_dv, ctx->d_rec_nres, ctx->d_rec_ndust,
                     ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done,
                     ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
@@ -700,10 +712,9 @@ thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
             return fail(THOR_E_UNSUPPORTED, "slab supports NONE or LINEAR velocity");
         if (g->tau_d > 0.0 && g->n_HI == 0.0 && g->tau0 == 0.0) return fail(THOR_E_INVAL, "dust needs gas");
         // release a previous grid
-        dfree(ctx, ctx->d_vn, ctx->grid_bytes);
-        dfree(ctx, ctx->d_T, ctx->grid_bytes / 4);
+        dfree(ctx, ctx->d_rec, ctx->grid_bytes);
         dfree(ctx, ctx->d_cdf, ctx->cdf_bytes);
-        ctx->d_vn = nullptr; ctx->d_T = nullptr; ctx->d_cdf = nullptr;
+        ctx->d_rec = nullptr; ctx->d_cdf = nullptr;
         ctx->grid_bytes = ctx->cdf_bytes = 0;
         std::memset(&ctx->grid, 0, sizeof ctx->grid);
         ctx->geom = *g;
@@ -718,48 +729,44 @@ thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
     if (!g->n_HI_field || !g->T_field || !g->vx || !g->vy || !g->vz) return fail(THOR_E_INVAL, "null grid field");
     if (g->mem != THOR_MEM_HOST && g->mem != THOR_MEM_DEVICE) return fail(THOR_E_INVAL, "bad memory kind");
     const uint64_t cells = uint64_t(g->nx) * g->ny * g->nz;
-    const uint64_t need = cells * 16 + cells * 4;
-    const uint64_t staging = g->mem == THOR_MEM_HOST ? cells * 16 : 0;
-    const uint64_t freed = ctx->grid_bytes + ctx->grid_bytes / 4 + ctx->cdf_bytes;
+    const uint64_t need = cells * sizeof(CellRec);
+    const uint64_t staging = g->mem == THOR_MEM_HOST ? cells * 20 : 0;
+    const uint64_t freed = ctx->grid_bytes + ctx->cdf_bytes;
     if (ctx->budget && ctx->used - std::min(ctx->used, freed) + need + staging > ctx->budget)
         return fail(THOR_E_BUDGET, "grid of %llu cells exceeds the HBM budget", (unsigned long long)cells);
-    dfree(ctx, ctx->d_vn, ctx->grid_bytes);
-    dfree(ctx, ctx->d_T, ctx->grid_bytes / 4);
+    dfree(ctx, ctx->d_rec, ctx->grid_bytes);
     dfree(ctx, ctx->d_cdf, ctx->cdf_bytes);
-    ctx->d_vn = nullptr; ctx->d_T = nullptr; ctx->d_cdf = nullptr;
+    ctx->d_rec = nullptr; ctx->d_cdf = nullptr;
     ctx->grid_bytes = ctx->cdf_bytes = 0;
     ctx->has_geom = false;
     ctx->pending.clear();
-    thor_status s = dalloc(ctx, (void**)&ctx->d_vn, cells * 16, "grid records");
+    thor_status s = dalloc(ctx, (void**)&ctx->d_rec, need, "grid records");
     if (s) return s;
-    ctx->grid_bytes = cells * 16;
-    s = dalloc(ctx, (void**)&ctx->d_T, cells * 4, "grid temperature");
-    if (s) return s;
-    const hipMemcpyKind kind = g->mem == THOR_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_T, g->T_field, cells * 4, kind, ctx->stream));
-    const float *n = g->n_HI_field, *vx = g->vx, *vy = g->vy, *vz = g->vz;
+    ctx->grid_bytes = need;
+    const float *n = g->n_HI_field, *vx = g->vx, *vy = g->vy, *vz = g->vz, *T = g->T_field;
     float* stage = nullptr;
     if (g->mem == THOR_MEM_HOST) {
-        s = dalloc(ctx, (void**)&stage, cells * 16, "grid staging");
+        s = dalloc(ctx, (void**)&stage, cells * 20, "grid staging");
         if (s) return s;
+        const hipMemcpyKind kind = hipMemcpyHostToDevice;
         HIPCHK(ctx, hipMemcpyAsync(stage, g->n_HI_field, cells * 4, kind, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(stage + cells, g->vx, cells * 4, kind, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(stage + 2 * cells, g->vy, cells * 4, kind, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(stage + 3 * cells, g->vz, cells * 4, kind, ctx->stream));
-        n = stage; vx = stage + cells; vy = stage + 2 * cells; vz = stage + 3 * cells;
+        HIPCHK(ctx, hipMemcpyAsync(stage + 4 * cells, g->T_field, cells * 4, kind, ctx->stream));
+        n = stage; vx = stage + cells; vy = stage + 2 * cells; vz = stage + 3 * cells; T = stage + 4 * cells;
     }
     HIPCHK(ctx, hipMemsetAsync(ctx->d_stats, 0, 8, ctx->stream));
-    hipLaunchKernelGGL(k_pack_grid, dim3(4096), dim3(256), 0, ctx->stream, n, vx, vy, vz, ctx->d_T, ctx->d_vn,
-                       cells, ctx->d_stats);
+    hipLaunchKernelGGL(k_pack_grid, dim3(4096), dim3(256), 0, ctx->stream, n, vx, vy, vz, T, ctx->d_rec, cells,
+                       ctx->d_stats);
     HIPCHK(ctx, hipGetLastError());
     unsigned long long nbad = 0;
     HIPCHK(ctx, hipMemcpyAsync(&nbad, ctx->d_stats, 8, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    if (stage) dfree(ctx, stage, cells * 16);
+    if (stage) dfree(ctx, stage, cells * 20);
     if (nbad) {
-        dfree(ctx, ctx->d_vn, ctx->grid_bytes);
-        dfree(ctx, ctx->d_T, cells * 4);
-        ctx->d_vn = nullptr; ctx->d_T = nullptr; ctx->grid_bytes = 0;
+        dfree(ctx, ctx->d_rec, ctx->grid_bytes);
+        ctx->d_rec = nullptr; ctx->grid_bytes = 0;
         return fail(THOR_E_INVAL, "%llu grid cells are not finite, have n_HI < 0 or gas at T <= 0", nbad);
     }
     ctx->geom = *g;
@@ -773,8 +780,7 @@ thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
         gd.lo[i] = g->lo[i];
         gd.dx[i] = (g->hi[i] - g->lo[i]) / dims[i];
     }
-    gd.vn = ctx->d_vn;
-    gd.T = ctx->d_T;
+    gd.rec = ctx->d_rec;
     gd.ncell = cells;
     gd.sigma_d = g->sigma_d;
     ctx->has_geom = true;
@@ -799,7 +805,7 @@ thor_status thor_emit(thor_ctx* ctx, const thor_source* src, uint64_t n_packets,
         thor_status s = dalloc(ctx, (void**)&ctx->d_cdf, cells * 8, "emission CDF");
         if (s) return s;
         ctx->cdf_bytes = cells * 8;
-        hipcub::TransformInputIterator<double, NSquared, const float4*> it(ctx->d_vn, NSquared());
+        hipcub::TransformInputIterator<double, NSquared, const CellRec*> it(ctx->d_rec, NSquared());
         size_t tmp_bytes = 0;
         HIPCHK(ctx, hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, it, ctx->d_cdf, (int64_t)cells, ctx->stream));
         void* tmp = nullptr;

@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libthor.so")
+LIB_PATH = os.environ.get("THOR_LIB") or os.path.join(HERE, "libthor.so")
 
 OK, INCOMPLETE = 0, 1
 STATUS = {0: "THOR_OK", 1: "THOR_INCOMPLETE", -1: "THOR_E_INVAL", -2: "THOR_E_NOMEM",

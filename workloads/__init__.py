@@ -89,7 +89,8 @@ def grf(n: int, slope: float, rng: np.random.Generator, dtype=np.float32):
     kz = np.fft.rfftfreq(n, d=1.0 / n).astype(np.float32)
     for i in range(n):   # slab by slab keeps the temporary small
         k2 = kx[i] ** 2 + kx[:, None] ** 2 + kz[None, :] ** 2
-        amp = np.where(k2 > 0, k2 ** (slope / 4.0), 0.0).astype(np.float32)
+        with np.errstate(divide="ignore"):
+            amp = np.where(k2 > 0, k2 ** (slope / 4.0), 0.0).astype(np.float32)
         fk[i] *= amp
     field = sfft.irfftn(fk, s=(n, n, n), workers=-1).astype(dtype, copy=False)
     del fk
@@ -112,6 +113,42 @@ def web_fields(n: int = 1024, sigma_ln: float = 2.0, n_mean: float = 1e-5, slope
         v = grf(n, slope, np.random.default_rng(s))
         v *= np.float32(sigma_v_kms * KMS)
         vel.append(v)
+    return dens, temp, vel[0], vel[1], vel[2]
+
+
+def grf_torch(n: int, slope: float, seed: int, device="cuda"):
+    """Same recipe as `grf` on a HIP device with torch (float32), for the large
+    grids; returns a device tensor [z][y][x]."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    white = torch.randn((n, n, n), generator=g, device=device, dtype=torch.float32)
+    fk = torch.fft.rfftn(white)
+    del white
+    kx = torch.fft.fftfreq(n, d=1.0 / n, device=device, dtype=torch.float32)
+    kz = torch.fft.rfftfreq(n, d=1.0 / n, device=device, dtype=torch.float32)
+    for i in range(n):   # slab by slab keeps the temporary small
+        k2 = kx[i] ** 2 + kx[:, None] ** 2 + kz[None, :] ** 2
+        amp = torch.where(k2 > 0, k2.clamp_min(1e-30) ** (slope / 4.0), torch.zeros_like(k2))
+        fk[i] *= amp
+    field = torch.fft.irfftn(fk, s=(n, n, n))
+    del fk
+    field -= field.mean(dtype=torch.float64).float()
+    field /= field.std().float()
+    return field
+
+
+def web_fields_torch(n: int = 1024, sigma_ln: float = 2.0, n_mean: float = 1e-5, slope: float = -2.5,
+                     sigma_v_kms: float = 100.0, T0: float = 1e4, entropy: int = 2507_11603, device="cuda"):
+    """Device-tensor version of `web_fields` (different random stream, same
+    statistics); used for the 512^3 and 1024^3 boxes."""
+    import torch
+    seeds = [int(s.generate_state(1)[0]) for s in np.random.SeedSequence(entropy).spawn(4)]
+    dens = grf_torch(n, slope, seeds[0], device)
+    dens.mul_(sigma_ln).exp_()
+    dens.mul_(n_mean / dens.mean(dtype=torch.float64).item())
+    temp = torch.sqrt(dens / n_mean).mul_(T0)
+    vel = [grf_torch(n, slope, s, device).mul_(sigma_v_kms * KMS) for s in seeds[1:]]
     return dens, temp, vel[0], vel[1], vel[2]
 
 
