@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--web-grid", type=int, default=0,
                     help="also measure the cosmic-web box at this grid size (fields generated on the GPU)")
     ap.add_argument("--web-packets", type=int, default=100_000)
+    ap.add_argument("--web-fields", default="gpu", choices=["gpu", "cpu"],
+                    help="make the web fields with torch on the GPU or with numpy on the host")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (PMC calibration)")
     return ap.parse_args()
@@ -112,13 +114,14 @@ def web_box(a, kw):
 
     import workloads as W
     from paper_2507_11603_amd import thor
-    f = W.web_fields_torch(a.web_grid)
+    f = W.web_fields_torch(a.web_grid) if a.web_fields == "gpu" else W.web_fields(a.web_grid)
     wl = W.web(n_grid=a.web_grid, fields=f)
     T = thor.Transport(0)
     try:
         T.load(wl["geom"])
         del f, wl["geom"]["n_HI_field"], wl["geom"]["T_field"], wl["geom"]["vx"], wl["geom"]["vy"], wl["geom"]["vz"]
-        torch.cuda.empty_cache()
+        if a.web_fields == "gpu":
+            torch.cuda.empty_cache()
         wkw = {k: v for k, v in kw.items() if k != "visits_per_turn"}
         run_steps(T, wl, a.web_packets // 10, 1, 10**13, **wkw)           # warm-up (CDF, caches)
         dt, st = run_steps(T, wl, a.web_packets, 1, 0, **wkw)

@@ -682,16 +682,20 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
 }
 
 // ----------------------------------------------------------------- peel queue
-// Per-wave ring of peel seeds in global memory (structure of arrays, slots
-// [base, base + kPeelRing)).  Lanes push the seeds of their events at
-// convergent points; when 64 or more are queued, the whole wave marches 64
-// peel rays together, one per lane, instead of one lane at a time.
+// Per-wave ring of peel rays in global memory (structure of arrays, slots
+// [base, base + kPeelRing)).  Lanes push the rays of their events at
+// convergent points; when 64 or more are queued the whole wave marches 64
+// rays together, one per lane, for at most kPeelChunk cells each, and pushes
+// the unfinished ones back, so a few long rays through voids do not hold
+// the other 63 lanes of the wave.
 constexpr uint32_t kPeelRing = 1024;
+constexpr int kPeelChunk = 16;
 
 struct PeelQueue {
-    double* px; double* py; double* pz;
-    int* cx; int* cy; int* cz;
+    double* px; double* py; double* pz;   // event position (image pixel)
+    double* pa; double* tau;              // ray front along its axis, tau so far
     double* w; double* dv;
+    int* cx; int* cy; int* cz;            // cell of the ray front
     int* obs;
 };
 
@@ -701,15 +705,19 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 
 // Wave-uniform tail update; call with the whole wave converged.
 __device__ __forceinline__ void peel_push(const PeelQueue& q, uint64_t base, uint32_t& tail, const PeelOut& po,
-                                          int n_obs) {
+                                          const OutDev& o) {
     const bool has = po.n > 0;
     const uint64_t mask = __ballot(has);
     if (!mask) return;
+    const int n_obs = o.n_obs;
     if (has) {
         const uint32_t first = tail + lane_rank(mask) * uint32_t(n_obs);
         for (int ob = 0; ob < n_obs; ++ob) {
             const uint64_t sl = base + ((first + uint32_t(ob)) & (kPeelRing - 1));
+            const int a = o.obs_axis[ob] % 3;
             q.px[sl] = po.p[0]; q.py[sl] = po.p[1]; q.pz[sl] = po.p[2];
+            q.pa[sl] = sel3(a, po.p[0], po.p[1], po.p[2]);
+            q.tau[sl] = 0.0;
             q.cx[sl] = po.c[0]; q.cy[sl] = po.c[1]; q.cz[sl] = po.c[2];
             q.w[sl] = po.w[ob]; q.dv[sl] = po.dv[ob]; q.obs[sl] = ob;
         }
@@ -717,24 +725,102 @@ __device__ __forceinline__ void peel_push(const PeelQueue& q, uint64_t base, uin
     tail += uint32_t(__popcll(mask)) * uint32_t(n_obs);
 }
 
-// March up to 64 queued peel rays, one per lane; wave converged.
+// One pass over up to 64 queued rays (one per lane, kPeelChunk cells each);
+// wave converged.  Finished rays deposit into the cube, the rest go back.
 template <class R>
-__device__ __forceinline__ void peel_drain(const GridDev& g, const ModelDev& m, const OutDev& o, const PeelQueue& q,
-                                           uint64_t base, uint32_t& head, uint32_t tail, Counters& cnt) {
+__device__ __forceinline__ void peel_drain(const GridDev& g, const OutDev& o, const PeelQueue& q, uint64_t base,
+                                           uint32_t& head, uint32_t& tail, Counters& cnt) {
     const uint32_t avail = tail - head;
     const uint32_t take = avail < 64u ? avail : 64u;
     const uint32_t lane = threadIdx.x & 63;
+    bool more = false;
+    double p[3], pa = 0.0, tau = 0.0, w = 0.0, dvp = 0.0;
+    int c[3], ob = 0;
     if (lane < take) {
         const uint64_t sl = base + ((head + lane) & (kPeelRing - 1));
-        Loc L;
-        L.p[0] = q.px[sl]; L.p[1] = q.py[sl]; L.p[2] = q.pz[sl];
-        L.c[0] = q.cx[sl]; L.c[1] = q.cy[sl]; L.c[2] = q.cz[sl];
-        L.region = kRegGas;
-        Fields<R> f0;
-        grid_fields<R>(g, L.c, f0);
-        peel<R, true>(g, m, o, L, f0, q.obs[sl], q.w[sl], R(q.dv[sl]), cnt);
+        p[0] = q.px[sl]; p[1] = q.py[sl]; p[2] = q.pz[sl];
+        pa = q.pa[sl]; tau = q.tau[sl]; w = q.w[sl]; dvp = q.dv[sl];
+        c[0] = q.cx[sl]; c[1] = q.cy[sl]; c[2] = q.cz[sl];
+        ob = q.obs[sl];
+        const int axis = o.obs_axis[ob];
+        const int a = axis % 3;
+        const bool pos = axis < 3;
+        const int dim = sel3(a, g.nx, g.ny, g.nz);
+        const double lo = sel3(a, g.lo[0], g.lo[1], g.lo[2]);
+        const double dx = sel3(a, g.dx[0], g.dx[1], g.dx[2]);
+        const int64_t stride = (a == 0 ? int64_t(1) : (a == 1 ? int64_t(g.nx) : int64_t(g.nx) * int64_t(g.ny))) *
+                               (pos ? 1 : -1);
+        int ca = sel3(a, c[0], c[1], c[2]);
+        int64_t idx = int64_t(cell_index(g, c));
+        const R dv_peel = R(dvp);
+        bool cut = false, out = false;
+        int done = 0;
+        constexpr int kLook = THOR_PEEL_LOOKAHEAD;
+        while (!cut && done < kPeelChunk) {
+            const int left = pos ? dim - ca : ca + 1;
+            if (left <= 0) { out = true; break; }
+            int m = left < kLook ? left : kLook;
+            m = m < kPeelChunk - done ? m : kPeelChunk - done;
+            CellRec r[kLook];
+#pragma unroll
+            for (int j = 0; j < kLook; ++j)
+                if (j < m) r[j] = g.rec[idx + int64_t(j) * stride];
+#pragma unroll
+            for (int j = 0; j < kLook; ++j) {
+                if (j >= m || cut) break;
+                const int cj = ca + (pos ? j : -j);
+                const double face = pos ? lo + double(cj + 1) * dx : lo + double(cj) * dx;
+                double t = pos ? face - pa : pa - face;
+                t = t < 0.0 ? 0.0 : t;
+                cnt.peel_visits++;
+                Fields<R> f;
+                fields_from_rec<R>(g, r[j], f);
+                if (f.k0 > 0.0 || f.kd > 0.0) {
+                    const R va = sel3(a, f.v[0], f.v[1], f.v[2]);
+                    const R x = fdiv(dv_peel - (pos ? va : -va), f.vth);
+                    tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
+                    cut = tau > o.tau_cut;
+                }
+                pa = face;
+            }
+            ca += pos ? m : -m;
+            idx += int64_t(m) * stride;
+            done += m;
+        }
+        if (!cut && !out) out = pos ? ca >= dim : ca < 0;
+        if (cut) {
+            cnt.peel_cut++;
+        } else if (out) {
+            double u, v;
+            obs_image(axis, p, &u, &v);
+            const int ix = bin_of(u, o.img_lo[0], o.img_w[0], o.cube_nx);
+            const int iy = bin_of(v, o.img_lo[1], o.img_w[1], o.cube_ny);
+            const int ib = bin_of(dvp, o.v_lo, o.v_w, o.cube_nb);
+            if (ix < 0 || iy < 0 || ib < 0) {
+                cnt.peel_dropped++;
+            } else {
+                const uint64_t ci = ((uint64_t(ob) * o.cube_ny + iy) * o.cube_nx + ix) * o.cube_nb + ib;
+                unsafeAtomicAdd(o.cube + ci, float(w * exp(-tau)));
+            }
+        } else {
+            more = true;
+            c[0] = a == 0 ? ca : c[0];
+            c[1] = a == 1 ? ca : c[1];
+            c[2] = a == 2 ? ca : c[2];
+        }
     }
     head += take;
+    const uint64_t mask = __ballot(more);
+    if (mask) {
+        if (more) {
+            const uint64_t sl = base + ((tail + lane_rank(mask)) & (kPeelRing - 1));
+            q.px[sl] = p[0]; q.py[sl] = p[1]; q.pz[sl] = p[2];
+            q.pa[sl] = pa; q.tau[sl] = tau; q.w[sl] = w; q.dv[sl] = dvp;
+            q.cx[sl] = c[0]; q.cy[sl] = c[1]; q.cz[sl] = c[2];
+            q.obs[sl] = ob;
+        }
+        tail += uint32_t(__popcll(mask));
+    }
 }
 
 // ----------------------------------------------------------------- finish

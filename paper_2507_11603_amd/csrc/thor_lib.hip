@@ -119,14 +119,14 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
             }
         }
         if (useq) {
-            peel_push(pq, qbase, qtail, po, o.n_obs);
-            while (qtail - qhead >= 64u) peel_drain<R>(g, models[0], o, pq, qbase, qhead, qtail, cnt);
+            peel_push(pq, qbase, qtail, po, o);
+            while (qtail - qhead >= 64u) peel_drain<R>(g, o, pq, qbase, qhead, qtail, cnt);
         }
         const bool work = active && used < budget;
         const uint64_t wmask = __ballot(work);
         if (wmask == 0) {
             if (useq && qtail != qhead) {
-                peel_drain<R>(g, models[0], o, pq, qbase, qhead, qtail, cnt);
+                peel_drain<R>(g, o, pq, qbase, qhead, qtail, cnt);
                 continue;
             }
             break;
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
                 active = false;
             }
         }
-        if (useq) peel_push(pq, qbase, qtail, po, o.n_obs);
+        if (useq) peel_push(pq, qbase, qtail, po, o);
     }
     if (pool.alive) {
         pool.alive[gid] = active ? 1 : 0;
@@ -575,7 +575,7 @@ thor_status ensure_peel_queue(thor_ctx* ctx, uint64_t waves, PeelQueue* pq) {
         dfree(ctx, ctx->d_pq, ctx->pq_bytes);
         ctx->d_pq = nullptr;
         ctx->pq_slots = ctx->pq_bytes = 0;
-        const uint64_t bytes = slots * (5 * 8 + 4 * 4);
+        const uint64_t bytes = slots * (7 * 8 + 4 * 4);
         thor_status s = dalloc(ctx, &ctx->d_pq, bytes, "peel seed rings");
         if (s) return s;
         ctx->pq_slots = slots;
@@ -586,7 +586,9 @@ thor_status ensure_peel_queue(thor_ctx* ctx, uint64_t waves, PeelQueue* pq) {
     pq->px = reinterpret_cast<double*>(b);
     pq->py = pq->px + n;
     pq->pz = pq->py + n;
-    pq->w = pq->pz + n;
+    pq->pa = pq->pz + n;
+    pq->tau = pq->pa + n;
+    pq->w = pq->tau + n;
     pq->dv = pq->w + n;
     pq->cx = reinterpret_cast<int*>(pq->dv + n);
     pq->cy = pq->cx + n;
