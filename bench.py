@@ -55,6 +55,25 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(a):
+    """HBM-side bytes per launch of the timed kernel from the committed counter
+    record (two rocprofv3 passes, calibrated on a plain copy), or None when the
+    record is missing, was taken on another workload, or the kernel sources have
+    changed since."""
+    from paper_2507_11603_amd import pmc_summary
+    path = os.path.join(ROOT, "profiles", "shell%d_traffic.json" % a.grid)
+    if a.path != "persistent" or a.precision != "mixed" or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != pmc_summary.source_hash():
+        return None
+    per_batch = rec["fetch_bytes_per_batch"] + rec["write_bytes_per_batch"]
+    return {"bytes": per_batch * a.steps, "fetch_bytes": rec["fetch_bytes_per_batch"] * a.steps,
+            "write_bytes": rec["write_bytes_per_batch"] * a.steps,
+            "over_algorithmic": rec["traffic_over_algorithmic"], "record": os.path.relpath(path, ROOT)}
+
+
 def run_steps(T, wl, n, steps, first_id, **kw):
     """Queue `steps` batches of n packets (distinct photon ids) and transport
     them with one thor_transport call: the persistent path runs all batches
@@ -205,11 +224,16 @@ def main():
         "cell_visits_per_s": visits / dt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "launches": 1, "batches_per_launch": a.steps,
                      "kernel": "k_persistent<float,true>" if a.path == "persistent" else "k_plain",
                      "kernel_ms_per_step": tot["kernel_ms"] / a.steps, "upar_trials_per_scattering":
                          tot["upar_trials"] / max(tot["n_res"], 1),
                      "bytes_per_visit": BYTES_PER_VISIT, "visits_per_step": visits / a.steps},
     }
+    tr = measured_traffic(a)
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["bytes"]
+        out["roofline"]["traffic_detail"] = tr
     if a.plain_steps:
         pdt, ptot = run_steps(T, wl, a.packets, a.plain_steps, 2 * 10**12, precision="fp64", path="plain")
         pval = (ptot["n_res"] + ptot["n_dust"]) / pdt
