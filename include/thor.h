@@ -169,8 +169,14 @@ typedef struct {
     int32_t visits_per_turn;    /* PERSISTENT: march segments per lane turn (0 = 256) */
     int32_t use_graph;          /* thor_step: replay one captured hipGraph per step */
     int32_t inline_peel;        /* PERSISTENT: march peel rays in the scattering lane
-                                   instead of the per-wave seed ring */
+                                   instead of the peel-seed pass */
     int32_t records;            /* 1: keep per-packet records of this call */
+    uint64_t seed_slots;        /* PERSISTENT, grid, 1-3 observers: slots (48 B each) of
+                                   the peel-seed buffer; 0 = max(2^26, 128 per lane of
+                                   the launch); at least observers x lanes.  A full
+                                   buffer ends a transport kernel early (packets wait
+                                   in device memory), the peel pass empties it and
+                                   transport resumes. */
 } thor_transport_opts;
 
 /* Counters of one thor_transport call (device counters read back at the end
@@ -183,7 +189,11 @@ typedef struct {
     uint64_t peel_contrib, peel_dropped, peel_cut;
     uint64_t upar_trials;           /* u_parallel proposals */
     double w_escaped, w_absorbed;
-    double kernel_ms;               /* device time of the transport kernels */
+    double kernel_ms;               /* device time of the call (events around all launches) */
+    double transport_ms;            /* of which transport kernels (grid persistent path with
+                                       peel seeds: summed per pass; otherwise = kernel_ms) */
+    double peel_ms;                 /* of which peel-pass kernels */
+    uint64_t passes;                /* transport + peel pass rounds (1 without seeds) */
 } thor_stats;
 
 /* Per-packet record (index = packet id - first id of its batch, batches in

@@ -11,6 +11,8 @@
 // redistribution and the Voigt function in FP32 and marches with the
 // reciprocal direction.
 #pragma once
+#include <type_traits>
+
 #include "thor_device.hpp"
 
 // cells of a grid peel ray whose records are fetched together
@@ -99,6 +101,15 @@ __device__ __forceinline__ void grid_fields(const GridDev& g, const int c[3], Fi
 // choose among three values without indexing a private array
 template <class T> __device__ __forceinline__ T sel3(int a, T x, T y, T z) {
     return a == 0 ? x : (a == 1 ? y : z);
+}
+
+// f(integral_constant<int, i>) for i = 0 .. N-1: per-observer arrays of a
+// lane are then indexed by constants and stay in registers
+template <int N, class F> __device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (N > 0) {
+        static_for<N - 1>(f);
+        f(std::integral_constant<int, N - 1>{});
+    }
 }
 
 // distance to the next cell face; *mask = axes whose face is hit first.
@@ -253,16 +264,42 @@ template <class R> struct CellCache {
     Fields<R> f;
 };
 
-// Peel seeds of one event held by a lane until the wave queues them: the
-// event position and cell, and per observer the weight and peeled frequency.
-constexpr int kMaxQueuedObs = 3;
-struct PeelOut {
-    int n;
-    double p[3];
-    int c[3];
-    double w[kMaxQueuedObs];
-    double dv[kMaxQueuedObs];
+// Peel seeds (the paper's peel-seed buffer, Section 3.4.1).  The transport
+// kernel finishes each peel ray's first segment at the event and writes the
+// rays that go on to a seed buffer in HBM; a separate kernel with a small
+// register footprint (high occupancy) marches them.  Each lane writes into its
+// own run of `chunk` consecutive slots, so it never waits for the rest of its
+// wave between events; runs are claimed for all lanes of a wave that need one
+// with a single atomic.  Slots left unused stay empty (obs < 0) and the pass
+// skips them, clearing every slot it reads.
+struct alignas(16) PeelSeed {
+    int32_t c[3];      // front cell: the cell after the event's cell
+    int32_t obs;       // observer index; -1 marks an empty slot
+    double tau;        // tau of the first segment
+    double dv;         // peeled lab-frame frequency
+    double w;          // weight
+    uint64_t cube;     // cube element the contribution goes to
 };
+static_assert(sizeof(PeelSeed) == 48, "seed layout");
+
+struct SeedBuf {
+    PeelSeed* s;
+    uint64_t cap;                  // slots
+    unsigned long long* count;     // slots claimed this step
+    unsigned long long* parked;    // waves with a lane stopped by a full buffer
+    uint32_t chunk;                // slots a lane claims at a time, >= observers
+};
+
+// observers the seed path serves (more go through the inline march)
+constexpr int kMaxSeedObs = 3;
+
+struct SeedLane {                  // a lane's current run of claimed slots
+    uint64_t cur;
+    uint32_t left;
+};
+
+// default slots per claim: about twenty events of three rays
+constexpr uint32_t kSeedChunk = 64;
 
 template <class R>
 __device__ __forceinline__ void cached_fields(const GridDev& g, const int c[3], CellCache<R>& cc) {
@@ -291,6 +328,20 @@ __device__ __forceinline__ void obs_image(int axis, const double p[3], double* u
 __device__ __forceinline__ int bin_of(double v, double lo, double w, int nb) {
     const double b = floor((v - lo) / w);
     return (b >= 0.0 && b < double(nb)) ? int(b) : -1;
+}
+
+// Contribution weight * exp(-tau) of a finished ray into its observer cube
+// at the pixel of the event position and the bin of the peeled frequency.
+__device__ __forceinline__ void peel_deposit(const OutDev& o, int obs, int axis, const double p[3], double dv_peel,
+                                             double weight, double tau, Counters& cnt) {
+    double u, v;
+    obs_image(axis, p, &u, &v);
+    const int ix = bin_of(u, o.img_lo[0], o.img_w[0], o.cube_nx);
+    const int iy = bin_of(v, o.img_lo[1], o.img_w[1], o.cube_ny);
+    const int ib = bin_of(dv_peel, o.v_lo, o.v_w, o.cube_nb);
+    if (ix < 0 || iy < 0 || ib < 0) { cnt.peel_dropped++; return; }
+    const uint64_t idx = ((uint64_t(obs) * o.cube_ny + iy) * o.cube_nx + ix) * o.cube_nb + ib;
+    unsafeAtomicAdd(o.cube + idx, float(weight * exp(-tau)));
 }
 
 // Peel-off ray (Section 3.4.1): tau along the observer axis from the event,
@@ -389,21 +440,91 @@ __device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const
         }
     }
     if (cut) { cnt.peel_cut++; return; }
+    peel_deposit(o, obs, axis, L0.p, double(dv_peel), weight, tau, cnt);
+}
+
+// First segment of a grid peel ray (from the event to the face of its cell,
+// fields f0 of that cell), the same arithmetic as in `peel`.  Finishes the
+// ray when tau already exceeds the cut or the next cell is outside the grid;
+// otherwise returns true with tau so far, and the rest of the ray is marched
+// from the next cell by the wave (ring or cooperative groups).
+template <class R>
+__device__ __forceinline__ bool peel_first(const GridDev& g, const OutDev& o, const Loc& L0, const Fields<R>& f0,
+                                           int obs, double weight, R dv_peel, Counters& cnt, double* tau_out) {
+    const int axis = o.obs_axis[obs];
+    const int a = axis % 3;
+    const bool pos = axis < 3;
+    cnt.peel_contrib++;
+    cnt.peel_visits++;
+    const int dim = sel3(a, g.nx, g.ny, g.nz);
+    const double lo = sel3(a, g.lo[0], g.lo[1], g.lo[2]);
+    const double dx = sel3(a, g.dx[0], g.dx[1], g.dx[2]);
+    const int ca = sel3(a, L0.c[0], L0.c[1], L0.c[2]);
+    const double pa = sel3(a, L0.p[0], L0.p[1], L0.p[2]);
+    const double face = pos ? lo + double(ca + 1) * dx : lo + double(ca) * dx;
+    double t = pos ? face - pa : pa - face;
+    t = t < 0.0 ? 0.0 : t;
+    double tau = 0.0;
+    if (f0.k0 > 0.0 || f0.kd > 0.0) {
+        const R va = sel3(a, f0.v[0], f0.v[1], f0.v[2]);
+        const R x = fdiv(dv_peel - (pos ? va : -va), f0.vth);
+        tau = (f0.k0 * double(voigt<R>(f0.a, x)) + f0.kd) * t;
+        if (tau > o.tau_cut) { cnt.peel_cut++; return false; }
+    }
+    const int nxt = ca + (pos ? 1 : -1);
+    if (nxt < 0 || nxt >= dim) {
+        peel_deposit(o, obs, axis, L0.p, double(dv_peel), weight, tau, cnt);
+        return false;
+    }
+    *tau_out = tau;
+    return true;
+}
+
+// Cube element of a ray (pixel of the event position, bin of the peeled
+// frequency), or -1 when it falls outside the cube.
+__device__ __forceinline__ int64_t cube_index(const OutDev& o, int obs, int axis, const double p[3], double dv) {
     double u, v;
-    obs_image(axis, L0.p, &u, &v);
+    obs_image(axis, p, &u, &v);
     const int ix = bin_of(u, o.img_lo[0], o.img_w[0], o.cube_nx);
     const int iy = bin_of(v, o.img_lo[1], o.img_w[1], o.cube_ny);
-    const int ib = bin_of(double(dv_peel), o.v_lo, o.v_w, o.cube_nb);
-    if (ix < 0 || iy < 0 || ib < 0) { cnt.peel_dropped++; return; }
-    const uint64_t idx = ((uint64_t(obs) * o.cube_ny + iy) * o.cube_nx + ix) * o.cube_nb + ib;
-    unsafeAtomicAdd(o.cube + idx, float(weight * exp(-tau)));
+    const int ib = bin_of(dv, o.v_lo, o.v_w, o.cube_nb);
+    if (ix < 0 || iy < 0 || ib < 0) return -1;
+    return int64_t(((uint64_t(obs) * o.cube_ny + iy) * o.cube_nx + ix) * o.cube_nb + ib);
+}
+
+// Peel ray `ob` of an event on the seed path: first segment now; a ray that
+// goes on is written to the lane's claimed slots (room for it was checked
+// before the event), unless its pixel or bin lies outside the cube.
+template <class R>
+__device__ __forceinline__ void seed_emit(const GridDev& g, const OutDev& o, const Loc& L, const Fields<R>& f, int ob,
+                                          double weight, R dv_peel, Counters& cnt, const SeedBuf& sb, SeedLane& sl) {
+    double tau;
+    if (!peel_first<R>(g, o, L, f, ob, weight, dv_peel, cnt, &tau)) return;
+    const int axis = o.obs_axis[ob];
+    const int64_t ci = cube_index(o, ob, axis, L.p, double(dv_peel));
+    if (ci < 0) { cnt.peel_dropped++; return; }
+    const int a = axis % 3;
+    const int nx = sel3(a, L.c[0], L.c[1], L.c[2]) + (axis < 3 ? 1 : -1);
+    PeelSeed sd;
+    sd.c[0] = a == 0 ? nx : L.c[0];
+    sd.c[1] = a == 1 ? nx : L.c[1];
+    sd.c[2] = a == 2 ? nx : L.c[2];
+    sd.obs = ob;
+    sd.tau = tau;
+    sd.dv = double(dv_peel);
+    sd.w = weight;
+    sd.cube = uint64_t(ci);
+    sb.s[sl.cur] = sd;
+    ++sl.cur;
+    --sl.left;
 }
 
 // ----------------------------------------------------------------- emission
 // Generator + photon initialisation (Section 3.4 "Emission").
-template <class R, bool GRID>
+// Q: peel rays go to the seed buffer (sb, sl) instead of being marched here.
+template <class R, bool GRID, bool Q = false>
 __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint64_t id, uint64_t q, int model,
-                     Pkt<R>& pk, Counters& cnt, PeelOut* po = nullptr) {
+                     Pkt<R>& pk, Counters& cnt, const SeedBuf* sb = nullptr, SeedLane* sl = nullptr) {
     const Key key{m.seed, m.req, uint32_t(id), uint32_t(id >> 32)};
     pk.id = id; pk.q = q; pk.model = model;
     pk.event = 0; pk.n_res = 0; pk.n_dust = 0;
@@ -476,19 +597,26 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
     }
     cnt.emitted++;
     if (L.region != kRegOut) {
-        if (po) {
-            po->n = o.n_obs;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) { po->p[i] = L.p[i]; po->c[i] = L.c[i]; }
+        if constexpr (GRID && Q) {
+            {
+                static_for<kMaxSeedObs>([&](auto obc) {
+                    constexpr int ob = decltype(obc)::value;
+                    if (ob < o.n_obs) {
+                        double kd[3];
+                        obs_dir(o.obs_axis[ob], kd);
+                        const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+                        const R dvp = (m.spectrum == kSpecThermal) ? dv_loc + dot3<R>(f0.v, ko) : pk.dv;
+                        seed_emit<R>(g, o, L, f0, ob, 1.0 / (4.0 * kPi), dvp, cnt, *sb, *sl);
+                    }
+                });
+            }
         }
-        for (int ob = 0; ob < o.n_obs; ++ob) {
-            double kd[3];
-            obs_dir(o.obs_axis[ob], kd);
-            const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
-            const R dvp = (m.spectrum == kSpecThermal) ? dv_loc + dot3<R>(f0.v, ko) : pk.dv;
-            if (po) {
-                if (ob < kMaxQueuedObs) { po->w[ob] = 1.0 / (4.0 * kPi); po->dv[ob] = double(dvp); }
-            } else {
+        if constexpr (!(GRID && Q)) {
+            for (int ob = 0; ob < o.n_obs; ++ob) {
+                double kd[3];
+                obs_dir(o.obs_axis[ob], kd);
+                const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+                const R dvp = (m.spectrum == kSpecThermal) ? dv_loc + dot3<R>(f0.v, ko) : pk.dv;
                 peel<R, GRID>(g, m, o, L, f0, ob, 1.0 / (4.0 * kPi), dvp, cnt);
             }
         }
@@ -505,10 +633,10 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
 // Dust (Section 2.3.2) or resonant scattering (Sections 2.3.1, 3.4, 3.4.2)
 // at location L in a cell with fields f; kt is the total opacity there.
 // Returns kFateAbsorbed or kFateNone; peels off to every observer.
-template <class R, bool GRID>
+template <class R, bool GRID, bool Q>
 __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk,
                                         const Loc& L, const Fields<R>& f, double kt, const Key& key,
-                                        Counters& cnt, PeelOut* po) {
+                                        Counters& cnt, const SeedBuf* sb, SeedLane* sl) {
     const Uni2<double> dtyp = draw<double>(key, kSlotType, pk.event);
     R kout[3], e1[3], e2[3];
     if (dtyp.a * kt < f.kd) {
@@ -522,21 +650,25 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
         const R sphi = sincos2pi<R>(dm.b, &cphi);
 #pragma unroll
         for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
-        for (int ob = 0; ob < o.n_obs; ++ob) {
-            double kd[3];
-            obs_dir(o.obs_axis[ob], kd);
-            const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
-            const double c = double(phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg))) / (2.0 * kPi);
-            if (po) {
-                if (ob < kMaxQueuedObs) { po->w[ob] = c; po->dv[ob] = double(dvl + dot3<R>(f.v, ko)); }
-            } else {
+        if constexpr (GRID && Q) {
+            static_for<kMaxSeedObs>([&](auto obc) {
+                constexpr int ob = decltype(obc)::value;
+                if (ob < o.n_obs) {
+                    double kd[3];
+                    obs_dir(o.obs_axis[ob], kd);
+                    const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+                    const double c = double(phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg))) / (2.0 * kPi);
+                    seed_emit<R>(g, o, L, f, ob, c, dvl + dot3<R>(f.v, ko), cnt, *sb, *sl);
+                }
+            });
+        } else {
+            for (int ob = 0; ob < o.n_obs; ++ob) {
+                double kd[3];
+                obs_dir(o.obs_axis[ob], kd);
+                const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+                const double c = double(phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg))) / (2.0 * kPi);
                 peel<R, GRID>(g, m, o, L, f, ob, c, dvl + dot3<R>(f.v, ko), cnt);
             }
-        }
-        if (po && o.n_obs) {
-            po->n = o.n_obs;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) { po->p[i] = L.p[i]; po->c[i] = L.c[i]; }
         }
         pk.dv = dvl + dot3<R>(f.v, kout);
         pk.n_dust++;
@@ -567,22 +699,27 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
         const R sphi = sincos2pi<R>(dm.b, &cphi);
 #pragma unroll
         for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
-        for (int ob = 0; ob < o.n_obs; ++ob) {
-            double kd[3];
-            obs_dir(o.obs_axis[ob], kd);
-            const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
-            const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
-            const R xo = x_atom + dot3<R>(u, ko);
-            if (po) {
-                if (ob < kMaxQueuedObs) { po->w[ob] = c; po->dv[ob] = double(xo * f.vth + dot3<R>(f.v, ko)); }
-            } else {
+        if constexpr (GRID && Q) {
+            static_for<kMaxSeedObs>([&](auto obc) {
+                constexpr int ob = decltype(obc)::value;
+                if (ob < o.n_obs) {
+                    double kd[3];
+                    obs_dir(o.obs_axis[ob], kd);
+                    const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+                    const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
+                    const R xo = x_atom + dot3<R>(u, ko);
+                    seed_emit<R>(g, o, L, f, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt, *sb, *sl);
+                }
+            });
+        } else {
+            for (int ob = 0; ob < o.n_obs; ++ob) {
+                double kd[3];
+                obs_dir(o.obs_axis[ob], kd);
+                const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
+                const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
+                const R xo = x_atom + dot3<R>(u, ko);
                 peel<R, GRID>(g, m, o, L, f, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt);
             }
-        }
-        if (po && o.n_obs) {
-            po->n = o.n_obs;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) { po->p[i] = L.p[i]; po->c[i] = L.c[i]; }
         }
         const R x_out = x_atom + dot3<R>(u, kout);
         pk.dv = x_out * f.vth + dot3<R>(f.v, kout);
@@ -608,17 +745,20 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
 // until tau_current = tau_target, then the interaction).  Returns the fate
 // (kFateNone while it lives on); the packet state is complete on return, so
 // a later call resumes it exactly.
-template <class R, bool GRID>
+template <class R, bool GRID, bool Q = false>
 __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt,
-                       uint32_t max_visits, uint32_t max_events, uint32_t* events_done, PeelOut* po = nullptr) {
+                       uint32_t max_visits, uint32_t max_events, uint32_t* events_done,
+                       const SeedBuf* sb = nullptr, SeedLane* sl = nullptr, CellCache<R>* ccp = nullptr) {
     const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
     Loc L;
 #pragma unroll
     for (int i = 0; i < 3; ++i) { L.p[i] = pk.p[i]; L.c[i] = pk.c[i]; }
     L.region = pk.region;
     if (L.region == kRegOut) return kFateEscaped;
-    CellCache<R> cc;
-    cc.valid = false;
+    // the seed path keeps the cell cache across calls (one event per call)
+    CellCache<R> cc_local;
+    cc_local.valid = false;
+    CellCache<R>& cc = Q ? *ccp : cc_local;
     double ik[3];
     auto set_inverse = [&]() {
         if constexpr (sizeof(R) == 4) {
@@ -649,6 +789,11 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
             kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
         }
         if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) {
+            if constexpr (Q) {
+                // no room for this event's rays: end the turn before it (state
+                // unchanged); the wave claims a new run of slots
+                if (sl->left < uint32_t(o.n_obs)) break;
+            }
             // interaction site where tau_current = tau_target along the step
             const double s = (pk.tau_t - pk.tau_a) / kt;
 #pragma unroll
@@ -656,7 +801,7 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
             pk.event++;
             ++ev;
             if (uint64_t(pk.event) > emax) { fate = kFateCapped; break; }
-            fate = interact<R, GRID>(g, m, o, pk, L, f, kt, key, cnt, po);
+            fate = interact<R, GRID, Q>(g, m, o, pk, L, f, kt, key, cnt, sb, sl);
             if (fate != kFateNone) break;
             set_inverse();
             continue;
@@ -681,146 +826,9 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
     return fate;
 }
 
-// ----------------------------------------------------------------- peel queue
-// Per-wave ring of peel rays in global memory (structure of arrays, slots
-// [base, base + kPeelRing)).  Lanes push the rays of their events at
-// convergent points; when 64 or more are queued the whole wave marches 64
-// rays together, one per lane, for at most kPeelChunk cells each, and pushes
-// the unfinished ones back, so a few long rays through voids do not hold
-// the other 63 lanes of the wave.
-constexpr uint32_t kPeelRing = 1024;
-constexpr int kPeelChunk = 16;
-
-struct PeelQueue {
-    double* px; double* py; double* pz;   // event position (image pixel)
-    double* pa; double* tau;              // ray front along its axis, tau so far
-    double* w; double* dv;
-    int* cx; int* cy; int* cz;            // cell of the ray front
-    int* obs;
-};
-
+// ----------------------------------------------------------------- waves
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
-}
-
-// Wave-uniform tail update; call with the whole wave converged.
-__device__ __forceinline__ void peel_push(const PeelQueue& q, uint64_t base, uint32_t& tail, const PeelOut& po,
-                                          const OutDev& o) {
-    const bool has = po.n > 0;
-    const uint64_t mask = __ballot(has);
-    if (!mask) return;
-    const int n_obs = o.n_obs;
-    if (has) {
-        const uint32_t first = tail + lane_rank(mask) * uint32_t(n_obs);
-        for (int ob = 0; ob < n_obs; ++ob) {
-            const uint64_t sl = base + ((first + uint32_t(ob)) & (kPeelRing - 1));
-            const int a = o.obs_axis[ob] % 3;
-            q.px[sl] = po.p[0]; q.py[sl] = po.p[1]; q.pz[sl] = po.p[2];
-            q.pa[sl] = sel3(a, po.p[0], po.p[1], po.p[2]);
-            q.tau[sl] = 0.0;
-            q.cx[sl] = po.c[0]; q.cy[sl] = po.c[1]; q.cz[sl] = po.c[2];
-            q.w[sl] = po.w[ob]; q.dv[sl] = po.dv[ob]; q.obs[sl] = ob;
-        }
-    }
-    tail += uint32_t(__popcll(mask)) * uint32_t(n_obs);
-}
-
-// One pass over up to 64 queued rays (one per lane, kPeelChunk cells each);
-// wave converged.  Finished rays deposit into the cube, the rest go back.
-template <class R>
-__device__ __forceinline__ void peel_drain(const GridDev& g, const OutDev& o, const PeelQueue& q, uint64_t base,
-                                           uint32_t& head, uint32_t& tail, Counters& cnt) {
-    const uint32_t avail = tail - head;
-    const uint32_t take = avail < 64u ? avail : 64u;
-    const uint32_t lane = threadIdx.x & 63;
-    bool more = false;
-    double p[3], pa = 0.0, tau = 0.0, w = 0.0, dvp = 0.0;
-    int c[3], ob = 0;
-    if (lane < take) {
-        const uint64_t sl = base + ((head + lane) & (kPeelRing - 1));
-        p[0] = q.px[sl]; p[1] = q.py[sl]; p[2] = q.pz[sl];
-        pa = q.pa[sl]; tau = q.tau[sl]; w = q.w[sl]; dvp = q.dv[sl];
-        c[0] = q.cx[sl]; c[1] = q.cy[sl]; c[2] = q.cz[sl];
-        ob = q.obs[sl];
-        const int axis = o.obs_axis[ob];
-        const int a = axis % 3;
-        const bool pos = axis < 3;
-        const int dim = sel3(a, g.nx, g.ny, g.nz);
-        const double lo = sel3(a, g.lo[0], g.lo[1], g.lo[2]);
-        const double dx = sel3(a, g.dx[0], g.dx[1], g.dx[2]);
-        const int64_t stride = (a == 0 ? int64_t(1) : (a == 1 ? int64_t(g.nx) : int64_t(g.nx) * int64_t(g.ny))) *
-                               (pos ? 1 : -1);
-        int ca = sel3(a, c[0], c[1], c[2]);
-        int64_t idx = int64_t(cell_index(g, c));
-        const R dv_peel = R(dvp);
-        bool cut = false, out = false;
-        int done = 0;
-        constexpr int kLook = THOR_PEEL_LOOKAHEAD;
-        while (!cut && done < kPeelChunk) {
-            const int left = pos ? dim - ca : ca + 1;
-            if (left <= 0) { out = true; break; }
-            int m = left < kLook ? left : kLook;
-            m = m < kPeelChunk - done ? m : kPeelChunk - done;
-            CellRec r[kLook];
-#pragma unroll
-            for (int j = 0; j < kLook; ++j)
-                if (j < m) r[j] = g.rec[idx + int64_t(j) * stride];
-#pragma unroll
-            for (int j = 0; j < kLook; ++j) {
-                if (j >= m || cut) break;
-                const int cj = ca + (pos ? j : -j);
-                const double face = pos ? lo + double(cj + 1) * dx : lo + double(cj) * dx;
-                double t = pos ? face - pa : pa - face;
-                t = t < 0.0 ? 0.0 : t;
-                cnt.peel_visits++;
-                Fields<R> f;
-                fields_from_rec<R>(g, r[j], f);
-                if (f.k0 > 0.0 || f.kd > 0.0) {
-                    const R va = sel3(a, f.v[0], f.v[1], f.v[2]);
-                    const R x = fdiv(dv_peel - (pos ? va : -va), f.vth);
-                    tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
-                    cut = tau > o.tau_cut;
-                }
-                pa = face;
-            }
-            ca += pos ? m : -m;
-            idx += int64_t(m) * stride;
-            done += m;
-        }
-        if (!cut && !out) out = pos ? ca >= dim : ca < 0;
-        if (cut) {
-            cnt.peel_cut++;
-        } else if (out) {
-            double u, v;
-            obs_image(axis, p, &u, &v);
-            const int ix = bin_of(u, o.img_lo[0], o.img_w[0], o.cube_nx);
-            const int iy = bin_of(v, o.img_lo[1], o.img_w[1], o.cube_ny);
-            const int ib = bin_of(dvp, o.v_lo, o.v_w, o.cube_nb);
-            if (ix < 0 || iy < 0 || ib < 0) {
-                cnt.peel_dropped++;
-            } else {
-                const uint64_t ci = ((uint64_t(ob) * o.cube_ny + iy) * o.cube_nx + ix) * o.cube_nb + ib;
-                unsafeAtomicAdd(o.cube + ci, float(w * exp(-tau)));
-            }
-        } else {
-            more = true;
-            c[0] = a == 0 ? ca : c[0];
-            c[1] = a == 1 ? ca : c[1];
-            c[2] = a == 2 ? ca : c[2];
-        }
-    }
-    head += take;
-    const uint64_t mask = __ballot(more);
-    if (mask) {
-        if (more) {
-            const uint64_t sl = base + ((tail + lane_rank(mask)) & (kPeelRing - 1));
-            q.px[sl] = p[0]; q.py[sl] = p[1]; q.pz[sl] = p[2];
-            q.pa[sl] = pa; q.tau[sl] = tau; q.w[sl] = w; q.dv[sl] = dvp;
-            q.cx[sl] = c[0]; q.cy[sl] = c[1]; q.cz[sl] = c[2];
-            q.obs[sl] = ob;
-        }
-        tail += uint32_t(__popcll(mask));
-    }
 }
 
 // ----------------------------------------------------------------- finish

@@ -64,24 +64,26 @@ __device__ __forceinline__ int find_batch(const BatchDev* b, int nb, uint64_t q)
 // short flights (packets trapped near line centre) make progress at the
 // pace of their neighbours' long flights.  A bounded step (step_events > 0)
 // parks live packets in the pool for the next launch.
-template <class R, bool GRID>
+template <class R, bool GRID, bool SEEDS>
 __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* __restrict__ models,
                                                     const BatchDev* __restrict__ batches,
                                                     const StepDesc* __restrict__ desc,
                                                     unsigned long long* cursor, OutDev o, PoolDev<R> pool,
-                                                    PeelQueue pq, unsigned long long* gstats) {
+                                                    SeedBuf sb, unsigned long long* gstats) {
     const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t q_end = desc->q_end;
     const int nbatch = desc->nbatch;
     const uint32_t step_events = desc->step_events;
     const uint32_t turn_visits = desc->turn_visits;
-    // peel rays of grid media go through the wave's seed ring
-    const bool useq = GRID && pq.px != nullptr && o.n_obs > 0 && o.n_obs <= kMaxQueuedObs;
-    const uint64_t qbase = (gid >> 6) * uint64_t(kPeelRing);
-    uint32_t qhead = 0, qtail = 0;
-    PeelOut po;
+    // peel rays of grid media: first segment at the event, the rest written to
+    // the seed buffer for the peel pass (SEEDS: 1..kMaxSeedObs observers)
+    constexpr bool useq = GRID && SEEDS;
+    SeedLane sl{0, 0};
+    bool stalled = false;          // the seed buffer is full: park and stop
     Counters cnt = {};
     Pkt<R> pk;
+    CellCache<R> cc;
+    cc.valid = false;
     bool active = false;
     if (pool.alive && pool.alive[gid]) {
         pk = pool.pk[gid];
@@ -91,8 +93,36 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
     const uint32_t budget = step_events ? step_events : ~0u;
     uint32_t used = 0;
     for (;;) {
-        po.n = 0;
-        const bool need = !active && !exhausted && used < budget;
+        bool need = !active && !exhausted && !stalled && used < budget;
+        if constexpr (useq) {
+            // once the buffer is full every lane stops at its next turn, so the
+            // launch ends promptly and the peel pass can empty the buffer
+            if (__hip_atomic_load(sb.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= sb.cap) {
+                stalled = true;
+                need = false;
+            }
+            // lanes without room for one more event's rays get a new run of
+            // slots, one atomic for the wave; with the buffer full they stop
+            const bool low = (need || (active && !stalled && used < budget)) && sl.left < uint32_t(o.n_obs);
+            const uint64_t lm = __ballot(low);
+            if (lm) {
+                const int leader = __ffsll((unsigned long long)lm) - 1;
+                unsigned long long base = 0;
+                if (int(threadIdx.x & 63) == leader)
+                    base = atomicAdd(sb.count, (unsigned long long)__popcll(lm) * sb.chunk);
+                base = __shfl(base, leader, 64);
+                if (low) {
+                    const uint64_t mine = base + uint64_t(lane_rank(lm)) * sb.chunk;
+                    if (mine + sb.chunk <= sb.cap) {
+                        sl.cur = mine;
+                        sl.left = sb.chunk;
+                    } else {
+                        stalled = true;
+                        need = false;
+                    }
+                }
+            }
+        }
         const uint64_t mask = __ballot(need);
         if (mask) {
             const int leader = __ffsll((unsigned long long)mask) - 1;
@@ -106,8 +136,9 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
                 if (q < q_end) {
                     const int bi = find_batch(batches, nbatch, q);
                     const BatchDev b = batches[bi];
-                    emit<R, GRID>(g, models[b.model], o, b.first_id + (q - b.q0), q, b.model, pk, cnt,
-                                  useq ? &po : nullptr);
+                    emit<R, GRID, useq>(g, models[b.model], o, b.first_id + (q - b.q0), q, b.model, pk, cnt, &sb,
+                                        &sl);
+                    cc.valid = false;
                     active = true;
                     if (pk.region == kRegOut) {
                         finish<R, GRID>(g, models[b.model], o, pk, kFateEscaped, cnt);
@@ -118,41 +149,139 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
                 }
             }
         }
-        if (useq) {
-            peel_push(pq, qbase, qtail, po, o);
-            while (qtail - qhead >= 64u) peel_drain<R>(g, o, pq, qbase, qhead, qtail, cnt);
-        }
-        const bool work = active && used < budget;
-        const uint64_t wmask = __ballot(work);
-        if (wmask == 0) {
-            if (useq && qtail != qhead) {
-                peel_drain<R>(g, o, pq, qbase, qhead, qtail, cnt);
-                continue;
-            }
-            break;
-        }
-        po.n = 0;
-        // the ring pays off while many lanes march; a few long-lived packets
-        // (the tail) peel inline and run many interactions per turn
-        const bool qnow = useq && __popcll(wmask) > 8;
+        const bool work = active && !stalled && used < budget;
+        if (__ballot(work) == 0) break;
         if (work) {
             const ModelDev& m = models[pk.model];
-            // with the seed ring, one interaction per turn keeps each lane's
-            // pending seeds to one event
-            const uint32_t ev_cap = qnow ? 1u : budget - used;
-            const int fate = advance<R, GRID>(g, m, o, pk, cnt, turn_visits, ev_cap, &used, qnow ? &po : nullptr);
+            const int fate = advance<R, GRID, useq>(g, m, o, pk, cnt, turn_visits, budget - used, &used, &sb, &sl,
+                                                    &cc);
             if (fate != kFateNone) {
                 finish<R, GRID>(g, m, o, pk, fate, cnt);
                 active = false;
             }
         }
-        if (useq) peel_push(pq, qbase, qtail, po, o);
     }
+    if (useq && __ballot(stalled) && (threadIdx.x & 63) == 0) atomicAdd(sb.parked, 1ull);
     if (pool.alive) {
         pool.alive[gid] = active ? 1 : 0;
         if (active) pool.pk[gid] = pk;
     }
     flush_counters(cnt, gstats);
+}
+
+// Peel pass: marches the rays appended by the transport kernel.  Each wave
+// takes chunks of kPassChunk slots from a global counter; a lane whose ray is
+// finished takes the next slot of the chunk (ballot + mbcnt), so lanes keep
+// marching while their neighbours' rays are long.  A ray advances
+// THOR_PEEL_LOOKAHEAD cells per round with their records fetched together;
+// segment lengths and the order of the tau sum are those of the serial march.
+constexpr uint32_t kPassChunk = 1024;
+
+template <class R>
+__global__ __launch_bounds__(256) void k_peel_pass(GridDev g, OutDev o, SeedBuf sb, unsigned long long* work,
+                                                   unsigned long long* gstats) {
+    const uint64_t claimed = *sb.count;
+    const uint64_t n = claimed < sb.cap ? claimed : sb.cap;
+    const int lane = int(threadIdx.x & 63);
+    Counters cnt = {};
+    bool have = false, drained = false;
+    int a = 0, ca = 0, dim = 0;
+    bool pos = true;
+    double lo = 0.0, dx = 0.0, pa = 0.0, tau = 0.0, w = 0.0;
+    int64_t stride = 0, idx = 0;
+    uint64_t ci = 0;
+    R dvp = R(0);
+    uint64_t cur = 0, end = 0;             // the wave's chunk, [cur, end)
+    for (;;) {
+        uint64_t m = __ballot(!have);
+        while (m && !drained) {
+            if (cur >= end) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(work, (unsigned long long)kPassChunk);
+                base = __shfl(base, 0, 64);
+                if (base >= n) { drained = true; break; }
+                cur = base;
+                end = base + kPassChunk < n ? base + kPassChunk : n;
+            }
+            const bool mine = (m >> lane) & 1ull;
+            const uint32_t r = lane_rank(m);
+            const uint64_t room = end - cur;
+            const uint32_t take = uint64_t(__popcll(m)) < room ? uint32_t(__popcll(m)) : uint32_t(room);
+            if (mine && r < take) {
+                PeelSeed* slot = sb.s + (cur + r);
+                const PeelSeed sd = *slot;
+                if (sd.obs >= 0) {
+                    slot->obs = -1;          // the slot is free for the next step
+                    const int axis = sel3(sd.obs, o.obs_axis[0], o.obs_axis[1], o.obs_axis[2]);
+                    a = axis % 3;
+                    pos = axis < 3;
+                    dim = sel3(a, g.nx, g.ny, g.nz);
+                    lo = sel3(a, g.lo[0], g.lo[1], g.lo[2]);
+                    dx = sel3(a, g.dx[0], g.dx[1], g.dx[2]);
+                    stride = (a == 0 ? int64_t(1) : (a == 1 ? int64_t(g.nx) : int64_t(g.nx) * int64_t(g.ny))) *
+                             (pos ? 1 : -1);
+                    ca = sel3(a, sd.c[0], sd.c[1], sd.c[2]);
+                    idx = int64_t(cell_index(g, sd.c));
+                    pa = pos ? lo + double(ca) * dx : lo + double(ca + 1) * dx;   // face shared with the event cell
+                    tau = sd.tau;
+                    w = sd.w;
+                    dvp = R(sd.dv);
+                    ci = sd.cube;
+                    have = true;
+                }
+            }
+            cur += take;
+            m = __ballot(mine && r >= take);
+        }
+        if (__ballot(have) == 0) {
+            if (drained) break;
+            continue;
+        }
+        if (have) {
+            constexpr int kLook = THOR_PEEL_LOOKAHEAD;
+            const int left = pos ? dim - ca : ca + 1;       // >= 1
+            const int mm = left < kLook ? left : kLook;
+            CellRec rc[kLook];
+#pragma unroll
+            for (int j = 0; j < kLook; ++j)
+                if (j < mm) rc[j] = g.rec[idx + int64_t(j) * stride];
+            bool cut = false;
+#pragma unroll
+            for (int j = 0; j < kLook; ++j) {
+                if (j >= mm || cut) break;
+                const int cj = ca + (pos ? j : -j);
+                const double face = pos ? lo + double(cj + 1) * dx : lo + double(cj) * dx;
+                double t = pos ? face - pa : pa - face;
+                t = t < 0.0 ? 0.0 : t;
+                cnt.peel_visits++;
+                Fields<R> f;
+                fields_from_rec<R>(g, rc[j], f);
+                if (f.k0 > 0.0 || f.kd > 0.0) {
+                    const R va = sel3(a, f.v[0], f.v[1], f.v[2]);
+                    const R x = fdiv(dvp - (pos ? va : -va), f.vth);
+                    tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
+                    cut = tau > o.tau_cut;
+                }
+                pa = face;
+            }
+            ca += pos ? mm : -mm;
+            idx += int64_t(mm) * stride;
+            if (cut) {
+                cnt.peel_cut++;
+                have = false;
+            } else if (mm == left) {
+                unsafeAtomicAdd(o.cube + ci, float(w * exp(-tau)));
+                have = false;
+            }
+        }
+    }
+    flush_counters(cnt, gstats);
+}
+
+// Marks every slot of a fresh seed buffer empty.
+__global__ void k_seed_clear(PeelSeed* s, uint64_t n) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        s[i].obs = -1;
 }
 
 // Re-layout of the grid fields into 32-byte cell records (see CellRec), with
@@ -210,6 +339,11 @@ __global__ void k_clamp_cursor(unsigned long long* cursor, const StepDesc* desc)
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
+}
+
+__global__ void k_zero_u32(unsigned* p, uint64_t n) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        p[i] = 0u;
 }
 
 }  // namespace thor
@@ -337,8 +471,12 @@ struct thor_ctx {
     unsigned long long* h_s_done = nullptr;    // pinned mirror of d_done
     unsigned long long* h_s_misc = nullptr;    // pinned: counters then cursor
     hipStream_t cap_stream = nullptr;      // private stream for graph capture
-    void* d_pq = nullptr;                  // peel seed rings
-    uint64_t pq_slots = 0, pq_bytes = 0;
+    PeelSeed* d_seeds = nullptr;           // peel seed buffer of the grid persistent path
+    uint64_t seed_cap = 0;                 // slots
+    unsigned long long* d_seedctl = nullptr;   // claimed slots, parked waves, pass work counter
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;  // per-step split of transport and peel-pass time
+    double split_tr = 0.0, split_pp = 0.0;     // ms of the last call's transport and peel-pass kernels
+    uint64_t split_passes = 0;
     hipGraphExec_t s_graph = nullptr;
     int s_graph_prec = -1, s_graph_grid = 0, s_graph_block = 0;
 
@@ -561,40 +699,44 @@ void launch_plain(thor_ctx* ctx, const BatchDev& b, const OutDev& out) {
 template <class R, bool GRID>
 void launch_persistent(thor_ctx* ctx, hipStream_t stream, int grid, int block, const BatchDev* d_b,
                        const StepDesc* d_desc, unsigned long long* cursor, const OutDev& out,
-                       const ModelDev* d_models, void* pool_pk, int* pool_alive, const PeelQueue& pq) {
+                       const ModelDev* d_models, void* pool_pk, int* pool_alive, const SeedBuf& sb) {
     PoolDev<R> pool{reinterpret_cast<Pkt<R>*>(pool_pk), pool_alive};
-    hipLaunchKernelGGL((k_persistent<R, GRID>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models, d_b,
-                       d_desc, cursor, out, pool, pq, ctx->d_stats);
+    bool seeds = false;
+    if constexpr (GRID) seeds = sb.s != nullptr;
+    if (seeds)
+        hipLaunchKernelGGL((k_persistent<R, GRID, GRID>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
+                           d_b, d_desc, cursor, out, pool, sb, ctx->d_stats);
+    else
+        hipLaunchKernelGGL((k_persistent<R, GRID, false>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
+                           d_b, d_desc, cursor, out, pool, sb, ctx->d_stats);
 }
 
-// Seed rings of the persistent grid path: one ring of kPeelRing slots per
-// resident wave.
-thor_status ensure_peel_queue(thor_ctx* ctx, uint64_t waves, PeelQueue* pq) {
-    const uint64_t slots = waves * kPeelRing;
-    if (ctx->pq_slots < slots) {
-        dfree(ctx, ctx->d_pq, ctx->pq_bytes);
-        ctx->d_pq = nullptr;
-        ctx->pq_slots = ctx->pq_bytes = 0;
-        const uint64_t bytes = slots * (7 * 8 + 4 * 4);
-        thor_status s = dalloc(ctx, &ctx->d_pq, bytes, "peel seed rings");
+// Peel seed buffer of the grid persistent path (slots of 48 B, all empty).
+thor_status ensure_seeds(thor_ctx* ctx, uint64_t slots, SeedBuf* sb) {
+    if (ctx->seed_cap != slots) {
+        dfree(ctx, ctx->d_seeds, ctx->seed_cap * sizeof(PeelSeed));
+        ctx->d_seeds = nullptr;
+        ctx->seed_cap = 0;
+        thor_status s = dalloc(ctx, (void**)&ctx->d_seeds, slots * sizeof(PeelSeed), "peel seed buffer");
         if (s) return s;
-        ctx->pq_slots = slots;
-        ctx->pq_bytes = bytes;
+        ctx->seed_cap = slots;
+        hipLaunchKernelGGL(k_seed_clear, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->d_seeds, slots);
     }
-    char* b = static_cast<char*>(ctx->d_pq);
-    const uint64_t n = ctx->pq_slots;
-    pq->px = reinterpret_cast<double*>(b);
-    pq->py = pq->px + n;
-    pq->pz = pq->py + n;
-    pq->pa = pq->pz + n;
-    pq->tau = pq->pa + n;
-    pq->w = pq->tau + n;
-    pq->dv = pq->w + n;
-    pq->cx = reinterpret_cast<int*>(pq->dv + n);
-    pq->cy = pq->cx + n;
-    pq->cz = pq->cy + n;
-    pq->obs = pq->cz + n;
+    if (!ctx->d_seedctl) {
+        thor_status s = dalloc(ctx, (void**)&ctx->d_seedctl, 4 * 8, "peel seed counters");
+        if (s) return s;
+    }
+    sb->s = ctx->d_seeds;
+    sb->cap = ctx->seed_cap;
+    sb->count = ctx->d_seedctl;
+    sb->parked = ctx->d_seedctl + 1;
     return THOR_OK;
+}
+
+template <class R>
+void launch_peel_pass(thor_ctx* ctx, const OutDev& out, const SeedBuf& sb) {
+    hipLaunchKernelGGL((k_peel_pass<R>), dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
+                       ctx->d_seedctl + 2, ctx->d_stats);
 }
 
 thor_status ensure_pool(thor_ctx* ctx, uint64_t slots, int prec) {
@@ -659,7 +801,8 @@ thor_status thor_create(thor_ctx** out, int hip_device, void* hip_stream, uint64
         hipMemcpyToSymbol(HIP_SYMBOL(c_dawson32), t32, sizeof t32) != hipSuccess)
         s = fail(THOR_E_DEVICE, "Dawson table upload failed");
     if (!s) s = dalloc(ctx, (void**)&ctx->d_stats, (kNumU64Counters + 1) * 8, "counters");
-    if (!s && (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess))
+    if (!s && (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
+               hipEventCreate(&ctx->ev_a) != hipSuccess || hipEventCreate(&ctx->ev_b) != hipSuccess))
         s = fail(THOR_E_DEVICE, "hipEventCreate failed");
     if (!s) s = dalloc(ctx, (void**)&ctx->d_desc, sizeof(StepDesc), "step descriptor");
     if (!s && hipHostMalloc((void**)&ctx->h_desc, sizeof(StepDesc)) != hipSuccess)
@@ -680,7 +823,7 @@ void thor_destroy(thor_ctx* ctx) {
                     ctx->d_models, ctx->d_batches, ctx->d_rec_dv, ctx->d_rec_nres, ctx->d_rec_ndust,
                     ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done,
                     ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
-                    ctx->d_pq};
+                    ctx->d_seeds, ctx->d_seedctl};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& kv : ctx->s_reqs)
@@ -695,6 +838,8 @@ void thor_destroy(thor_ctx* ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
+    if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
     delete ctx;
 }
 
@@ -908,6 +1053,7 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         HIPCHK(ctx, hipMemsetAsync(ctx->d_stats, 0, kNumU64Counters * 8, ctx->stream));
     }
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    ctx->split_passes = 0;
     if (opt->path == THOR_PATH_PLAIN) {
         for (size_t i = 0; i < nb; ++i) {
             if (fp64) grid ? launch_plain<double, true>(ctx, batches[i], out) : launch_plain<double, false>(ctx, batches[i], out);
@@ -924,20 +1070,69 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
             s = ensure_pool(ctx, uint64_t(gsize) * block, opt->precision);
             if (s) return s;
         }
-        void* ppk = bounded ? ctx->d_pool_pk : nullptr;
-        int* pal = bounded ? ctx->d_pool_alive : nullptr;
-        unsigned long long* cur = ctx->d_stats + kNumU64Counters;
-        PeelQueue pq;
-        std::memset(&pq, 0, sizeof pq);
-        if (grid && opt->n_obs > 0 && opt->n_obs <= kMaxQueuedObs && !opt->inline_peel) {
-            s = ensure_peel_queue(ctx, uint64_t(gsize) * block / 64, &pq);
+        SeedBuf sb;
+        std::memset(&sb, 0, sizeof sb);
+        const bool seeds = grid && opt->n_obs > 0 && opt->n_obs <= kMaxSeedObs && !opt->inline_peel;
+        if (seeds) {
+            // default: 2^26 slots (3.2 GB) or two runs of kSeedChunk per lane;
+            // a smaller buffer shrinks the runs, down to one event's rays
+            const uint64_t lanes = uint64_t(gsize) * block;
+            const uint64_t ev_rays = uint64_t(opt->n_obs);
+            const uint64_t slots = opt->seed_slots ? opt->seed_slots
+                                                   : std::max<uint64_t>(uint64_t(1) << 26, lanes * 2 * kSeedChunk);
+            if (slots < lanes * ev_rays)
+                return fail(THOR_E_INVAL, "seed_slots must be at least %llu (observers per lane)",
+                            (unsigned long long)(lanes * ev_rays));
+            s = ensure_seeds(ctx, slots, &sb);
             if (s) return s;
+            sb.chunk = uint32_t(std::max<uint64_t>(ev_rays, std::min<uint64_t>(kSeedChunk, slots / (2 * lanes))));
+            if (!bounded) {
+                // packets wait in the pool while the buffer is full
+                s = ensure_pool(ctx, uint64_t(gsize) * block, opt->precision);
+                if (s) return s;
+            }
         }
-        if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, pq)
-                       : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, pq);
-        else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, pq)
-                  : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, pq);
-        hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, ctx->stream, cur, ctx->d_desc);
+        const bool use_pool = bounded || seeds;
+        void* ppk = use_pool ? ctx->d_pool_pk : nullptr;
+        int* pal = use_pool ? ctx->d_pool_alive : nullptr;
+        if (use_pool && !resuming)    // nothing may be left over from an abandoned bounded run
+            hipLaunchKernelGGL(k_zero_u32, dim3(ctx->num_cu), dim3(256), 0, ctx->stream,
+                               reinterpret_cast<unsigned*>(ctx->d_pool_alive), ctx->pool_slots);
+        unsigned long long* cur = ctx->d_stats + kNumU64Counters;
+        double t_tr = 0.0, t_pp = 0.0;
+        uint64_t passes = 0;
+        for (;;) {
+            if (seeds) {
+                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_seedctl, 4);
+                HIPCHK(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
+            }
+            if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb)
+                           : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb);
+            else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb)
+                      : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb);
+            hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, ctx->stream, cur, ctx->d_desc);
+            if (!seeds) break;
+            HIPCHK(ctx, hipEventRecord(ctx->ev_b, ctx->stream));
+            if (fp64) launch_peel_pass<double>(ctx, out, sb);
+            else launch_peel_pass<float>(ctx, out, sb);
+            HIPCHK(ctx, hipGetLastError());
+            HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+            unsigned long long ctl[4];
+            HIPCHK(ctx, hipMemcpyAsync(ctl, ctx->d_seedctl, sizeof ctl, hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            float ms_tr = 0.0f, ms_pp = 0.0f;
+            HIPCHK(ctx, hipEventElapsedTime(&ms_tr, ctx->ev_a, ctx->ev_b));
+            HIPCHK(ctx, hipEventElapsedTime(&ms_pp, ctx->ev_b, ctx->ev1));
+            t_tr += ms_tr;
+            t_pp += ms_pp;
+            ++passes;
+            if (ctl[1] == 0) break;     // no wave stopped on a full buffer
+        }
+        if (seeds) {
+            ctx->split_tr = t_tr;
+            ctx->split_pp = t_pp;
+            ctx->split_passes = passes;
+        }
     }
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
@@ -946,7 +1141,15 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     float ms = 0.0f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    if (!ctx->split_passes) {       // one kernel type: all device time is transport
+        ctx->split_tr = ms;
+        ctx->split_pp = 0.0;
+        ctx->split_passes = 1;
+    }
     collect_stats(ctx, h, ms, &ctx->last);
+    ctx->last.transport_ms = ctx->split_tr;
+    ctx->last.peel_ms = ctx->split_pp;
+    ctx->last.passes = ctx->split_passes;
     if (out_stats) *out_stats = ctx->last;
     if (bounded) {
         // work left: queue not drained or packets parked in the pool
@@ -1175,14 +1378,14 @@ static void enqueue_serving_step(thor_ctx* ctx, hipStream_t st, int prec, int gs
     out.phase = THOR_PHASE_DIPOLE;
     out.tau_cut = 40.0;
     out.img_w[0] = out.img_w[1] = out.v_w = 1.0;
-    PeelQueue pq;
-    std::memset(&pq, 0, sizeof pq);
+    SeedBuf sb;
+    std::memset(&sb, 0, sizeof sb);
     if (prec == THOR_PREC_FP64)
         launch_persistent<double, false>(ctx, st, gsize, block, ctx->d_s_batches, ctx->d_s_desc, ctx->d_s_cursor, out,
-                                         ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive, pq);
+                                         ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive, sb);
     else
         launch_persistent<float, false>(ctx, st, gsize, block, ctx->d_s_batches, ctx->d_s_desc, ctx->d_s_cursor, out,
-                                        ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive, pq);
+                                        ctx->d_s_models, ctx->d_s_pool, ctx->d_s_alive, sb);
     hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, st, ctx->d_s_cursor, ctx->d_s_desc);
     (void)hipMemcpyAsync(ctx->h_s_done, ctx->d_done, 8ull * kServingMaxModels, hipMemcpyDeviceToHost, st);
     (void)hipMemcpyAsync(ctx->h_s_misc, ctx->d_stats, 8ull * kNumU64Counters, hipMemcpyDeviceToHost, st);

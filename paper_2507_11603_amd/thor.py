@@ -66,7 +66,8 @@ class thor_transport_opts(C.Structure):
                 ("spec_lo", C.c_double), ("spec_hi", C.c_double), ("spec_T_ref", C.c_double),
                 ("tau_cut", C.c_double), ("max_events", C.c_uint64), ("step_events", C.c_uint64),
                 ("waves_per_cu", C.c_int32), ("block", C.c_int32), ("visits_per_turn", C.c_int32),
-                ("use_graph", C.c_int32), ("inline_peel", C.c_int32), ("records", C.c_int32)]
+                ("use_graph", C.c_int32), ("inline_peel", C.c_int32), ("records", C.c_int32),
+                ("seed_slots", C.c_uint64)]
 
 
 STAT_U64 = ("emitted", "escaped", "absorbed", "capped", "handed_off", "n_res", "n_dust",
@@ -75,7 +76,8 @@ STAT_U64 = ("emitted", "escaped", "absorbed", "capped", "handed_off", "n_res", "
 
 class thor_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in STAT_U64] + [
-        ("w_escaped", C.c_double), ("w_absorbed", C.c_double), ("kernel_ms", C.c_double)]
+        ("w_escaped", C.c_double), ("w_absorbed", C.c_double), ("kernel_ms", C.c_double),
+        ("transport_ms", C.c_double), ("peel_ms", C.c_double), ("passes", C.c_uint64)]
 
     def to_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -247,7 +249,7 @@ def make_source(src: dict) -> thor_source:
 
 def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_events=0,
               waves_per_cu=0, block=0, visits_per_turn=0, use_graph=False,
-              inline_peel=False) -> thor_transport_opts:
+              inline_peel=False, seed_slots=0) -> thor_transport_opts:
     o = thor_transport_opts()
     o.precision = PREC[precision]
     o.path = PATH[path]
@@ -276,6 +278,7 @@ def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_ev
     o.use_graph = int(use_graph)
     o.inline_peel = int(inline_peel)
     o.records = int(records)
+    o.seed_slots = int(seed_slots)
     return o
 
 

@@ -198,6 +198,39 @@ def test_shell_grid_chi2(T, shell_case, precision, path):
     assert p > 0.01
 
 
+def test_shell_seed_pass_matches_inline_peel(T, shell_case):
+    """Peel rays through the seed buffer and the peel pass, with a buffer so
+    small that transport stops and resumes many times, against rays marched
+    inline by the scattering lane: identical packet histories, and the same
+    cube up to the order of the float additions (both march each ray's cells
+    in the same order with the same arithmetic).  The two kernels are
+    separate instantiations, so the compiler may fuse multiply-adds
+    differently: final frequencies agree to rounding, not bit for bit."""
+    import torch
+    from paper_2507_11603_amd import thor
+    wl, _ = shell_case
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    _say("shell seed pass vs inline peel (%d CUs)" % n_cu)
+    kw = dict(path="persistent", records=True, waves_per_cu=1)
+    a = thor.run(wl, precision="fp64", inline_peel=True, **kw)
+    b = thor.run(wl, precision="fp64", seed_slots=128 * n_cu, **kw)
+    _say("passes %d, peel visits inline %d seeds %d" % (b["stats"]["passes"], a["stats"]["peel_visits"],
+                                                         b["stats"]["peel_visits"]))
+    assert a["stats"]["passes"] == 1 and b["stats"]["passes"] > 1
+    for k in ("n_res", "n_dust", "fate"):
+        assert np.array_equal(a["records"][k], b["records"][k]), k
+    da, db = a["records"]["dv"], b["records"]["dv"]
+    _say("dv: %d of %d differ, max relative difference %.3g"
+         % (np.count_nonzero(da != db), da.size, np.max(np.abs(da - db) / np.maximum(np.abs(da), 1.0))))
+    assert np.allclose(db, da, rtol=1e-9, atol=1e-3)      # cm/s
+    assert a["stats"]["peel_contrib"] == b["stats"]["peel_contrib"]
+    ca, cb = a["cube"].astype(np.float64), b["cube"].astype(np.float64)
+    assert np.allclose(cb, ca, rtol=1e-5, atol=1e-6 * ca.max())
+    # rays whose pixel is outside the cube are dropped before marching on
+    # the seed path, so it visits no more cells than the inline march
+    assert b["stats"]["peel_visits"] <= a["stats"]["peel_visits"]
+
+
 # ------------------------------------------------------------ edge cases and errors
 def test_edge_cases(T):
     from paper_2507_11603_amd import thor
