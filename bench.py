@@ -50,28 +50,71 @@ def parse():
     ap.add_argument("--web-packets", type=int, default=100_000)
     ap.add_argument("--web-fields", default="gpu", choices=["gpu", "cpu"],
                     help="make the web fields with torch on the GPU or with numpy on the host")
+    ap.add_argument("--web-only", type=int, default=0,
+                    help="measure only the cosmic-web box and print its record (for counter runs)")
+    ap.add_argument("--web-warmup", type=int, default=1, help="untimed web run of a tenth of the packets first")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (PMC calibration)")
     return ap.parse_args()
 
 
-def measured_traffic(a):
-    """HBM-side bytes per launch of the timed kernel from the committed counter
-    record (two rocprofv3 passes, calibrated on a plain copy), or None when the
-    record is missing, was taken on another workload, or the kernel sources have
-    changed since."""
+def kernel_split(st):
+    """Device time and algorithmic cell visits of the two kernels of a call.
+    On the peel-seed path the transport kernel marches the main flights and
+    the first segment of every peel ray (one visit per ray); the peel pass
+    marches the rest.  Otherwise the transport kernel does everything."""
+    seeded = st["peel_ms"] > 0.0
+    tr_visits = st["main_visits"] + (st["peel_contrib"] if seeded else st["peel_visits"])
+    pp_visits = st["peel_visits"] - st["peel_contrib"] if seeded else 0
+    out = {}
+    for name, ms, v in (("transport", st["transport_ms"], tr_visits), ("peel_pass", st["peel_ms"], pp_visits)):
+        ach = BYTES_PER_VISIT * v / (ms / 1e3) / 1e9 if ms > 0 else 0.0
+        out[name] = {"ms": ms, "visits": v, "launches": int(st["passes"]) if (ms > 0 or name == "transport") else 0,
+                     "achieved_GBps": ach, "hbm_frac": ach / HBM_PEAK_GBS}
+    return out
+
+
+def counter_record(name):
+    """The committed counter record for workload `name` (two HBM byte passes
+    calibrated on a plain copy, one VALU pass), or None when it is missing or
+    the kernel sources have changed since it was taken."""
     from paper_2507_11603_amd import pmc_summary
-    path = os.path.join(ROOT, "profiles", "shell%d_traffic.json" % a.grid)
-    if a.path != "persistent" or a.precision != "mixed" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", "%s_counters.json" % name)
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("source_hash") != pmc_summary.source_hash():
         return None
-    per_batch = rec["fetch_bytes_per_batch"] + rec["write_bytes_per_batch"]
-    return {"bytes": per_batch * a.steps, "fetch_bytes": rec["fetch_bytes_per_batch"] * a.steps,
-            "write_bytes": rec["write_bytes_per_batch"] * a.steps,
-            "over_algorithmic": rec["traffic_over_algorithmic"], "record": os.path.relpath(path, ROOT)}
+    rec["path"] = os.path.relpath(path, ROOT)
+    return rec
+
+
+def attach_counters(roof, split, dom, rec, batches):
+    """HBM traffic per launch of the dominant kernel and VALU activity of both
+    kernels from a counter record (per batch there, scaled to this run)."""
+    kname = {"transport": "k_persistent", "peel_pass": "k_peel_pass"}[dom]
+    kr = rec["kernels"].get(kname)
+    if kr and "fetch_bytes_per_batch" in kr and "write_bytes_per_batch" in kr:
+        launches = max(split[dom]["launches"], 1)
+        per_batch = kr["fetch_bytes_per_batch"] + kr["write_bytes_per_batch"]
+        roof["traffic"] = per_batch * batches / launches
+        roof["traffic_over_algorithmic"] = roof["traffic"] / (BYTES_PER_VISIT * split[dom]["visits"] / launches)
+    roof["counters"] = {"record": rec["path"], "kernels": rec["kernels"],
+                        "fetch_scale": rec.get("fetch_scale"), "write_scale": rec.get("write_scale")}
+
+
+def calib_copy(a):
+    """A plain device copy of --calib-copy-mib MiB (reads and writes that many
+    bytes): the reference dispatch that scales the HBM byte counters."""
+    if not a.calib_copy_mib:
+        return
+    import torch
+    x = torch.empty(a.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
 
 
 def run_steps(T, wl, n, steps, first_id, **kw):
@@ -142,19 +185,28 @@ def web_box(a, kw):
         if a.web_fields == "gpu":
             torch.cuda.empty_cache()
         wkw = {k: v for k, v in kw.items() if k != "visits_per_turn"}
-        run_steps(T, wl, a.web_packets // 10, 1, 10**13, **wkw)           # warm-up (CDF, caches)
+        if a.web_warmup:
+            run_steps(T, wl, a.web_packets // 10, 1, 10**13, **wkw)       # warm-up (caches, allocations)
         dt, st = run_steps(T, wl, a.web_packets, 1, 0, **wkw)
     finally:
         T.close()
     visits = st["main_visits"] + st["peel_visits"]
     ks = st["kernel_ms"] / 1e3
     ach = BYTES_PER_VISIT * visits / ks / 1e9
+    split = kernel_split(st)
+    dom = max(split, key=lambda k: split[k]["ms"])
+    roof = {"bound": "hbm", "kernel": dom, "achieved": split[dom]["achieved_GBps"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": split[dom]["hbm_frac"], "traffic": None}
+    rec = counter_record("web%d" % a.web_grid) if (a.path == "persistent" and a.precision == "mixed") else None
+    if rec is not None and rec.get("packets") == a.web_packets:
+        attach_counters(roof, split, dom, rec, 1)
     return {"grid": a.web_grid, "packets": a.web_packets, "seconds": dt, "kernel_ms": st["kernel_ms"],
             "scatterings_per_s": (st["n_res"] + st["n_dust"]) / dt, "packets_per_s": st["emitted"] / dt,
             "main_visits": st["main_visits"], "peel_visits": st["peel_visits"],
-            "cell_visits_per_s": visits / ks,
-            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ach / HBM_PEAK_GBS, "traffic": None}}
+            "cell_visits_per_s": visits / ks, "passes": st["passes"],
+            "path_hbm": {"achieved": ach, "frac": ach / HBM_PEAK_GBS},
+            "kernels": split,
+            "roofline": roof}
 
 
 def main():
@@ -163,6 +215,19 @@ def main():
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if a.web_only:
+        import torch
+
+        from paper_2507_11603_amd import thor
+        if not torch.cuda.is_available():
+            print("no HIP device", file=sys.stderr)
+            sys.exit(1)
+        thor.lib()
+        calib_copy(a)
+        kw = dict(precision=a.precision, path=a.path, waves_per_cu=a.waves_per_cu, block=a.block,
+                  inline_peel=bool(a.inline_peel))
+        print(json.dumps({"web": web_box(a, kw)}), flush=True)
+        return
     import workloads as W
     wl = W.shell(n_grid=a.grid, n_packets=a.packets)
     # the CPU baseline runs first, in forked workers, before anything touches the GPU
@@ -176,12 +241,7 @@ def main():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     thor.lib()
-    if a.calib_copy_mib:
-        x = torch.empty(a.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
+    calib_copy(a)
     T = thor.Transport(0)
     T.load(wl["geom"])
     kw = dict(precision=a.precision, path=a.path, waves_per_cu=a.waves_per_cu, block=a.block,
@@ -198,8 +258,9 @@ def main():
     scat = tot["n_res"] + tot["n_dust"]
     value = scat / dt
     visits = tot["main_visits"] + tot["peel_visits"]
-    kernel_s = tot["kernel_ms"] / 1e3
-    achieved = BYTES_PER_VISIT * visits / a.steps / (kernel_s / a.steps) / 1e9
+    split = kernel_split(tot)
+    dom = max(split, key=lambda k: split[k]["ms"])
+    achieved = split[dom]["achieved_GBps"]
     out = {
         "metric": "photon scatterings/s on 1 MI355X (vs FP64 plain path)",
         "value": value,
@@ -224,16 +285,17 @@ def main():
         "cell_visits_per_s": visits / dt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "launches": 1, "batches_per_launch": a.steps,
-                     "kernel": "k_persistent<float,true>" if a.path == "persistent" else "k_plain",
-                     "kernel_ms_per_step": tot["kernel_ms"] / a.steps, "upar_trials_per_scattering":
-                         tot["upar_trials"] / max(tot["n_res"], 1),
-                     "bytes_per_visit": BYTES_PER_VISIT, "visits_per_step": visits / a.steps},
+                     "kernel": ({"transport": "k_persistent<float,true,true>", "peel_pass": "k_peel_pass<float>"}[dom]
+                                if a.path == "persistent" else "k_plain"),
+                     "launches": split[dom]["launches"], "batches_per_launch": a.steps / max(split[dom]["launches"], 1),
+                     "kernel_ms": split[dom]["ms"], "visits": split[dom]["visits"],
+                     "bytes_per_visit": BYTES_PER_VISIT,
+                     "upar_trials_per_scattering": tot["upar_trials"] / max(tot["n_res"], 1)},
+        "kernels": split,
     }
-    tr = measured_traffic(a)
-    if tr is not None:
-        out["roofline"]["traffic"] = tr["bytes"]
-        out["roofline"]["traffic_detail"] = tr
+    rec = counter_record("shell%d" % a.grid) if (a.path == "persistent" and a.precision == "mixed") else None
+    if rec is not None:
+        attach_counters(out["roofline"], split, dom, rec, a.steps)
     if a.plain_steps:
         pdt, ptot = run_steps(T, wl, a.packets, a.plain_steps, 2 * 10**12, precision="fp64", path="plain")
         pval = (ptot["n_res"] + ptot["n_dust"]) / pdt

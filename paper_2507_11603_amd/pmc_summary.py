@@ -1,18 +1,19 @@
-"""Turn two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) over bench.py into
-the per-batch HBM-side traffic record that bench.py reports as
-`roofline.traffic`.
+"""Turn rocprofv3 counter passes over one bench.py command into the record
+bench.py reports beside its roofline: HBM-side bytes (FETCH_SIZE, WRITE_SIZE)
+and VALU activity (VALUBusy, VALUUtilization, SQ_INSTS_VALU) per kernel and
+per batch.
 
-Both passes must profile the same bench.py command with `--calib-copy-mib M`:
-its first dispatch is then a plain device copy of M MiB, which reads and writes
-exactly M MiB, and the ratio of that to what each counter reports for it is the
-counter's scale factor.  The timed persistent launch is the last dispatch of
-`k_persistent`; its bytes are divided by the number of batches it ran.
+The counter passes must profile the same command, run with `--warmup 0` (so
+every dispatch of a kernel belongs to the timed call) and `--calib-copy-mib
+M`: its first dispatch is a plain device copy of M MiB, which reads and
+writes exactly M MiB, and the ratio of that to what FETCH_SIZE and
+WRITE_SIZE report for it is each counter's scale factor.
 
 The record carries a hash of the kernel sources; bench.py uses it only while
 the hash matches the sources it was built from.
 
-    python -m paper_2507_11603_amd.pmc_summary --fetch DIR_F --write DIR_W \
-        --copy-mib 1024 --batches 3 --visits-per-batch V --out profiles/shell128_traffic.json
+    python -m paper_2507_11603_amd.pmc_summary --fetch DIR --write DIR --valu DIR \\
+        --copy-mib 1024 --batches 3 --out profiles/shell128_counters.json
 """
 from __future__ import annotations
 
@@ -26,6 +27,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/thor_lib.hip", "csrc/thor_engine.hpp", "csrc/thor_device.hpp"]
+KERNELS = ("k_persistent", "k_peel_pass")
 
 
 def source_hash() -> str:
@@ -36,51 +38,79 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def _per_dispatch(d: str):
+def _rows(d: str):
     path = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if not path:
         raise FileNotFoundError("no counter_collection.csv under %s" % d)
-    vals, names = collections.defaultdict(float), {}
     with open(path[0]) as f:
-        for r in csv.DictReader(f):
-            k = int(r["Dispatch_Id"])
-            vals[k] += float(r["Counter_Value"])        # KiB, summed over XCD / instance rows
-            names[k] = r["Kernel_Name"]
+        return list(csv.DictReader(f))
+
+
+def _per_dispatch(rows, counter):
+    vals, names = collections.defaultdict(float), {}
+    for r in rows:
+        if r["Counter_Name"] != counter:
+            continue
+        k = int(r["Dispatch_Id"])
+        vals[k] += float(r["Counter_Value"])        # summed over XCD / instance rows
+        names[k] = r["Kernel_Name"]
     return vals, names
 
 
-def summarise(fetch_dir: str, write_dir: str, copy_mib: int, batches: int, visits_per_batch: float,
-              kernel: str = "k_persistent") -> dict:
-    out = {}
-    for key, d in (("fetch", fetch_dir), ("write", write_dir)):
-        vals, names = _per_dispatch(d)
+def _durations(rows):
+    return {int(r["Dispatch_Id"]): int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows}
+
+
+def summarise(fetch_dir: str, write_dir: str, valu_dir: str | None, copy_mib: int, batches: int,
+              packets: int = 0) -> dict:
+    rec = {"source_hash": source_hash(), "batches": batches, "packets": packets, "kernels": {}}
+    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        vals, names = _per_dispatch(_rows(d), counter)
         first = min(vals)
         if "copy" not in names[first].lower():
             raise ValueError("first dispatch %r is not the calibration copy" % names[first])
         scale = copy_mib * 1024.0 / vals[first]
-        last = max(k for k in vals if kernel in names[k])
-        out[key] = dict(scale=scale, calib_kib=vals[first], dispatch=last, raw_kib=vals[last],
-                        bytes_per_batch=vals[last] * 1024.0 * scale / batches)
-    alg = 20.0 * visits_per_batch
-    return {"source_hash": source_hash(), "kernel": kernel, "batches_in_launch": batches,
-            "fetch_bytes_per_batch": out["fetch"]["bytes_per_batch"],
-            "write_bytes_per_batch": out["write"]["bytes_per_batch"],
-            "algorithmic_bytes_per_batch": alg,
-            "traffic_over_algorithmic": (out["fetch"]["bytes_per_batch"] + out["write"]["bytes_per_batch"]) / alg,
-            "counters": out}
+        rec["%s_scale" % key] = scale
+        for kname in KERNELS:
+            ds = [k for k in vals if kname in names[k]]
+            if not ds:
+                continue
+            kr = rec["kernels"].setdefault(kname, {})
+            kr["launches"] = len(ds)
+            kr["%s_bytes_per_batch" % key] = sum(vals[k] for k in ds) * 1024.0 * scale / batches
+    if valu_dir:
+        rows = _rows(valu_dir)
+        for kname in KERNELS:
+            kr_rows = [r for r in rows if kname in r["Kernel_Name"]]
+            busy, _ = _per_dispatch(kr_rows, "VALUBusy")
+            util, _ = _per_dispatch(kr_rows, "VALUUtilization")
+            insts, _ = _per_dispatch(kr_rows, "SQ_INSTS_VALU")
+            if not insts:
+                continue
+            dur = _durations(kr_rows)
+            kr = rec["kernels"].setdefault(kname, {})
+            # per-dispatch percentages: busy (a share of time) weighted by
+            # duration, lane utilisation (a share per instruction) by instructions
+            t_tot = sum(dur[k] for k in insts)
+            i_tot = sum(insts.values())
+            kr["valu_busy_pct"] = sum(busy.get(k, 0.0) * dur[k] for k in insts) / t_tot if t_tot else 0.0
+            kr["valu_lane_util_pct"] = sum(util.get(k, 0.0) * insts[k] for k in insts) / i_tot if i_tot else 0.0
+            kr["valu_insts_per_batch"] = i_tot / batches
+    return rec
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
+    ap.add_argument("--valu", default=None)
     ap.add_argument("--copy-mib", type=int, required=True)
     ap.add_argument("--batches", type=int, required=True)
-    ap.add_argument("--visits-per-batch", type=float, required=True)
+    ap.add_argument("--packets", type=int, default=0, help="packets per batch")
     ap.add_argument("--command", default="", help="the profiled command, stored with the record")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    rec = summarise(a.fetch, a.write, a.copy_mib, a.batches, a.visits_per_batch)
+    rec = summarise(a.fetch, a.write, a.valu, a.copy_mib, a.batches, a.packets)
     rec["command"] = a.command
     with open(a.out, "w") as f:
         json.dump(rec, f, indent=1)
