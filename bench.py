@@ -285,7 +285,7 @@ def main():
         "cell_visits_per_s": visits / dt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ({"transport": "k_persistent<float,true,true>", "peel_pass": "k_peel_pass<float>"}[dom]
+                     "kernel": ({"transport": "k_persistent<float,true,true>", "peel_pass": "k_peel_pass_f32"}[dom]
                                 if a.path == "persistent" else "k_plain"),
                      "launches": split[dom]["launches"], "batches_per_launch": a.steps / max(split[dom]["launches"], 1),
                      "kernel_ms": split[dom]["ms"], "visits": split[dom]["visits"],

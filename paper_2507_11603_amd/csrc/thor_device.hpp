@@ -468,10 +468,19 @@ struct CellRec {
     float4 hi;   // T, v_th, a, k0
 };
 
+// Peel-march record of one cell for rays along one axis: velocity component
+// on that axis, 1/v_th, k0 and dust opacity (FP32).  One array per axis in
+// pencil order (that axis's index fastest), so consecutive cells of a ray
+// are consecutive in memory; a = A21 lambda0 / (4 pi v_th) comes from 1/v_th.
+struct alignas(16) AxisRec {
+    float v, ivth, k0, kd;
+};
+
 struct GridDev {
     int nx, ny, nz, handoff;
     double lo[3], dx[3];
     const CellRec* rec;   // [z][y][x]
+    const AxisRec* axr[3];   // pencil arrays per axis (built on first use), or null
     const double* cdf;    // inclusive prefix of n_HI^2 (CELL_N2 sources)
     double cdf_total;
     uint64_t ncell;

@@ -178,8 +178,11 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
 constexpr uint32_t kPassChunk = 1024;
 
 template <class R>
-__global__ __launch_bounds__(256) void k_peel_pass(GridDev g, OutDev o, SeedBuf sb, unsigned long long* work,
-                                                   unsigned long long* gstats) {
+__device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, const SeedBuf& sb,
+                                          unsigned long long* work, unsigned long long* gstats) {
+    // FP32 (mixed) rays read the pencil records of their axis: consecutive
+    // cells of a ray are consecutive 16-byte records
+    constexpr bool kAxis = sizeof(R) == 4;
     const uint64_t claimed = *sb.count;
     const uint64_t n = claimed < sb.cap ? claimed : sb.cap;
     const int lane = int(threadIdx.x & 63);
@@ -189,6 +192,7 @@ __global__ __launch_bounds__(256) void k_peel_pass(GridDev g, OutDev o, SeedBuf 
     bool pos = true;
     double lo = 0.0, dx = 0.0, pa = 0.0, tau = 0.0, w = 0.0;
     int64_t stride = 0, idx = 0;
+    const AxisRec* axr = nullptr;
     uint64_t ci = 0;
     R dvp = R(0);
     uint64_t cur = 0, end = 0;             // the wave's chunk, [cur, end)
@@ -218,10 +222,18 @@ __global__ __launch_bounds__(256) void k_peel_pass(GridDev g, OutDev o, SeedBuf 
                     dim = sel3(a, g.nx, g.ny, g.nz);
                     lo = sel3(a, g.lo[0], g.lo[1], g.lo[2]);
                     dx = sel3(a, g.dx[0], g.dx[1], g.dx[2]);
-                    stride = (a == 0 ? int64_t(1) : (a == 1 ? int64_t(g.nx) : int64_t(g.nx) * int64_t(g.ny))) *
-                             (pos ? 1 : -1);
                     ca = sel3(a, sd.c[0], sd.c[1], sd.c[2]);
-                    idx = int64_t(cell_index(g, sd.c));
+                    if constexpr (kAxis) {
+                        const uint64_t x = uint64_t(sd.c[0]), y = uint64_t(sd.c[1]), z = uint64_t(sd.c[2]);
+                        idx = int64_t(a == 0 ? (z * g.ny + y) * g.nx + x
+                                             : (a == 1 ? (z * g.nx + x) * g.ny + y : (y * g.nx + x) * g.nz + z));
+                        stride = pos ? 1 : -1;
+                        axr = sel3(a, g.axr[0], g.axr[1], g.axr[2]);
+                    } else {
+                        idx = int64_t(cell_index(g, sd.c));
+                        stride = (a == 0 ? int64_t(1) : (a == 1 ? int64_t(g.nx) : int64_t(g.nx) * int64_t(g.ny))) *
+                                 (pos ? 1 : -1);
+                    }
                     pa = pos ? lo + double(ca) * dx : lo + double(ca + 1) * dx;   // face shared with the event cell
                     tau = sd.tau;
                     w = sd.w;
@@ -241,28 +253,51 @@ __global__ __launch_bounds__(256) void k_peel_pass(GridDev g, OutDev o, SeedBuf 
             constexpr int kLook = THOR_PEEL_LOOKAHEAD;
             const int left = pos ? dim - ca : ca + 1;       // >= 1
             const int mm = left < kLook ? left : kLook;
-            CellRec rc[kLook];
-#pragma unroll
-            for (int j = 0; j < kLook; ++j)
-                if (j < mm) rc[j] = g.rec[idx + int64_t(j) * stride];
             bool cut = false;
+            if constexpr (kAxis) {
+                AxisRec rc[kLook];
 #pragma unroll
-            for (int j = 0; j < kLook; ++j) {
-                if (j >= mm || cut) break;
-                const int cj = ca + (pos ? j : -j);
-                const double face = pos ? lo + double(cj + 1) * dx : lo + double(cj) * dx;
-                double t = pos ? face - pa : pa - face;
-                t = t < 0.0 ? 0.0 : t;
-                cnt.peel_visits++;
-                Fields<R> f;
-                fields_from_rec<R>(g, rc[j], f);
-                if (f.k0 > 0.0 || f.kd > 0.0) {
-                    const R va = sel3(a, f.v[0], f.v[1], f.v[2]);
-                    const R x = fdiv(dvp - (pos ? va : -va), f.vth);
-                    tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
-                    cut = tau > o.tau_cut;
+                for (int j = 0; j < kLook; ++j)
+                    if (j < mm) rc[j] = axr[idx + int64_t(j) * stride];
+#pragma unroll
+                for (int j = 0; j < kLook; ++j) {
+                    if (j >= mm || cut) break;
+                    const int cj = ca + (pos ? j : -j);
+                    const double face = pos ? lo + double(cj + 1) * dx : lo + double(cj) * dx;
+                    double t = pos ? face - pa : pa - face;
+                    t = t < 0.0 ? 0.0 : t;
+                    cnt.peel_visits++;
+                    if (rc[j].k0 > 0.0f || rc[j].kd > 0.0f) {
+                        const float x = (dvp - (pos ? rc[j].v : -rc[j].v)) * rc[j].ivth;
+                        const float av = float(kDampTimesVth) * rc[j].ivth;
+                        tau += (double(rc[j].k0) * double(voigt32(av, x)) + double(rc[j].kd)) * t;
+                        cut = tau > o.tau_cut;
+                    }
+                    pa = face;
                 }
-                pa = face;
+            } else {
+                CellRec rc[kLook];
+#pragma unroll
+                for (int j = 0; j < kLook; ++j)
+                    if (j < mm) rc[j] = g.rec[idx + int64_t(j) * stride];
+#pragma unroll
+                for (int j = 0; j < kLook; ++j) {
+                    if (j >= mm || cut) break;
+                    const int cj = ca + (pos ? j : -j);
+                    const double face = pos ? lo + double(cj + 1) * dx : lo + double(cj) * dx;
+                    double t = pos ? face - pa : pa - face;
+                    t = t < 0.0 ? 0.0 : t;
+                    cnt.peel_visits++;
+                    Fields<R> f;
+                    fields_from_rec<R>(g, rc[j], f);
+                    if (f.k0 > 0.0 || f.kd > 0.0) {
+                        const R va = sel3(a, f.v[0], f.v[1], f.v[2]);
+                        const R x = fdiv(dvp - (pos ? va : -va), f.vth);
+                        tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
+                        cut = tau > o.tau_cut;
+                    }
+                    pa = face;
+                }
             }
             ca += pos ? mm : -mm;
             idx += int64_t(mm) * stride;
@@ -276,6 +311,17 @@ __global__ __launch_bounds__(256) void k_peel_pass(GridDev g, OutDev o, SeedBuf 
         }
     }
     flush_counters(cnt, gstats);
+}
+
+// FP32 pass: at most 80 VGPRs, six waves per SIMD to hide the gather latency.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+void k_peel_pass_f32(GridDev g, OutDev o, SeedBuf sb, unsigned long long* work, unsigned long long* gstats) {
+    peel_pass<float>(g, o, sb, work, gstats);
+}
+
+__global__ __launch_bounds__(256) void k_peel_pass_f64(GridDev g, OutDev o, SeedBuf sb, unsigned long long* work,
+                                                       unsigned long long* gstats) {
+    peel_pass<double>(g, o, sb, work, gstats);
 }
 
 // Marks every slot of a fresh seed buffer empty.
@@ -309,6 +355,28 @@ __global__ void k_pack_grid(const float* __restrict__ n, const float* __restrict
         out[i] = c;
     }
     if (nbad) atomicAdd(bad, nbad);
+}
+
+// Pencil-order copy of the cell records for rays along `axis`: index with
+// that axis fastest ([z][y][x] for x, [z][x][y] for y, [y][x][z] for z).
+__global__ void k_pack_axis(const CellRec* __restrict__ rec, AxisRec* __restrict__ out, int axis, int nx, int ny,
+                            int nz, double sigma_d, uint64_t count) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
+         i += uint64_t(gridDim.x) * blockDim.x) {
+        const uint64_t x = i % uint64_t(nx), y = (i / uint64_t(nx)) % uint64_t(ny), z = i / (uint64_t(nx) * ny);
+        const CellRec r = rec[i];
+        AxisRec o;
+        o.v = axis == 0 ? r.lo.x : (axis == 1 ? r.lo.y : r.lo.z);
+        if (r.lo.w > 0.0f) {
+            o.ivth = float(1.0 / sqrt(kVth2PerT * double(r.hi.x)));
+            o.k0 = r.hi.w;
+            o.kd = float(sigma_d * double(r.lo.w));
+        } else {
+            o.ivth = 0.0f; o.k0 = 0.0f; o.kd = 0.0f;
+        }
+        const uint64_t j = axis == 0 ? i : (axis == 1 ? (z * nx + x) * ny + y : (y * nx + x) * nz + z);
+        out[j] = o;
+    }
 }
 
 struct NSquared {
@@ -471,6 +539,7 @@ struct thor_ctx {
     unsigned long long* h_s_done = nullptr;    // pinned mirror of d_done
     unsigned long long* h_s_misc = nullptr;    // pinned: counters then cursor
     hipStream_t cap_stream = nullptr;      // private stream for graph capture
+    AxisRec* d_axr[3] = {nullptr, nullptr, nullptr};   // pencil records per axis (mixed peel pass)
     PeelSeed* d_seeds = nullptr;           // peel seed buffer of the grid persistent path
     uint64_t seed_cap = 0;                 // slots
     unsigned long long* d_seedctl = nullptr;   // claimed slots, parked waves, pass work counter
@@ -735,8 +804,12 @@ thor_status ensure_seeds(thor_ctx* ctx, uint64_t slots, SeedBuf* sb) {
 
 template <class R>
 void launch_peel_pass(thor_ctx* ctx, const OutDev& out, const SeedBuf& sb) {
-    hipLaunchKernelGGL((k_peel_pass<R>), dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
-                       ctx->d_seedctl + 2, ctx->d_stats);
+    if constexpr (sizeof(R) == 4)
+        hipLaunchKernelGGL(k_peel_pass_f32, dim3(ctx->num_cu * 6), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
+                           ctx->d_seedctl + 2, ctx->d_stats);
+    else
+        hipLaunchKernelGGL(k_peel_pass_f64, dim3(ctx->num_cu * 4), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
+                           ctx->d_seedctl + 2, ctx->d_stats);
 }
 
 thor_status ensure_pool(thor_ctx* ctx, uint64_t slots, int prec) {
@@ -823,7 +896,7 @@ void thor_destroy(thor_ctx* ctx) {
                     ctx->d_models, ctx->d_batches, ctx->d_rec_dv, ctx->d_rec_nres, ctx->d_rec_ndust,
                     ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done,
                     ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
-                    ctx->d_seeds, ctx->d_seedctl};
+                    ctx->d_seeds, ctx->d_seedctl, ctx->d_axr[0], ctx->d_axr[1], ctx->d_axr[2]};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& kv : ctx->s_reqs)
@@ -843,6 +916,28 @@ void thor_destroy(thor_ctx* ctx) {
     delete ctx;
 }
 
+void free_axis_records(thor_ctx* ctx) {
+    for (int a = 0; a < 3; ++a) {
+        dfree(ctx, ctx->d_axr[a], ctx->grid.ncell * sizeof(AxisRec));
+        ctx->d_axr[a] = nullptr;
+        ctx->grid.axr[a] = nullptr;
+    }
+}
+
+// Pencil records for peel rays along axis a (mixed precision), built once per
+// grid from the cell records; staging, outside the timed transport.
+thor_status ensure_axis_records(thor_ctx* ctx, int a) {
+    if (ctx->d_axr[a]) return THOR_OK;
+    const uint64_t cells = ctx->grid.ncell;
+    thor_status s = dalloc(ctx, (void**)&ctx->d_axr[a], cells * sizeof(AxisRec), "axis records");
+    if (s) return s;
+    hipLaunchKernelGGL(k_pack_axis, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->d_rec, ctx->d_axr[a], a,
+                       ctx->grid.nx, ctx->grid.ny, ctx->grid.nz, ctx->grid.sigma_d, cells);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->grid.axr[a] = ctx->d_axr[a];
+    return THOR_OK;
+}
+
 thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
     CHECK_CTX(ctx);
     if (!g) return fail(THOR_E_INVAL, "null geometry");
@@ -859,6 +954,7 @@ thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
             return fail(THOR_E_UNSUPPORTED, "slab supports NONE or LINEAR velocity");
         if (g->tau_d > 0.0 && g->n_HI == 0.0 && g->tau0 == 0.0) return fail(THOR_E_INVAL, "dust needs gas");
         // release a previous grid
+        free_axis_records(ctx);
         dfree(ctx, ctx->d_rec, ctx->grid_bytes);
         dfree(ctx, ctx->d_cdf, ctx->cdf_bytes);
         ctx->d_rec = nullptr; ctx->d_cdf = nullptr;
@@ -881,6 +977,7 @@ thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
     const uint64_t freed = ctx->grid_bytes + ctx->cdf_bytes;
     if (ctx->budget && ctx->used - std::min(ctx->used, freed) + need + staging > ctx->budget)
         return fail(THOR_E_BUDGET, "grid of %llu cells exceeds the HBM budget", (unsigned long long)cells);
+    free_axis_records(ctx);
     dfree(ctx, ctx->d_rec, ctx->grid_bytes);
     dfree(ctx, ctx->d_cdf, ctx->cdf_bytes);
     ctx->d_rec = nullptr; ctx->d_cdf = nullptr;
@@ -1051,6 +1148,13 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         HIPCHK(ctx, hipMemsetAsync(ctx->d_stats, 0, (kNumU64Counters + 1) * 8, ctx->stream));
     } else {
         HIPCHK(ctx, hipMemsetAsync(ctx->d_stats, 0, kNumU64Counters * 8, ctx->stream));
+    }
+    if (grid && opt->path == THOR_PATH_PERSISTENT && !fp64 && opt->n_obs > 0 && opt->n_obs <= kMaxSeedObs &&
+        !opt->inline_peel) {
+        for (int i = 0; i < opt->n_obs; ++i) {
+            s = ensure_axis_records(ctx, opt->obs_axis[i] % 3);
+            if (s) return s;
+        }
     }
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     ctx->split_passes = 0;
