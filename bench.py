@@ -95,13 +95,13 @@ def attach_counters(roof, split, dom, rec, batches):
     kernels from a counter record (per batch there, scaled to this run)."""
     kname = {"transport": "k_persistent", "peel_pass": "k_peel_pass"}[dom]
     kr = rec["kernels"].get(kname)
-    if kr and "fetch_bytes_per_batch" in kr and "write_bytes_per_batch" in kr:
+    if kr and "read_bytes_per_batch" in kr and "write_bytes_per_batch" in kr:
         launches = max(split[dom]["launches"], 1)
-        per_batch = kr["fetch_bytes_per_batch"] + kr["write_bytes_per_batch"]
+        per_batch = kr["read_bytes_per_batch"] + kr["write_bytes_per_batch"]
         roof["traffic"] = per_batch * batches / launches
         roof["traffic_over_algorithmic"] = roof["traffic"] / (BYTES_PER_VISIT * split[dom]["visits"] / launches)
     roof["counters"] = {"record": rec["path"], "kernels": rec["kernels"],
-                        "fetch_scale": rec.get("fetch_scale"), "write_scale": rec.get("write_scale")}
+                        "read_check": rec.get("read_check"), "write_scale": rec.get("write_scale")}
 
 
 def calib_copy(a):

@@ -15,6 +15,9 @@ HEADERS = [os.path.join(HERE, "csrc", f) for f in ("thor_device.hpp", "thor_engi
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
+    # multiply-adds fused only within one expression: every kernel that
+    # evaluates the same formula rounds it the same way
+    "-ffp-contract=on",
     # packed FP32 instructions are disabled on this target on purpose
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

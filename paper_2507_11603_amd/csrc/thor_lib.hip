@@ -170,12 +170,13 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
 }
 
 // Peel pass: marches the rays appended by the transport kernel.  Each wave
-// takes chunks of kPassChunk slots from a global counter; a lane whose ray is
+// takes chunks of kPassChunk slots from per-XCD counters; a lane whose ray is
 // finished takes the next slot of the chunk (ballot + mbcnt), so lanes keep
 // marching while their neighbours' rays are long.  A ray advances
 // THOR_PEEL_LOOKAHEAD cells per round with their records fetched together;
 // segment lengths and the order of the tau sum are those of the serial march.
 constexpr uint32_t kPassChunk = 1024;
+constexpr uint32_t kXcds = 8;           // accelerator complex dies of an MI355X
 
 template <class R>
 __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, const SeedBuf& sb,
@@ -196,16 +197,30 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
     uint64_t ci = 0;
     R dvp = R(0);
     uint64_t cur = 0, end = 0;             // the wave's chunk, [cur, end)
+    const uint32_t xcd = blockIdx.x % kXcds; // workgroups are dealt round-robin over the XCDs
+    uint32_t part = 0;
     for (;;) {
         uint64_t m = __ballot(!have);
         while (m && !drained) {
             if (cur >= end) {
-                unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd(work, (unsigned long long)kPassChunk);
-                base = __shfl(base, 0, 64);
-                if (base >= n) { drained = true; break; }
-                cur = base;
-                end = base + kPassChunk < n ? base + kPassChunk : n;
+                // the buffer is split in kXcds contiguous parts; waves take chunks
+                // of their own XCD's part first (seeds written by one lane are
+                // consecutive, so its rays' cells stay in that XCD's L2), then
+                // help the other parts
+                for (;;) {
+                    const uint32_t x = (xcd + part) % kXcds;
+                    const uint64_t p_lo = n * x / kXcds, p_hi = n * (x + 1) / kXcds;
+                    unsigned long long base = 0;
+                    if (lane == 0) base = atomicAdd(work + x, (unsigned long long)kPassChunk);
+                    base = __shfl(base, 0, 64) + p_lo;
+                    if (base < p_hi) {
+                        cur = base;
+                        end = base + kPassChunk < p_hi ? base + kPassChunk : p_hi;
+                        break;
+                    }
+                    if (++part == kXcds) { drained = true; break; }
+                }
+                if (drained) break;
             }
             const bool mine = (m >> lane) & 1ull;
             const uint32_t r = lane_rank(m);
@@ -542,7 +557,7 @@ struct thor_ctx {
     AxisRec* d_axr[3] = {nullptr, nullptr, nullptr};   // pencil records per axis (mixed peel pass)
     PeelSeed* d_seeds = nullptr;           // peel seed buffer of the grid persistent path
     uint64_t seed_cap = 0;                 // slots
-    unsigned long long* d_seedctl = nullptr;   // claimed slots, parked waves, pass work counter
+    unsigned long long* d_seedctl = nullptr;   // claimed slots, parked waves, then kXcds pass work counters
     hipEvent_t ev_a = nullptr, ev_b = nullptr;  // per-step split of transport and peel-pass time
     double split_tr = 0.0, split_pp = 0.0;     // ms of the last call's transport and peel-pass kernels
     uint64_t split_passes = 0;
@@ -792,7 +807,7 @@ thor_status ensure_seeds(thor_ctx* ctx, uint64_t slots, SeedBuf* sb) {
         hipLaunchKernelGGL(k_seed_clear, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->d_seeds, slots);
     }
     if (!ctx->d_seedctl) {
-        thor_status s = dalloc(ctx, (void**)&ctx->d_seedctl, 4 * 8, "peel seed counters");
+        thor_status s = dalloc(ctx, (void**)&ctx->d_seedctl, (2 + kXcds) * 8, "peel seed counters");
         if (s) return s;
     }
     sb->s = ctx->d_seeds;
@@ -1207,7 +1222,7 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         uint64_t passes = 0;
         for (;;) {
             if (seeds) {
-                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_seedctl, 4);
+                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_seedctl, 2 + kXcds);
                 HIPCHK(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
             }
             if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb)

@@ -1,18 +1,21 @@
 """Turn rocprofv3 counter passes over one bench.py command into the record
-bench.py reports beside its roofline: HBM-side bytes (FETCH_SIZE, WRITE_SIZE)
-and VALU activity (VALUBusy, VALUUtilization, SQ_INSTS_VALU) per kernel and
-per batch.
+bench.py reports beside its roofline: bytes the L2 caches read from and
+write to the memory fabric, and VALU activity (VALUBusy, VALUUtilization,
+SQ_INSTS_VALU), per kernel and per batch.
 
-The counter passes must profile the same command, run with `--warmup 0` (so
-every dispatch of a kernel belongs to the timed call) and `--calib-copy-mib
-M`: its first dispatch is a plain device copy of M MiB, which reads and
-writes exactly M MiB, and the ratio of that to what FETCH_SIZE and
-WRITE_SIZE report for it is each counter's scale factor.
+Reads are counted from the L2 read requests by size (TCC_EA0_RDREQ_32B,
+_64B, _128B): bytes = 32 n32 + 64 n64 + 128 n128.  (The derived FETCH_SIZE
+counts a 128-byte request as 64 bytes, so it reports half of a streaming
+copy.)  Writes come from WRITE_SIZE.  The passes must profile the same
+command, run with `--warmup 0` (so every dispatch of a kernel belongs to the
+timed call) and `--calib-copy-mib M`: the first dispatch is then a plain
+device copy of M MiB, which reads and writes exactly M MiB; the record keeps
+what the counters report for it as a check (read) and a scale (write).
 
 The record carries a hash of the kernel sources; bench.py uses it only while
 the hash matches the sources it was built from.
 
-    python -m paper_2507_11603_amd.pmc_summary --fetch DIR --write DIR --valu DIR \\
+    python -m paper_2507_11603_amd.pmc_summary --reads DIR --write DIR --valu DIR \\
         --copy-mib 1024 --batches 3 --out profiles/shell128_counters.json
 """
 from __future__ import annotations
@@ -61,23 +64,48 @@ def _durations(rows):
     return {int(r["Dispatch_Id"]): int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows}
 
 
-def summarise(fetch_dir: str, write_dir: str, valu_dir: str | None, copy_mib: int, batches: int,
-              packets: int = 0) -> dict:
+def summarise(reads_dir: str, write_dir: str, valu_dir: str | None, copy_mib: int, batches: int,
+              packets: int = 0, hits_dir: str | None = None) -> dict:
     rec = {"source_hash": source_hash(), "batches": batches, "packets": packets, "kernels": {}}
-    for key, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
-        vals, names = _per_dispatch(_rows(d), counter)
-        first = min(vals)
-        if "copy" not in names[first].lower():
-            raise ValueError("first dispatch %r is not the calibration copy" % names[first])
-        scale = copy_mib * 1024.0 / vals[first]
-        rec["%s_scale" % key] = scale
-        for kname in KERNELS:
-            ds = [k for k in vals if kname in names[k]]
-            if not ds:
-                continue
+    # reads: request counts by size
+    rows = _rows(reads_dir)
+    per = {sz: _per_dispatch(rows, "TCC_EA0_RDREQ_%dB" % sz) for sz in (32, 64, 128)}
+    names = per[128][1]
+    rbytes = collections.defaultdict(float)
+    for sz, (vals, _) in per.items():
+        for k, v in vals.items():
+            rbytes[k] += sz * v
+    first = min(rbytes)
+    if "copy" not in names[first].lower():
+        raise ValueError("first dispatch %r is not the calibration copy" % names[first])
+    rec["read_check"] = rbytes[first] / (copy_mib * 2.0 ** 20)     # 1.0: the copy reads what it copies
+    for kname in KERNELS:
+        ds = [k for k in rbytes if kname in names[k]]
+        if ds:
             kr = rec["kernels"].setdefault(kname, {})
             kr["launches"] = len(ds)
-            kr["%s_bytes_per_batch" % key] = sum(vals[k] for k in ds) * 1024.0 * scale / batches
+            kr["read_bytes_per_batch"] = sum(rbytes[k] for k in ds) / batches
+    # writes: WRITE_SIZE (KiB), scaled by the copy
+    vals, names = _per_dispatch(_rows(write_dir), "WRITE_SIZE")
+    first = min(vals)
+    if "copy" not in names[first].lower():
+        raise ValueError("first dispatch %r is not the calibration copy" % names[first])
+    scale = copy_mib * 1024.0 / vals[first]
+    rec["write_scale"] = scale
+    for kname in KERNELS:
+        ds = [k for k in vals if kname in names[k]]
+        if ds:
+            kr = rec["kernels"].setdefault(kname, {})
+            kr["write_bytes_per_batch"] = sum(vals[k] for k in ds) * 1024.0 * scale / batches
+    if hits_dir:
+        rows = _rows(hits_dir)
+        for kname in KERNELS:
+            kr_rows = [r for r in rows if kname in r["Kernel_Name"]]
+            hit, _ = _per_dispatch(kr_rows, "TCC_HIT")
+            miss, _ = _per_dispatch(kr_rows, "TCC_MISS")
+            h, m = sum(hit.values()), sum(miss.values())
+            if h + m > 0:
+                rec["kernels"].setdefault(kname, {})["l2_hit_pct"] = 100.0 * h / (h + m)
     if valu_dir:
         rows = _rows(valu_dir)
         for kname in KERNELS:
@@ -101,16 +129,17 @@ def summarise(fetch_dir: str, write_dir: str, valu_dir: str | None, copy_mib: in
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--valu", default=None)
+    ap.add_argument("--reads", required=True, help="pass with TCC_EA0_RDREQ_32B/_64B/_128B")
+    ap.add_argument("--write", required=True, help="pass with WRITE_SIZE")
+    ap.add_argument("--valu", default=None, help="pass with VALUBusy VALUUtilization SQ_INSTS_VALU")
+    ap.add_argument("--hits", default=None, help="pass with TCC_HIT TCC_MISS")
     ap.add_argument("--copy-mib", type=int, required=True)
     ap.add_argument("--batches", type=int, required=True)
     ap.add_argument("--packets", type=int, default=0, help="packets per batch")
     ap.add_argument("--command", default="", help="the profiled command, stored with the record")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    rec = summarise(a.fetch, a.write, a.valu, a.copy_mib, a.batches, a.packets)
+    rec = summarise(a.reads, a.write, a.valu, a.copy_mib, a.batches, a.packets, a.hits)
     rec["command"] = a.command
     with open(a.out, "w") as f:
         json.dump(rec, f, indent=1)

@@ -46,6 +46,32 @@ def test_web_same_seed(web64):
     assert abs(gpu["cube"].sum() / ref["cube"].sum() - 1) < 0.01
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_web_seed_pass_matches_inline_peel(web64, precision):
+    """Three observers (+x, +y, +z): peel rays through the seed buffer and the
+    peel pass (FP32 rays read the per-axis pencil records) against rays
+    marched inline by the scattering lane, on the same packets.  Histories are
+    identical; FP64 cubes agree to the order of float additions, FP32 cubes to
+    the rounding of the pencil records' derived quantities."""
+    import torch
+    from paper_2507_11603_amd import thor
+    wl, _ = web64
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    _say("web seed pass vs inline peel, %s" % precision)
+    kw = dict(n=3000, precision=precision, path="persistent", records=True, waves_per_cu=1)
+    a = thor.run(wl, inline_peel=True, **kw)
+    b = thor.run(wl, seed_slots=3 * 128 * n_cu, **kw)
+    assert b["stats"]["passes"] > 1
+    for k in ("n_res", "n_dust", "fate"):
+        assert np.array_equal(a["records"][k], b["records"][k]), k
+    ca, cb = a["cube"].astype(np.float64), b["cube"].astype(np.float64)
+    rel = np.abs(cb - ca).sum() / ca.sum()
+    _say("passes %d; cube L1 relative difference %.3g; per observer sums %s vs %s"
+         % (b["stats"]["passes"], rel, cb.sum(axis=(1, 2, 3)), ca.sum(axis=(1, 2, 3))))
+    tol = 1e-5 if precision == "fp64" else 1e-4
+    assert np.allclose(cb, ca, rtol=tol, atol=tol * ca.max())
+
+
 @pytest.mark.parametrize("precision,path", [("fp64", "persistent"), ("mixed", "persistent")])
 def test_web_chi2(web64, precision, path):
     from paper_2507_11603_amd import thor
