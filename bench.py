@@ -198,7 +198,8 @@ def web_box(a, kw):
     roof = {"bound": "hbm", "kernel": dom, "achieved": split[dom]["achieved_GBps"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": split[dom]["hbm_frac"], "traffic": None}
     rec = counter_record("web%d" % a.web_grid) if (a.path == "persistent" and a.precision == "mixed") else None
-    if rec is not None and rec.get("packets") == a.web_packets:
+    # the counter record was taken on the numpy-built fields (no torch kernels under the profiler)
+    if rec is not None and rec.get("packets") == a.web_packets and a.web_fields == "cpu":
         attach_counters(roof, split, dom, rec, 1)
     return {"grid": a.web_grid, "packets": a.web_packets, "seconds": dt, "kernel_ms": st["kernel_ms"],
             "scatterings_per_s": (st["n_res"] + st["n_dust"]) / dt, "packets_per_s": st["emitted"] / dt,
