@@ -28,7 +28,7 @@ BYTES_PER_VISIT = 20.0         # (vx, vy, vz, n_HI, T) float32 per cell visit
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=int, default=1_000_000)
     ap.add_argument("--grid", type=int, default=128)
@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--serving", type=int, default=300, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serving-warmup", type=int, default=60)
     ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--serving-step-events", type=int, default=4096,
+                    help="interactions per lane per serving step (longer steps: fewer launches and host syncs)")
     ap.add_argument("--web-grid", type=int, default=0,
                     help="also measure the cosmic-web box at this grid size (fields generated on the GPU)")
     ap.add_argument("--web-packets", type=int, default=100_000)
@@ -154,7 +156,7 @@ def serving(a, kw):
     import workloads as W
     from paper_2507_11603_amd import serve
     stream = W.request_stream(a.serving + a.serving_warmup, rate_hz=a.serving_rate)
-    srv = serve.ShellServer(precision=a.precision, step_events=64,
+    srv = serve.ShellServer(precision=a.precision, step_events=a.serving_step_events,
                             waves_per_cu=kw.get("waves_per_cu", 0), visits_per_turn=kw.get("visits_per_turn", 0))
     try:
         r = srv.run_stream(stream, warmup=a.serving_warmup)
@@ -166,7 +168,8 @@ def serving(a, kw):
             "p50_ms": r["p50_s"] * 1e3, "p99_ms": r["p99_s"] * 1e3,
             "offered_packets_per_s": pk / span, "sustained_packets_per_s": pk / r["wall_s"],
             "sustained_scatterings_per_s": r["scatterings"] / r["wall_s"], "wall_s": r["wall_s"],
-            "steps": r["steps"], "budget_deferrals": r["deferrals"], "graph_steps": True}
+            "steps": r["steps"], "step_events": a.serving_step_events, "budget_deferrals": r["deferrals"],
+            "graph_steps": True}
 
 
 def web_box(a, kw):

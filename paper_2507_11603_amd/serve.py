@@ -36,7 +36,7 @@ def make_request(N_HI: float, v_exp_kms: float, tau_d: float, n_packets: int, re
 
 class ShellServer:
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, precision: str = "mixed",
-                 step_events: int = 64, waves_per_cu: int = 0, visits_per_turn: int = 0,
+                 step_events: int = 4096, waves_per_cu: int = 0, visits_per_turn: int = 0,
                  use_graph: bool = True):
         import torch
         self.stream = torch.cuda.current_stream(torch.device("cuda", device))
