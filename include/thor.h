@@ -177,6 +177,13 @@ typedef struct {
                                    buffer ends a transport kernel early (packets wait
                                    in device memory), the peel pass empties it and
                                    transport resumes. */
+    int32_t wide_lanes;         /* PERSISTENT, step_events = 0: once the queue is drained, a
+                                   wave holding at most this many live packets hands them
+                                   to a tail kernel that runs each in a wave of its own,
+                                   its idle lanes evaluating the random draws of the
+                                   packet's next events ahead (same results; a shorter
+                                   serial chain for the packets that end a launch);
+                                   0 = 8, negative = never, at most 16 */
 } thor_transport_opts;
 
 /* Counters of one thor_transport call (device counters read back at the end

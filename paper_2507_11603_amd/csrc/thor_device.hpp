@@ -257,9 +257,19 @@ constexpr double kUparSwitch = 2.25;
 // Hard bound on proposals (never reached for finite x, a > 0: the expected
 // count is below 10); keeps a non-finite input from spinning a lane forever.
 constexpr uint32_t kUparMaxTrials = 1u << 20;
+// The first kPreUpar u_par slots (kSlotUpar ...) may be drawn ahead of the
+// event (the draws depend only on the key, the slot and the event number).
+constexpr uint32_t kPreUpar = 4;
+
+template <class R>
+__device__ __forceinline__ Uni2<R> upar_draw(const Key& key, uint32_t slot, uint32_t event, const Uni2<R>* pre) {
+    const uint32_t j = slot - kSlotUpar;
+    if (pre && j < kPreUpar) return pre[j];
+    return draw<R>(key, slot, event);
+}
 
 __device__ __forceinline__ double upar_sample64(double x, double a, const Key& key, uint32_t event,
-                                                uint32_t* trials) {
+                                                uint32_t* trials, const Uni2<double>* pre) {
     const double xa = fabs(x);
     const double sgn = x < 0.0 ? -1.0 : 1.0;
     uint32_t n = 0;
@@ -278,7 +288,7 @@ __device__ __forceinline__ double upar_sample64(double x, double a, const Key& k
         const double m = p1 + e0 * (kPi / 2 - th0);
         for (;;) {
             if (n >= kUparMaxTrials) break;
-            const Uni2<double> r12 = draw<double>(key, kSlotUpar + 2u * n, event);
+            const Uni2<double> r12 = upar_draw<double>(key, kSlotUpar + 2u * n, event, pre);
             ++n;
             const double r = r12.a * m;
             if (r < p1) {
@@ -302,10 +312,10 @@ __device__ __forceinline__ double upar_sample64(double x, double a, const Key& k
         const double zb = e0 * (kPi / 2 - th0) / a;
         for (;;) {
             if (n >= kUparMaxTrials) break;
-            const Uni2<double> r12 = draw<double>(key, kSlotUpar + 2u * n, event);
+            const Uni2<double> r12 = upar_draw<double>(key, kSlotUpar + 2u * n, event, pre);
             const double r = r12.a * (za + zb);
             if (r < za) {
-                const Uni2<double> r34 = draw<double>(key, kSlotUpar + 2u * n + 1u, event);
+                const Uni2<double> r34 = upar_draw<double>(key, kSlotUpar + 2u * n + 1u, event, pre);
                 ++n;
                 double cs, sn;
                 sincos(2.0 * kPi * r34.b, &sn, &cs);
@@ -327,7 +337,7 @@ __device__ __forceinline__ double upar_sample64(double x, double a, const Key& k
 }
 
 __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key, uint32_t event,
-                                               uint32_t* trials) {
+                                               uint32_t* trials, const Uni2<float>* pre) {
     const float xa = fabsf(x);
     const float sgn = x < 0.0f ? -1.0f : 1.0f;
     constexpr float pi = float(kPi), hpi = float(kPi / 2);
@@ -348,7 +358,7 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
         const float m = fmaf(e0, q2, p1);
         for (;;) {
             if (n >= kUparMaxTrials) break;
-            const Uni2<float> r12 = draw<float>(key, kSlotUpar + 2u * n, event);
+            const Uni2<float> r12 = upar_draw<float>(key, kSlotUpar + 2u * n, event, pre);
             ++n;
             const float r = r12.a * m;
             if (r < p1) {
@@ -378,10 +388,10 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
         const float zb = __fdividef(e0 * q2, a);
         for (;;) {
             if (n >= kUparMaxTrials) break;
-            const Uni2<float> r12 = draw<float>(key, kSlotUpar + 2u * n, event);
+            const Uni2<float> r12 = upar_draw<float>(key, kSlotUpar + 2u * n, event, pre);
             const float r = r12.a * (za + zb);
             if (r < za) {
-                const Uni2<float> r34 = draw<float>(key, kSlotUpar + 2u * n + 1u, event);
+                const Uni2<float> r34 = upar_draw<float>(key, kSlotUpar + 2u * n + 1u, event, pre);
                 ++n;
                 float sn, cs;
                 sincospif(2.0f * r34.b, &sn, &cs);
@@ -402,12 +412,17 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
     return sgn * u;
 }
 
-template <class R> __device__ __forceinline__ R upar_sample(R x, R a, const Key& k, uint32_t e, uint32_t* t);
-template <> __device__ __forceinline__ double upar_sample<double>(double x, double a, const Key& k, uint32_t e, uint32_t* t) {
-    return upar_sample64(x, a, k, e, t);
+template <class R>
+__device__ __forceinline__ R upar_sample(R x, R a, const Key& k, uint32_t e, uint32_t* t, const Uni2<R>* pre = nullptr);
+template <>
+__device__ __forceinline__ double upar_sample<double>(double x, double a, const Key& k, uint32_t e, uint32_t* t,
+                                                      const Uni2<double>* pre) {
+    return upar_sample64(x, a, k, e, t, pre);
 }
-template <> __device__ __forceinline__ float upar_sample<float>(float x, float a, const Key& k, uint32_t e, uint32_t* t) {
-    return upar_sample32(x, a, k, e, t);
+template <>
+__device__ __forceinline__ float upar_sample<float>(float x, float a, const Key& k, uint32_t e, uint32_t* t,
+                                                    const Uni2<float>* pre) {
+    return upar_sample32(x, a, k, e, t, pre);
 }
 
 // ---------------------------------------------------------------------------
@@ -516,7 +531,7 @@ struct StepDesc {
     int nbatch;
     uint32_t step_events;  // 0 = run to completion
     uint32_t turn_visits;
-    uint32_t pad;
+    uint32_t wide;         // wide turns at or below this many live lanes (0 = never)
 };
 
 struct OutDev {

@@ -519,6 +519,52 @@ __device__ __forceinline__ void seed_emit(const GridDev& g, const OutDev& o, con
     --sl.left;
 }
 
+// ----------------------------------------------------------------- event draws
+// Quantities of interaction `event` that depend only on the packet's key and
+// the event number (the counter-based draws, Section 3.4.3), not on its
+// state: a wave with few live packets evaluates them for the packets' next
+// events on its idle lanes.  The inline path and the precomputation call the
+// same functions below, so both give the same bits.
+template <class R> __device__ __forceinline__ double tau_target(const Uni2<double>& d) {
+    return sizeof(R) == 8 ? -log(1.0 - d.a) : double(-__logf(float(1.0 - d.a)));
+}
+template <class R> __device__ __forceinline__ R sin_of_cos(R mu) { return M<R>::sqrt(fmax(R(0), R(1) - mu * mu)); }
+template <class R> __device__ __forceinline__ R uperp_rho2(R u) { return -M<R>::log(R(1) - u); }
+
+template <class R> struct EventDraws {
+    Uni2<double> typ;       // interaction choice, albedo
+    double tau_t;           // optical depth target of the next flight
+    R mu_hg, s_hg;          // dust: Henyey-Greenstein mu, sqrt(1 - mu^2)
+    R mu_ph, s_ph;          // resonant: the phase function of the run
+    R mu_dp, s_dp;          // resonant, core/wing mix outside the core: dipole
+    R cphi, sphi;           // azimuth of the new direction
+    R rho2, cps, sps;       // u_perp: radius^2 before core skipping, its angle
+    Uni2<R> up[kPreUpar];   // first u_par proposals
+};
+
+template <class R>
+__device__ __forceinline__ void event_draws(const Key& key, uint32_t event, int phase, R g_hg, EventDraws<R>& d) {
+    d.typ = draw<double>(key, kSlotType, event);
+    const Uni2<R> dm = draw<R>(key, kSlotMu, event);
+    d.mu_hg = sample_mu<R>(kPhaseHG, dm.a, g_hg);
+    d.s_hg = sin_of_cos<R>(d.mu_hg);
+    d.mu_ph = sample_mu<R>(phase, dm.a, R(0));
+    d.s_ph = sin_of_cos<R>(d.mu_ph);
+    d.mu_dp = d.mu_ph;
+    d.s_dp = d.s_ph;
+    if (phase == kPhaseCoreWing) {
+        d.mu_dp = sample_mu<R>(kPhaseDipole, dm.a, R(0));
+        d.s_dp = sin_of_cos<R>(d.mu_dp);
+    }
+    d.sphi = sincos2pi<R>(dm.b, &d.cphi);
+    const Uni2<R> dp = draw<R>(key, kSlotUperp, event);
+    d.rho2 = uperp_rho2<R>(dp.a);
+    d.sps = sincos2pi<R>(dp.b, &d.cps);
+    d.tau_t = tau_target<R>(draw<double>(key, kSlotTau, event));
+#pragma unroll
+    for (uint32_t j = 0; j < kPreUpar; ++j) d.up[j] = draw<R>(key, kSlotUpar + j, event);
+}
+
 // ----------------------------------------------------------------- emission
 // Generator + photon initialisation (Section 3.4 "Emission").
 // Q: peel rays go to the seed buffer (sb, sl) instead of being marched here.
@@ -622,7 +668,7 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
         }
     }
     const Uni2<double> dt = draw<double>(key, kSlotETau, 0);
-    pk.tau_t = sizeof(R) == 8 ? -log(1.0 - dt.a) : double(-__logf(float(1.0 - dt.a)));
+    pk.tau_t = tau_target<R>(dt);
     pk.tau_a = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) { pk.p[i] = L.p[i]; pk.c[i] = L.c[i]; }
@@ -632,22 +678,29 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
 // ----------------------------------------------------------------- interaction
 // Dust (Section 2.3.2) or resonant scattering (Sections 2.3.1, 3.4, 3.4.2)
 // at location L in a cell with fields f; kt is the total opacity there.
-// Returns kFateAbsorbed or kFateNone; peels off to every observer.
-template <class R, bool GRID, bool Q>
+// Returns kFateAbsorbed or kFateNone; peels off to every observer.  PRE:
+// `pre` holds this event's draws evaluated ahead (event_draws).
+template <class R, bool GRID, bool Q, bool PRE = false>
 __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk,
                                         const Loc& L, const Fields<R>& f, double kt, const Key& key,
-                                        Counters& cnt, const SeedBuf* sb, SeedLane* sl) {
-    const Uni2<double> dtyp = draw<double>(key, kSlotType, pk.event);
+                                        Counters& cnt, const SeedBuf* sb, SeedLane* sl,
+                                        const EventDraws<R>* pre = nullptr) {
+    Uni2<double> dtyp;
+    if constexpr (PRE) dtyp = pre->typ; else dtyp = draw<double>(key, kSlotType, pk.event);
     R kout[3], e1[3], e2[3];
     if (dtyp.a * kt < f.kd) {
         if (dtyp.b >= m.albedo) return kFateAbsorbed;
-        const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
-        const R mu = sample_mu<R>(kPhaseHG, dm.a, R(m.g_hg));
+        R mu, s_, cphi, sphi;
+        if constexpr (PRE) {
+            mu = pre->mu_hg; s_ = pre->s_hg; cphi = pre->cphi; sphi = pre->sphi;
+        } else {
+            const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
+            mu = sample_mu<R>(kPhaseHG, dm.a, R(m.g_hg));
+            s_ = sin_of_cos<R>(mu);
+            sphi = sincos2pi<R>(dm.b, &cphi);
+        }
         const R dvl = pk.dv - dot3<R>(f.v, pk.k);
         onb<R>(pk.k, e1, e2);
-        const R s_ = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
-        R cphi;
-        const R sphi = sincos2pi<R>(dm.b, &cphi);
 #pragma unroll
         for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
         if constexpr (GRID && Q) {
@@ -676,14 +729,18 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
     } else {
         const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
         uint32_t trials = 0;
-        const R upar = upar_sample<R>(x, f.a, key, pk.event, &trials);
+        const R upar = upar_sample<R>(x, f.a, key, pk.event, &trials, PRE ? pre->up : nullptr);
         cnt.upar_trials += trials;
-        const Uni2<R> dp = draw<R>(key, kSlotUperp, pk.event);
-        R rho2 = -M<R>::log(R(1) - dp.a);
+        R rho2, cps, sps;
+        if constexpr (PRE) {
+            rho2 = pre->rho2; cps = pre->cps; sps = pre->sps;
+        } else {
+            const Uni2<R> dp = draw<R>(key, kSlotUperp, pk.event);
+            rho2 = uperp_rho2<R>(dp.a);
+            sps = sincos2pi<R>(dp.b, &cps);
+        }
         if (m.xcrit > 0.0 && fabs(x) < R(m.xcrit)) rho2 += R(m.xcrit * m.xcrit);
         const R rho = M<R>::sqrt(rho2);
-        R cps;
-        const R sps = sincos2pi<R>(dp.b, &cps);
         const R up1 = rho * cps, up2 = rho * sps;
         onb<R>(pk.k, e1, e2);
         R u[3];
@@ -692,11 +749,18 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
         const R x_atom = x - upar;
         int ph = o.phase;
         if (ph == kPhaseCoreWing && fabs(x_atom) >= R(0.2)) ph = kPhaseDipole;
-        const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
-        const R mu = sample_mu<R>(ph, dm.a, R(0));
-        const R s_ = M<R>::sqrt(fmax(R(0), R(1) - mu * mu));
-        R cphi;
-        const R sphi = sincos2pi<R>(dm.b, &cphi);
+        R mu, s_, cphi, sphi;
+        if constexpr (PRE) {
+            const bool wing = ph != o.phase;
+            mu = wing ? pre->mu_dp : pre->mu_ph;
+            s_ = wing ? pre->s_dp : pre->s_ph;
+            cphi = pre->cphi; sphi = pre->sphi;
+        } else {
+            const Uni2<R> dm = draw<R>(key, kSlotMu, pk.event);
+            mu = sample_mu<R>(ph, dm.a, R(0));
+            s_ = sin_of_cos<R>(mu);
+            sphi = sincos2pi<R>(dm.b, &cphi);
+        }
 #pragma unroll
         for (int i = 0; i < 3; ++i) kout[i] = mu * pk.k[i] + s_ * (cphi * e1[i] + sphi * e2[i]);
         if constexpr (GRID && Q) {
@@ -733,8 +797,7 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) pk.k[i] = kout[i];
-    const Uni2<double> dtau = draw<double>(key, kSlotTau, pk.event);
-    pk.tau_t = sizeof(R) == 8 ? -log(1.0 - dtau.a) : double(-__logf(float(1.0 - dtau.a)));
+    if constexpr (PRE) pk.tau_t = pre->tau_t; else pk.tau_t = tau_target<R>(draw<double>(key, kSlotTau, pk.event));
     pk.tau_a = 0.0;
     return kFateNone;
 }
@@ -744,11 +807,14 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
 // interactions (propagation, Section 3.4: piecewise-linear tau integration
 // until tau_current = tau_target, then the interaction).  Returns the fate
 // (kFateNone while it lives on); the packet state is complete on return, so
-// a later call resumes it exactly.
-template <class R, bool GRID, bool Q = false>
+// a later call resumes it exactly.  PRE: `pre` holds the draws of events
+// pre_event, pre_event + 1, ... evaluated ahead; max_events must not run
+// past them.
+template <class R, bool GRID, bool Q = false, bool PRE = false>
 __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt,
                        uint32_t max_visits, uint32_t max_events, uint32_t* events_done,
-                       const SeedBuf* sb = nullptr, SeedLane* sl = nullptr, CellCache<R>* ccp = nullptr) {
+                       const SeedBuf* sb = nullptr, SeedLane* sl = nullptr, CellCache<R>* ccp = nullptr,
+                       const EventDraws<R>* pre = nullptr, uint32_t pre_event = 0) {
     const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
     Loc L;
 #pragma unroll
@@ -801,7 +867,8 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
             pk.event++;
             ++ev;
             if (uint64_t(pk.event) > emax) { fate = kFateCapped; break; }
-            fate = interact<R, GRID, Q>(g, m, o, pk, L, f, kt, key, cnt, sb, sl);
+            fate = interact<R, GRID, Q, PRE>(g, m, o, pk, L, f, kt, key, cnt, sb, sl,
+                                             PRE ? pre + (pk.event - pre_event) : nullptr);
             if (fate != kFateNone) break;
             set_inverse();
             continue;

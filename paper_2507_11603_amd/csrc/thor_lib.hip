@@ -48,6 +48,19 @@ template <class R> struct PoolDev {
     int* alive;
 };
 
+// Packets handed from the persistent kernel to the tail kernel: the packet,
+// its home pool slot (the lane that held it), the count and a claim cursor;
+// `gone` counts the persistent waves that have left their loop, and waves
+// hand off only once at most `max_waves` are still running (the tail).
+template <class R> struct TailDev {
+    Pkt<R>* pk;
+    uint32_t* home;
+    unsigned long long* count;
+    unsigned long long* cursor;
+    unsigned long long* gone;
+    uint64_t max_waves;
+};
+
 __device__ __forceinline__ int find_batch(const BatchDev* b, int nb, uint64_t q) {
     int lo = 0, hi = nb - 1;   // last batch with q0 <= q
     while (lo < hi) {
@@ -64,17 +77,24 @@ __device__ __forceinline__ int find_batch(const BatchDev* b, int nb, uint64_t q)
 // short flights (packets trapped near line centre) make progress at the
 // pace of their neighbours' long flights.  A bounded step (step_events > 0)
 // parks live packets in the pool for the next launch.
+//
+// Tail hand-off (desc->wide > 0, unbounded calls): once the queue is drained,
+// at most tail.max_waves waves are still running and a wave holds at most
+// desc->wide live packets, it appends them to the tail list and exits; k_tail
+// then runs each of them in a wave of its own.
 template <class R, bool GRID, bool SEEDS>
 __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* __restrict__ models,
                                                     const BatchDev* __restrict__ batches,
                                                     const StepDesc* __restrict__ desc,
                                                     unsigned long long* cursor, OutDev o, PoolDev<R> pool,
-                                                    SeedBuf sb, unsigned long long* gstats) {
+                                                    TailDev<R> tail, SeedBuf sb, unsigned long long* gstats) {
     const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t q_end = desc->q_end;
     const int nbatch = desc->nbatch;
     const uint32_t step_events = desc->step_events;
     const uint32_t turn_visits = desc->turn_visits;
+    const int hand_off = tail.pk ? int(desc->wide) : 0;
+    const uint64_t waves_total = uint64_t(gridDim.x) * (blockDim.x >> 6);
     // peel rays of grid media: first segment at the event, the rest written to
     // the seed buffer for the peel pass (SEEDS: 1..kMaxSeedObs observers)
     constexpr bool useq = GRID && SEEDS;
@@ -150,7 +170,24 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
             }
         }
         const bool work = active && !stalled && used < budget;
-        if (__ballot(work) == 0) break;
+        const uint64_t wm = __ballot(work);
+        if (wm == 0) break;
+        if (hand_off && __popcll(wm) <= hand_off && __ballot(exhausted) != 0 &&
+            waves_total - __hip_atomic_load(tail.gone, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
+                tail.max_waves) {
+            // queue drained, few packets left: the tail kernel takes them
+            const int leader = __ffsll((unsigned long long)wm) - 1;
+            unsigned long long base = 0;
+            if (int(threadIdx.x & 63) == leader) base = atomicAdd(tail.count, (unsigned long long)__popcll(wm));
+            base = __shfl(base, leader, 64);
+            if (work) {
+                const uint64_t t = base + lane_rank(wm);
+                tail.pk[t] = pk;
+                tail.home[t] = uint32_t(gid);
+                active = false;
+            }
+            break;
+        }
         if (work) {
             const ModelDev& m = models[pk.model];
             const int fate = advance<R, GRID, useq>(g, m, o, pk, cnt, turn_visits, budget - used, &used, &sb, &sl,
@@ -162,10 +199,94 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
         }
     }
     if (useq && __ballot(stalled) && (threadIdx.x & 63) == 0) atomicAdd(sb.parked, 1ull);
+    if (hand_off && (threadIdx.x & 63) == 0) atomicAdd(tail.gone, 1ull);
     if (pool.alive) {
         pool.alive[gid] = active ? 1 : 0;
         if (active) pool.pk[gid] = pk;
     }
+    flush_counters(cnt, gstats);
+}
+
+// Tail of a persistent launch: the packets handed off by waves whose queue
+// was drained (typically a few trapped near line centre that scatter 1e4-1e6
+// times and would set the launch time alone), one packet per wave.  Before
+// each turn all 64 lanes evaluate the state-independent draws of the
+// packet's next 64 events (event_draws, the same functions as the inline
+// path, so the histories are the same bits) into LDS; lane 0 then runs
+// those events, its serial chain reduced to what depends on the packet's
+// state (march, Voigt, u_parallel, basis, peel).  When the seed buffer is
+// full, packets go back to their home pool slots for the next round.
+template <class R, bool GRID, bool SEEDS>
+__global__ __launch_bounds__(256) void k_tail(GridDev g, const ModelDev* __restrict__ models,
+                                              const StepDesc* __restrict__ desc, OutDev o, PoolDev<R> pool,
+                                              TailDev<R> tail, SeedBuf sb, unsigned long long* gstats) {
+    constexpr bool useq = GRID && SEEDS;
+    __shared__ EventDraws<R> s_pre[256];
+    EventDraws<R>* wd = s_pre + (threadIdx.x & ~63u);
+    const int lane = int(threadIdx.x & 63);
+    const uint64_t n = *tail.count;
+    const uint32_t turn_visits = desc->turn_visits;
+    Counters cnt = {};
+    SeedLane sl{0, 0};
+    bool stalled = false;          // wave-uniform
+    for (;;) {
+        unsigned long long i = 0;
+        if (lane == 0) i = atomicAdd(tail.cursor, 1ull);
+        i = __shfl(i, 0, 64);
+        if (i >= n) break;
+        Pkt<R> pk = tail.pk[i];
+        const uint32_t home = tail.home[i];
+        const ModelDev& m = models[pk.model];
+        const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
+        CellCache<R> cc;
+        cc.valid = false;
+        int fate = kFateNone;
+        while (!stalled) {
+            if constexpr (useq) {
+                int st = 0;
+                if (lane == 0) {
+                    if (__hip_atomic_load(sb.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= sb.cap) {
+                        st = 1;
+                    } else if (sl.left < uint32_t(o.n_obs)) {
+                        const unsigned long long base = atomicAdd(sb.count, (unsigned long long)sb.chunk);
+                        if (base + sb.chunk <= sb.cap) {
+                            sl.cur = base;
+                            sl.left = sb.chunk;
+                        } else {
+                            st = 1;
+                        }
+                    }
+                }
+                stalled = __shfl(st, 0, 64) != 0;
+                if (stalled) break;
+            }
+            event_draws<R>(key, pk.event + 1u + uint32_t(lane), o.phase, R(m.g_hg), wd[lane]);
+            // the wave's own LDS stores, read back by lane 0
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane == 0) {
+                uint32_t used = 0;
+                fate = advance<R, GRID, useq, true>(g, m, o, pk, cnt, turn_visits, 64u, &used, &sb, &sl, &cc, wd,
+                                                    pk.event + 1u);
+            }
+            fate = __shfl(fate, 0, 64);
+            pk.event = __shfl(pk.event, 0, 64);
+            // lane 0's reads of the draws precede the next turn's stores
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (fate != kFateNone) break;
+        }
+        if (lane == 0) {
+            if (fate != kFateNone) {
+                finish<R, GRID>(g, m, o, pk, fate, cnt);
+            } else {            // seed buffer full: the next round resumes it
+                pool.pk[home] = pk;
+                pool.alive[home] = 1;
+            }
+        }
+    }
+    if (useq && stalled && lane == 0) atomicAdd(sb.parked, 1ull);
     flush_counters(cnt, gstats);
 }
 
@@ -544,6 +665,12 @@ struct thor_ctx {
     uint64_t q_total = 0;        // queue indices handed out so far
     uint64_t pool_bytes = 0;
 
+    // tail list (packets handed to k_tail), one slot per persistent lane
+    void* d_tail_pk = nullptr;
+    uint32_t* d_tail_home = nullptr;
+    unsigned long long* d_tailctl = nullptr;   // count, cursor
+    uint64_t tail_slots = 0;
+
     thor_stats last{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     StepDesc* d_desc = nullptr;            // step descriptor of the transport path
@@ -767,6 +894,13 @@ OutDev make_out(thor_ctx* ctx, const thor_transport_opts* o) {
     return out;
 }
 
+// Live lanes at or below which a persistent wave takes wide turns.
+uint32_t wide_lanes(const thor_transport_opts* o) {
+    if (o->wide_lanes < 0) return 0u;
+    if (o->wide_lanes == 0) return 8u;
+    return o->wide_lanes > 16 ? 16u : uint32_t(o->wide_lanes);
+}
+
 int launch_grid_size(thor_ctx* ctx, const thor_transport_opts* o, int block) {
     const int waves = o->waves_per_cu > 0 ? o->waves_per_cu : 8;
     const int wpb = block / 64;
@@ -780,19 +914,66 @@ void launch_plain(thor_ctx* ctx, const BatchDev& b, const OutDev& out) {
                        out, ctx->d_stats);
 }
 
+template <class R>
+TailDev<R> tail_dev(thor_ctx* ctx, bool on) {
+    if (!on) return TailDev<R>{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
+    return TailDev<R>{reinterpret_cast<Pkt<R>*>(ctx->d_tail_pk), ctx->d_tail_home, ctx->d_tailctl,
+                      ctx->d_tailctl + 1, ctx->d_tailctl + 2, uint64_t(ctx->num_cu)};
+}
+
 template <class R, bool GRID>
 void launch_persistent(thor_ctx* ctx, hipStream_t stream, int grid, int block, const BatchDev* d_b,
                        const StepDesc* d_desc, unsigned long long* cursor, const OutDev& out,
-                       const ModelDev* d_models, void* pool_pk, int* pool_alive, const SeedBuf& sb) {
+                       const ModelDev* d_models, void* pool_pk, int* pool_alive, const SeedBuf& sb,
+                       bool hand_off = false) {
     PoolDev<R> pool{reinterpret_cast<Pkt<R>*>(pool_pk), pool_alive};
+    const TailDev<R> tail = tail_dev<R>(ctx, hand_off);
     bool seeds = false;
     if constexpr (GRID) seeds = sb.s != nullptr;
     if (seeds)
         hipLaunchKernelGGL((k_persistent<R, GRID, GRID>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
-                           d_b, d_desc, cursor, out, pool, sb, ctx->d_stats);
+                           d_b, d_desc, cursor, out, pool, tail, sb, ctx->d_stats);
     else
         hipLaunchKernelGGL((k_persistent<R, GRID, false>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
-                           d_b, d_desc, cursor, out, pool, sb, ctx->d_stats);
+                           d_b, d_desc, cursor, out, pool, tail, sb, ctx->d_stats);
+}
+
+// The tail kernel over what the preceding persistent launch handed off (its
+// waves exit at once when nothing was).
+template <class R, bool GRID>
+void launch_tail(thor_ctx* ctx, const StepDesc* d_desc, const OutDev& out, void* pool_pk, int* pool_alive,
+                 const SeedBuf& sb) {
+    PoolDev<R> pool{reinterpret_cast<Pkt<R>*>(pool_pk), pool_alive};
+    const TailDev<R> tail = tail_dev<R>(ctx, true);
+    bool seeds = false;
+    if constexpr (GRID) seeds = sb.s != nullptr;
+    if (seeds)
+        hipLaunchKernelGGL((k_tail<R, GRID, GRID>), dim3(ctx->num_cu), dim3(256), 0, ctx->stream, ctx->grid,
+                           ctx->d_models, d_desc, out, pool, tail, sb, ctx->d_stats);
+    else
+        hipLaunchKernelGGL((k_tail<R, GRID, false>), dim3(ctx->num_cu), dim3(256), 0, ctx->stream, ctx->grid,
+                           ctx->d_models, d_desc, out, pool, tail, sb, ctx->d_stats);
+}
+
+// Tail list of `slots` packets of either precision.
+thor_status ensure_tail(thor_ctx* ctx, uint64_t slots) {
+    if (ctx->d_tail_pk && ctx->tail_slots >= slots) return THOR_OK;
+    dfree(ctx, ctx->d_tail_pk, ctx->tail_slots * sizeof(Pkt<double>));
+    dfree(ctx, ctx->d_tail_home, ctx->tail_slots * 4);
+    ctx->d_tail_pk = nullptr;
+    ctx->d_tail_home = nullptr;
+    ctx->tail_slots = 0;
+    static_assert(sizeof(Pkt<double>) >= sizeof(Pkt<float>), "tail slots sized for FP64 packets");
+    thor_status s = dalloc(ctx, &ctx->d_tail_pk, slots * sizeof(Pkt<double>), "tail list");
+    if (s) return s;
+    s = dalloc(ctx, (void**)&ctx->d_tail_home, slots * 4, "tail list homes");
+    if (s) return s;
+    if (!ctx->d_tailctl) {
+        s = dalloc(ctx, (void**)&ctx->d_tailctl, 3 * 8, "tail list counters");
+        if (s) return s;
+    }
+    ctx->tail_slots = slots;
+    return THOR_OK;
 }
 
 // Peel seed buffer of the grid persistent path (slots of 48 B, all empty).
@@ -911,7 +1092,8 @@ void thor_destroy(thor_ctx* ctx) {
                     ctx->d_models, ctx->d_batches, ctx->d_rec_dv, ctx->d_rec_nres, ctx->d_rec_ndust,
                     ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done,
                     ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
-                    ctx->d_seeds, ctx->d_seedctl, ctx->d_axr[0], ctx->d_axr[1], ctx->d_axr[2]};
+                    ctx->d_seeds, ctx->d_seedctl, ctx->d_axr[0], ctx->d_axr[1], ctx->d_axr[2],
+                    ctx->d_tail_pk, ctx->d_tail_home, ctx->d_tailctl};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& kv : ctx->s_reqs)
@@ -1183,7 +1365,9 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         const int gsize = launch_grid_size(ctx, opt, block);
         const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
         if (opt->step_events > 0xFFFFFFFFull) return fail(THOR_E_INVAL, "step_events must fit 32 bits");
-        *ctx->h_desc = StepDesc{q_end, int(nb), uint32_t(opt->step_events), turn, 0u};
+        // unbounded calls hand the last packets of drained waves to k_tail
+        const bool hand_off = !bounded && wide_lanes(opt) > 0;
+        *ctx->h_desc = StepDesc{q_end, int(nb), uint32_t(opt->step_events), turn, hand_off ? wide_lanes(opt) : 0u};
         HIPCHK(ctx, hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(StepDesc), hipMemcpyHostToDevice, ctx->stream));
         if (bounded) {
             s = ensure_pool(ctx, uint64_t(gsize) * block, opt->precision);
@@ -1211,6 +1395,10 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
                 if (s) return s;
             }
         }
+        if (hand_off) {
+            s = ensure_tail(ctx, uint64_t(gsize) * block);
+            if (s) return s;
+        }
         const bool use_pool = bounded || seeds;
         void* ppk = use_pool ? ctx->d_pool_pk : nullptr;
         int* pal = use_pool ? ctx->d_pool_alive : nullptr;
@@ -1225,10 +1413,18 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
                 hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_seedctl, 2 + kXcds);
                 HIPCHK(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
             }
-            if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb)
-                           : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb);
-            else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb)
-                      : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb);
+            if (hand_off)
+                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_tailctl, 3);
+            if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off)
+                           : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off);
+            else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off)
+                      : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off);
+            if (hand_off) {
+                if (fp64) grid ? launch_tail<double, true>(ctx, ctx->d_desc, out, ppk, pal, sb)
+                               : launch_tail<double, false>(ctx, ctx->d_desc, out, ppk, pal, sb);
+                else grid ? launch_tail<float, true>(ctx, ctx->d_desc, out, ppk, pal, sb)
+                          : launch_tail<float, false>(ctx, ctx->d_desc, out, ppk, pal, sb);
+            }
             hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, ctx->stream, cur, ctx->d_desc);
             if (!seeds) break;
             HIPCHK(ctx, hipEventRecord(ctx->ev_b, ctx->stream));
