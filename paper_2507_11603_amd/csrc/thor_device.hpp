@@ -234,6 +234,18 @@ __device__ __forceinline__ float voigt32(float a, float x) {
     return h;
 }
 
+// A lower bound of H(a, x) that decides sure peel cuts without the profile.
+// H is the mean of exp(-(x - l)^2) over a Lorentzian l of half width a, so
+// for delta = 1/4, H >= P(|l| <= delta) exp(-(|x| + delta)^2) and
+// P(|l| <= delta) = (2/pi) atan(delta/a) >= 1 - 2a/(pi delta).  The factor
+// 0.99 keeps the bound below both evaluations of H (FP64 within 1e-13, FP32
+// within 2e-5 relative for a <= 0.05); above that a, 0.
+__device__ __forceinline__ float voigt_floor(float a, float x) {
+    if (!(a <= 0.05f)) return 0.0f;
+    const float ax = fabsf(x) + 0.25f;
+    return 0.99f * (1.0f - 2.5464790894703255f * a) * __expf(-ax * ax);
+}
+
 template <class R> __device__ __forceinline__ R voigt(R a, R x);
 template <> __device__ __forceinline__ double voigt<double>(double a, double x) { return voigt64(a, x); }
 template <> __device__ __forceinline__ float voigt<float>(float a, float x) { return voigt32(a, x); }
@@ -336,6 +348,57 @@ __device__ __forceinline__ double upar_sample64(double x, double a, const Key& k
     return sgn * u;
 }
 
+// FP32 arctangent of z >= 0: atan z = pi/2 - atan(1/z) above 1, and
+// atan w = pi/4 + atan((w - 1)/(w + 1)) above tan(pi/8), leaving |t| <=
+// tan(pi/8) for the Taylor series t - t^3/3 + ... - t^15/15 + t^17/17
+// (truncation below 3e-9 relative).
+__device__ __forceinline__ float atan_nonneg(float z) {
+    const bool inv = z > 1.0f;
+    const float w = inv ? __builtin_amdgcn_rcpf(z) : z;
+    const bool mid = w > 0.41421356f;
+    const float t = mid ? __fdividef(w - 1.0f, w + 1.0f) : w;
+    const float t2 = t * t;
+    float p = 1.0f / 17.0f;
+    p = fmaf(p, t2, -1.0f / 15.0f);
+    p = fmaf(p, t2, 1.0f / 13.0f);
+    p = fmaf(p, t2, -1.0f / 11.0f);
+    p = fmaf(p, t2, 1.0f / 9.0f);
+    p = fmaf(p, t2, -1.0f / 7.0f);
+    p = fmaf(p, t2, 1.0f / 5.0f);
+    p = fmaf(p, t2, -1.0f / 3.0f);
+    p = fmaf(p, t2, 1.0f);
+    float r = t * p;
+    if (mid) r += float(kPi / 4);
+    return inv ? float(kPi / 2) - r : r;
+}
+
+// FP32 cotangent on [0, pi): cot(pi - t) = -cot t, cot t = tan(pi/2 - t)
+// above pi/4, and sin, cos of t in [0, pi/4] from their Taylor series to
+// t^11, t^12 (truncation below 1e-11).  cot 0 = +inf.
+__device__ __forceinline__ float cot_0pi(float th) {
+    const bool neg = th > float(kPi / 2);
+    float t = neg ? float(kPi) - th : th;
+    const bool hi = t > float(kPi / 4);
+    t = hi ? float(kPi / 2) - t : t;
+    const float t2 = t * t;
+    float sp = -1.0f / 39916800.0f;
+    sp = fmaf(sp, t2, 1.0f / 362880.0f);
+    sp = fmaf(sp, t2, -1.0f / 5040.0f);
+    sp = fmaf(sp, t2, 1.0f / 120.0f);
+    sp = fmaf(sp, t2, -1.0f / 6.0f);
+    sp = fmaf(sp, t2, 1.0f);
+    const float sn = t * sp;
+    float cp = 1.0f / 479001600.0f;
+    cp = fmaf(cp, t2, -1.0f / 3628800.0f);
+    cp = fmaf(cp, t2, 1.0f / 40320.0f);
+    cp = fmaf(cp, t2, -1.0f / 720.0f);
+    cp = fmaf(cp, t2, 1.0f / 24.0f);
+    cp = fmaf(cp, t2, -0.5f);
+    const float cs = fmaf(cp, t2, 1.0f);
+    const float c = hi ? __fdividef(sn, cs) : __fdividef(cs, sn);
+    return neg ? -c : c;
+}
+
 __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key, uint32_t event,
                                                uint32_t* trials, const Uni2<float>* pre) {
     const float xa = fabsf(x);
@@ -345,15 +408,17 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
     float u = 0.0f;
     if (!(xa < 1e30f) || !(a > 0.0f)) { *trials = 0; return 0.0f; }
     if (xa < float(kUparSwitch)) {
+        // any split in [0, xa] keeps the sampler exact, so its iteration
+        // runs on fast (approximate) exp and sqrt
         float u0 = xa;
         for (int it = 0; it < 2; ++it) {
             if (u0 <= 0.0f) break;
-            u0 = xa - sqrtf(__fdividef(a * expm1f(u0 * u0), 2.0f * pi * u0));
+            u0 = xa - __builtin_amdgcn_sqrtf(__fdividef(a * (__expf(u0 * u0) - 1.0f), 2.0f * pi * u0));
             u0 = fminf(fmaxf(u0, 0.0f), xa);
         }
         const float d = xa - u0;                    // >= 0
-        const float p1 = d > 0.0f ? atanf(__fdividef(a, d)) : hpi;   // theta0 + pi/2
-        const float q2 = d > 0.0f ? pi - p1 : hpi;                  // pi/2 - theta0
+        const float p1 = d > 0.0f ? atan_nonneg(__fdividef(a, d)) : hpi;   // theta0 + pi/2
+        const float q2 = d > 0.0f ? pi - p1 : hpi;                        // pi/2 - theta0
         const float e0 = __expf(-u0 * u0);
         const float m = fmaf(e0, q2, p1);
         for (;;) {
@@ -362,10 +427,10 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
             ++n;
             const float r = r12.a * m;
             if (r < p1) {
-                u = xa - __fdividef(a, tanf(r));        // tan(r - pi/2) = -1/tan(r)
+                u = xa - a * cot_0pi(r);                // tan(r - pi/2) = -cot(r)
                 if (r12.b < __expf(-u * u)) break;
             } else {
-                u = xa + __fdividef(a, tanf(q2 - __fdividef(r - p1, e0)));  // tan(pi/2 - psi) = 1/tan(psi)
+                u = xa + a * cot_0pi(q2 - __fdividef(r - p1, e0));  // tan(pi/2 - psi) = cot(psi)
                 if (r12.b < __expf((u0 - u) * (u0 + u))) break;
             }
         }
@@ -383,7 +448,7 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
         const float p = 1.0f - __fdividef(c, xa * xa), mu = __builtin_amdgcn_rcpf(xa * p);
         const float za = __fdividef(__expf(p * mu * mu) * sqrtf(__fdividef(pi, p)), xa * xa);
         const float d = xa - u0;
-        const float q2 = pi - atanf(__fdividef(a, d));
+        const float q2 = pi - atan_nonneg(__fdividef(a, d));
         const float e0 = __expf(-u0 * u0);
         const float zb = __fdividef(e0 * q2, a);
         for (;;) {
@@ -403,7 +468,7 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
                 if (r12.b * env < tgt) break;
             } else {
                 ++n;
-                u = xa + __fdividef(a, tanf(q2 - __fdividef((r - za) * a, e0)));
+                u = xa + a * cot_0pi(q2 - __fdividef((r - za) * a, e0));
                 if (r12.b < __expf((u0 - u) * (u0 + u))) break;
             }
         }
@@ -459,7 +524,7 @@ template <class R> __device__ __forceinline__ R phase_value(int phase, R mu, R g
 // Orthonormal basis perpendicular to unit n (Duff et al. 2017, JCGT 6(1)).
 template <class R> __device__ __forceinline__ void onb(const R n[3], R e1[3], R e2[3]) {
     const R sign = copysign(R(1), n[2]);
-    const R a = R(-1) / (sign + n[2]);
+    const R a = fdiv(R(-1), sign + n[2]);
     const R b = n[0] * n[1] * a;
     e1[0] = R(1) + sign * n[0] * n[0] * a; e1[1] = sign * b; e1[2] = -sign * n[0];
     e2[0] = b; e2[1] = sign + n[1] * n[1] * a; e2[2] = -n[1];

@@ -468,6 +468,12 @@ __device__ __forceinline__ bool peel_first(const GridDev& g, const OutDev& o, co
     if (f0.k0 > 0.0 || f0.kd > 0.0) {
         const R va = sel3(a, f0.v[0], f0.v[1], f0.v[2]);
         const R x = fdiv(dv_peel - (pos ? va : -va), f0.vth);
+        // a sure cut needs no profile: the same test on a lower bound of H
+        // (each step of the expression is monotone in H)
+        if ((f0.k0 * double(voigt_floor(float(f0.a), float(x))) + f0.kd) * t > o.tau_cut) {
+            cnt.peel_cut++;
+            return false;
+        }
         tau = (f0.k0 * double(voigt<R>(f0.a, x)) + f0.kd) * t;
         if (tau > o.tau_cut) { cnt.peel_cut++; return false; }
     }
