@@ -499,19 +499,18 @@ __device__ __forceinline__ int64_t cube_index(const OutDev& o, int obs, int axis
 }
 
 // Peel ray `ob` of an event on the seed path: first segment now; a ray that
-// goes on is written to the lane's claimed slots (room for it was checked
-// before the event), unless its pixel or bin lies outside the cube.
+// goes on becomes a seed (returns true), unless its pixel or bin lies
+// outside the cube.
 template <class R>
-__device__ __forceinline__ void seed_emit(const GridDev& g, const OutDev& o, const Loc& L, const Fields<R>& f, int ob,
-                                          double weight, R dv_peel, Counters& cnt, const SeedBuf& sb, SeedLane& sl) {
+__device__ __forceinline__ bool seed_make(const GridDev& g, const OutDev& o, const Loc& L, const Fields<R>& f, int ob,
+                                          double weight, R dv_peel, Counters& cnt, PeelSeed& sd) {
     double tau;
-    if (!peel_first<R>(g, o, L, f, ob, weight, dv_peel, cnt, &tau)) return;
+    if (!peel_first<R>(g, o, L, f, ob, weight, dv_peel, cnt, &tau)) return false;
     const int axis = o.obs_axis[ob];
     const int64_t ci = cube_index(o, ob, axis, L.p, double(dv_peel));
-    if (ci < 0) { cnt.peel_dropped++; return; }
+    if (ci < 0) { cnt.peel_dropped++; return false; }
     const int a = axis % 3;
     const int nx = sel3(a, L.c[0], L.c[1], L.c[2]) + (axis < 3 ? 1 : -1);
-    PeelSeed sd;
     sd.c[0] = a == 0 ? nx : L.c[0];
     sd.c[1] = a == 1 ? nx : L.c[1];
     sd.c[2] = a == 2 ? nx : L.c[2];
@@ -520,10 +519,35 @@ __device__ __forceinline__ void seed_emit(const GridDev& g, const OutDev& o, con
     sd.dv = double(dv_peel);
     sd.w = weight;
     sd.cube = uint64_t(ci);
+    return true;
+}
+
+// The same, written to the lane's claimed slots (room for it was checked
+// before the event).
+template <class R>
+__device__ __forceinline__ void seed_emit(const GridDev& g, const OutDev& o, const Loc& L, const Fields<R>& f, int ob,
+                                          double weight, R dv_peel, Counters& cnt, const SeedBuf& sb, SeedLane& sl) {
+    PeelSeed sd;
+    if (!seed_make<R>(g, o, L, f, ob, weight, dv_peel, cnt, sd)) return;
     sb.s[sl.cur] = sd;
     ++sl.cur;
     --sl.left;
 }
+
+// A peel ray recorded by a serial event loop, its first segment marched
+// later by whichever lane takes it (seed_make with these arguments).
+template <class R> struct PeelJob {
+    double p[3];
+    int c[3];
+    int ob;
+    Fields<R> f;
+    double w;
+    R dvp;
+};
+template <class R> struct JobSink {
+    PeelJob<R>* jobs;
+    uint32_t n;
+};
 
 // ----------------------------------------------------------------- event draws
 // Quantities of interaction `event` that depend only on the packet's key and
@@ -690,7 +714,7 @@ template <class R, bool GRID, bool Q, bool PRE = false>
 __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk,
                                         const Loc& L, const Fields<R>& f, double kt, const Key& key,
                                         Counters& cnt, const SeedBuf* sb, SeedLane* sl,
-                                        const EventDraws<R>* pre = nullptr) {
+                                        const EventDraws<R>* pre = nullptr, JobSink<R>* js = nullptr) {
     Uni2<double> dtyp;
     if constexpr (PRE) dtyp = pre->typ; else dtyp = draw<double>(key, kSlotType, pk.event);
     R kout[3], e1[3], e2[3];
@@ -717,7 +741,12 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
                     obs_dir(o.obs_axis[ob], kd);
                     const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
                     const double c = double(phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg))) / (2.0 * kPi);
-                    seed_emit<R>(g, o, L, f, ob, c, dvl + dot3<R>(f.v, ko), cnt, *sb, *sl);
+                    if constexpr (PRE) {
+                        js->jobs[js->n++] = PeelJob<R>{{L.p[0], L.p[1], L.p[2]}, {L.c[0], L.c[1], L.c[2]}, ob, f, c,
+                                                       R(dvl + dot3<R>(f.v, ko))};
+                    } else {
+                        seed_emit<R>(g, o, L, f, ob, c, dvl + dot3<R>(f.v, ko), cnt, *sb, *sl);
+                    }
                 }
             });
         } else {
@@ -778,7 +807,12 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
                     const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
                     const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
                     const R xo = x_atom + dot3<R>(u, ko);
-                    seed_emit<R>(g, o, L, f, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt, *sb, *sl);
+                    if constexpr (PRE) {
+                        js->jobs[js->n++] = PeelJob<R>{{L.p[0], L.p[1], L.p[2]}, {L.c[0], L.c[1], L.c[2]}, ob, f, c,
+                                                       R(xo * f.vth + dot3<R>(f.v, ko))};
+                    } else {
+                        seed_emit<R>(g, o, L, f, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt, *sb, *sl);
+                    }
                 }
             });
         } else {
@@ -820,7 +854,7 @@ template <class R, bool GRID, bool Q = false, bool PRE = false>
 __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt,
                        uint32_t max_visits, uint32_t max_events, uint32_t* events_done,
                        const SeedBuf* sb = nullptr, SeedLane* sl = nullptr, CellCache<R>* ccp = nullptr,
-                       const EventDraws<R>* pre = nullptr, uint32_t pre_event = 0) {
+                       const EventDraws<R>* pre = nullptr, uint32_t pre_event = 0, JobSink<R>* js = nullptr) {
     const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
     Loc L;
 #pragma unroll
@@ -861,7 +895,7 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
             kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
         }
         if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) {
-            if constexpr (Q) {
+            if constexpr (Q && !PRE) {
                 // no room for this event's rays: end the turn before it (state
                 // unchanged); the wave claims a new run of slots
                 if (sl->left < uint32_t(o.n_obs)) break;
@@ -874,7 +908,7 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
             ++ev;
             if (uint64_t(pk.event) > emax) { fate = kFateCapped; break; }
             fate = interact<R, GRID, Q, PRE>(g, m, o, pk, L, f, kt, key, cnt, sb, sl,
-                                             PRE ? pre + (pk.event - pre_event) : nullptr);
+                                             PRE ? pre + (pk.event - pre_event) : nullptr, js);
             if (fate != kFateNone) break;
             set_inverse();
             continue;

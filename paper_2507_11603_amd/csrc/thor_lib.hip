@@ -209,23 +209,28 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
 
 // Tail of a persistent launch: the packets handed off by waves whose queue
 // was drained (typically a few trapped near line centre that scatter 1e4-1e6
-// times and would set the launch time alone), one packet per wave.  Before
-// each turn all 64 lanes evaluate the state-independent draws of the
-// packet's next 64 events (event_draws, the same functions as the inline
-// path, so the histories are the same bits) into LDS; lane 0 then runs
-// those events, its serial chain reduced to what depends on the packet's
-// state (march, Voigt, u_parallel, basis, peel).  When the seed buffer is
-// full, packets go back to their home pool slots for the next round.
+// times and would set the launch time alone), one packet per wave (one wave
+// per workgroup).  Each turn, all 64 lanes first evaluate the
+// state-independent draws of the packet's next events (event_draws, the same
+// functions as the inline path, so the histories are the same bits) into
+// LDS; lane 0 then runs those events, its serial chain reduced to what
+// depends on the packet's state (march, Voigt, u_parallel, basis).  On the
+// seed path lane 0 only records each event's peel rays, and all lanes then
+// march their first segments (seed_make), one ray per lane, into a run of
+// slots claimed for the turn.  When the seed buffer is full, packets go back
+// to their home pool slots for the next round.
 template <class R, bool GRID, bool SEEDS>
-__global__ __launch_bounds__(256) void k_tail(GridDev g, const ModelDev* __restrict__ models,
-                                              const StepDesc* __restrict__ desc, OutDev o, PoolDev<R> pool,
-                                              TailDev<R> tail, SeedBuf sb, unsigned long long* gstats) {
+__global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restrict__ models,
+                                             const StepDesc* __restrict__ desc, OutDev o, PoolDev<R> pool,
+                                             TailDev<R> tail, SeedBuf sb, unsigned long long* gstats) {
     constexpr bool useq = GRID && SEEDS;
-    __shared__ EventDraws<R> s_pre[256];
-    EventDraws<R>* wd = s_pre + (threadIdx.x & ~63u);
-    const int lane = int(threadIdx.x & 63);
+    __shared__ EventDraws<R> wd[64];
+    __shared__ PeelJob<R> wj[useq ? 64 : 1];
+    const int lane = int(threadIdx.x);
     const uint64_t n = *tail.count;
     const uint32_t turn_visits = desc->turn_visits;
+    // events per turn: at most one peel ray per lane
+    const uint32_t per = useq ? uint32_t(64 / o.n_obs) : 64u;
     Counters cnt = {};
     SeedLane sl{0, 0};
     bool stalled = false;          // wave-uniform
@@ -242,37 +247,55 @@ __global__ __launch_bounds__(256) void k_tail(GridDev g, const ModelDev* __restr
         cc.valid = false;
         int fate = kFateNone;
         while (!stalled) {
+            unsigned long long base = 0;
             if constexpr (useq) {
+                // slots for every ray of the turn, claimed before its events
+                const uint64_t need = uint64_t(per) * uint64_t(o.n_obs);
                 int st = 0;
                 if (lane == 0) {
                     if (__hip_atomic_load(sb.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= sb.cap) {
                         st = 1;
-                    } else if (sl.left < uint32_t(o.n_obs)) {
-                        const unsigned long long base = atomicAdd(sb.count, (unsigned long long)sb.chunk);
-                        if (base + sb.chunk <= sb.cap) {
-                            sl.cur = base;
-                            sl.left = sb.chunk;
-                        } else {
-                            st = 1;
-                        }
+                    } else {
+                        base = atomicAdd(sb.count, (unsigned long long)need);
+                        if (base + need > sb.cap) st = 1;
                     }
                 }
                 stalled = __shfl(st, 0, 64) != 0;
                 if (stalled) break;
+                base = __shfl(base, 0, 64);
             }
             event_draws<R>(key, pk.event + 1u + uint32_t(lane), o.phase, R(m.g_hg), wd[lane]);
             // the wave's own LDS stores, read back by lane 0
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            JobSink<R> js{wj, 0u};
             if (lane == 0) {
                 uint32_t used = 0;
-                fate = advance<R, GRID, useq, true>(g, m, o, pk, cnt, turn_visits, 64u, &used, &sb, &sl, &cc, wd,
-                                                    pk.event + 1u);
+                fate = advance<R, GRID, useq, true>(g, m, o, pk, cnt, turn_visits, per, &used, &sb, &sl, &cc, wd,
+                                                    pk.event + 1u, &js);
             }
             fate = __shfl(fate, 0, 64);
             pk.event = __shfl(pk.event, 0, 64);
-            // lane 0's reads of the draws precede the next turn's stores
+            if constexpr (useq) {
+                const uint32_t nj = __shfl(js.n, 0, 64);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                bool keep = false;
+                PeelSeed sd;
+                if (uint32_t(lane) < nj) {
+                    const PeelJob<R> j = wj[lane];
+                    Loc L;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) { L.p[k] = j.p[k]; L.c[k] = j.c[k]; }
+                    L.region = kRegGas;
+                    keep = seed_make<R>(g, o, L, j.f, j.ob, j.w, j.dvp, cnt, sd);
+                }
+                const uint64_t km = __ballot(keep);
+                if (keep) sb.s[base + lane_rank(km)] = sd;
+            }
+            // every read of this turn's draws and jobs precedes the next turn's stores
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             if (fate != kFateNone) break;
@@ -948,10 +971,10 @@ void launch_tail(thor_ctx* ctx, const StepDesc* d_desc, const OutDev& out, void*
     bool seeds = false;
     if constexpr (GRID) seeds = sb.s != nullptr;
     if (seeds)
-        hipLaunchKernelGGL((k_tail<R, GRID, GRID>), dim3(ctx->num_cu), dim3(256), 0, ctx->stream, ctx->grid,
+        hipLaunchKernelGGL((k_tail<R, GRID, GRID>), dim3(ctx->num_cu * 4), dim3(64), 0, ctx->stream, ctx->grid,
                            ctx->d_models, d_desc, out, pool, tail, sb, ctx->d_stats);
     else
-        hipLaunchKernelGGL((k_tail<R, GRID, false>), dim3(ctx->num_cu), dim3(256), 0, ctx->stream, ctx->grid,
+        hipLaunchKernelGGL((k_tail<R, GRID, false>), dim3(ctx->num_cu * 4), dim3(64), 0, ctx->stream, ctx->grid,
                            ctx->d_models, d_desc, out, pool, tail, sb, ctx->d_stats);
 }
 
