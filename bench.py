@@ -61,18 +61,27 @@ def parse():
 
 
 def kernel_split(st):
-    """Device time and algorithmic cell visits of the two kernels of a call.
-    On the peel-seed path the transport kernel marches the main flights and
-    the first segment of every peel ray (one visit per ray); the peel pass
-    marches the rest.  Otherwise the transport kernel does everything."""
+    """Device time and algorithmic cell visits of the kernels of a call.
+    Persistent path: the persistent kernel marches main flights and, on the
+    peel-seed path, the first segment of every peel ray (one visit per ray);
+    the tail kernel does the same for the packets handed off at the end of
+    the launch; the peel pass marches the rest of the rays.  Plain path or
+    inline peel: the transport kernel does everything."""
     seeded = st["peel_ms"] > 0.0
-    tr_visits = st["main_visits"] + (st["peel_contrib"] if seeded else st["peel_visits"])
+    tail_ms = st.get("tail_ms", 0.0)
+    tl_visits = st.get("tail_main_visits", 0) + st.get("tail_peel_visits", 0)
+    tr_visits = st["main_visits"] + (st["peel_contrib"] if seeded else st["peel_visits"]) - tl_visits
     pp_visits = st["peel_visits"] - st["peel_contrib"] if seeded else 0
     out = {}
-    for name, ms, v in (("transport", st["transport_ms"], tr_visits), ("peel_pass", st["peel_ms"], pp_visits)):
+    for name, ms, v in (("transport", st["transport_ms"] - tail_ms, tr_visits), ("tail", tail_ms, tl_visits),
+                        ("peel_pass", st["peel_ms"], pp_visits)):
+        if name == "tail" and ms <= 0.0:
+            continue
         ach = BYTES_PER_VISIT * v / (ms / 1e3) / 1e9 if ms > 0 else 0.0
         out[name] = {"ms": ms, "visits": v, "launches": int(st["passes"]) if (ms > 0 or name == "transport") else 0,
                      "achieved_GBps": ach, "hbm_frac": ach / HBM_PEAK_GBS}
+    if "tail" in out:
+        out["tail"]["events"] = st["tail_events"]
     return out
 
 
@@ -95,7 +104,7 @@ def counter_record(name):
 def attach_counters(roof, split, dom, rec, batches):
     """HBM traffic per launch of the dominant kernel and VALU activity of both
     kernels from a counter record (per batch there, scaled to this run)."""
-    kname = {"transport": "k_persistent", "peel_pass": "k_peel_pass"}[dom]
+    kname = {"transport": "k_persistent", "tail": "k_tail", "peel_pass": "k_peel_pass"}[dom]
     kr = rec["kernels"].get(kname)
     if kr and "read_bytes_per_batch" in kr and "write_bytes_per_batch" in kr:
         launches = max(split[dom]["launches"], 1)
@@ -289,13 +298,19 @@ def main():
         "cell_visits_per_s": visits / dt,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ({"transport": "k_persistent<float,true,true>", "peel_pass": "k_peel_pass_f32"}[dom]
-                                if a.path == "persistent" else "k_plain"),
+                     "kernel": ({"transport": "k_persistent<float,true,true>", "tail": "k_tail<float,true,true>",
+                                 "peel_pass": "k_peel_pass_f32"}[dom] if a.path == "persistent" else "k_plain"),
                      "launches": split[dom]["launches"], "batches_per_launch": a.steps / max(split[dom]["launches"], 1),
                      "kernel_ms": split[dom]["ms"], "visits": split[dom]["visits"],
                      "bytes_per_visit": BYTES_PER_VISIT,
                      "upar_trials_per_scattering": tot["upar_trials"] / max(tot["n_res"], 1)},
         "kernels": split,
+        # the step ends when its longest packet history does: a few packets per
+        # million scatter 1e4-1e6 times near line centre, and the last of them
+        # run alone, one lane's serial chain of interactions each
+        "longest_history": {"events": tot["max_events"],
+                            "us_per_event_if_alone_for_the_step": dt * 1e6 / max(tot["max_events"], 1),
+                            "tail_kernel_ms": tot.get("tail_ms", 0.0), "tail_events": tot.get("tail_events", 0)},
     }
     rec = counter_record("shell%d" % a.grid) if (a.path == "persistent" and a.precision == "mixed") else None
     if rec is not None:

@@ -201,6 +201,13 @@ typedef struct {
                                        peel seeds: summed per pass; otherwise = kernel_ms) */
     double peel_ms;                 /* of which peel-pass kernels */
     uint64_t passes;                /* transport + peel pass rounds (1 without seeds) */
+    double tail_ms;                 /* of transport_ms, the tail kernels (packets handed off
+                                       by drained waves, see wide_lanes) */
+    uint64_t max_events;            /* longest finished history of the call (interactions;
+                                       plain and unbounded persistent calls) */
+    uint64_t tail_events;           /* interactions run by the tail kernels (in n_res, n_dust) */
+    uint64_t tail_main_visits;      /* main-march cell visits of the tail kernels */
+    uint64_t tail_peel_visits;      /* peel cell visits of the tail kernels */
 } thor_stats;
 
 /* Per-packet record (index = packet id - first id of its batch, batches in

@@ -92,6 +92,24 @@ enum : uint32_t { kSlotType = 0, kSlotUperp = 1, kSlotMu = 2, kSlotTau = 3, kSlo
 
 // Division: IEEE in FP64; reciprocal-based (about 1 ulp) in the FP32 path.
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+
+// FP64 reciprocal from the hardware estimate and two Newton steps (within
+// 1 ulp): the mixed path's inverse directions and interaction distances.
+__device__ __forceinline__ double rcp64(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    r = fma(r, fma(-b, r, 1.0), r);
+    return fma(r, fma(-b, r, 1.0), r);
+}
+// a / b in the FP64 quantities of the mixed path: a * (1/b) with one
+// residual correction; IEEE division in the FP64 path.
+template <class R> __device__ __forceinline__ double div_tau(double a, double b) {
+    if constexpr (sizeof(R) == 8) {
+        return a / b;
+    } else {
+        const double q = a * rcp64(b);
+        return fma(rcp64(b), fma(-b, q, a), q);
+    }
+}
 __device__ __forceinline__ float fdiv(float a, float b) { return __fdividef(a, b); }
 
 // ---------------------------------------------------------------------------
@@ -624,6 +642,7 @@ struct Counters {
     uint32_t emitted, escaped, absorbed, capped, handed_off, n_res, n_dust;
     uint32_t peel_contrib, peel_dropped, peel_cut;
     uint64_t main_visits, peel_visits, upar_trials;
+    uint32_t max_events;    // longest finished history (interactions)
 };
 constexpr int kNumU64Counters = 13;
 

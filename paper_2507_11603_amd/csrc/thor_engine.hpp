@@ -541,7 +541,7 @@ template <class R> struct PeelJob {
     int c[3];
     int ob;
     Fields<R> f;
-    double w;
+    R pv;          // phase function value; the weight is pv / 2 pi
     R dvp;
 };
 template <class R> struct JobSink {
@@ -740,12 +740,12 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
                     double kd[3];
                     obs_dir(o.obs_axis[ob], kd);
                     const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
-                    const double c = double(phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg))) / (2.0 * kPi);
+                    const R pv = phase_value<R>(kPhaseHG, dot3<R>(pk.k, ko), R(m.g_hg));
                     if constexpr (PRE) {
-                        js->jobs[js->n++] = PeelJob<R>{{L.p[0], L.p[1], L.p[2]}, {L.c[0], L.c[1], L.c[2]}, ob, f, c,
+                        js->jobs[js->n++] = PeelJob<R>{{L.p[0], L.p[1], L.p[2]}, {L.c[0], L.c[1], L.c[2]}, ob, f, pv,
                                                        R(dvl + dot3<R>(f.v, ko))};
                     } else {
-                        seed_emit<R>(g, o, L, f, ob, c, dvl + dot3<R>(f.v, ko), cnt, *sb, *sl);
+                        seed_emit<R>(g, o, L, f, ob, double(pv) / (2.0 * kPi), dvl + dot3<R>(f.v, ko), cnt, *sb, *sl);
                     }
                 }
             });
@@ -805,13 +805,14 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
                     double kd[3];
                     obs_dir(o.obs_axis[ob], kd);
                     const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
-                    const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
+                    const R pv = phase_value<R>(ph, dot3<R>(pk.k, ko), R(0));
                     const R xo = x_atom + dot3<R>(u, ko);
                     if constexpr (PRE) {
-                        js->jobs[js->n++] = PeelJob<R>{{L.p[0], L.p[1], L.p[2]}, {L.c[0], L.c[1], L.c[2]}, ob, f, c,
+                        js->jobs[js->n++] = PeelJob<R>{{L.p[0], L.p[1], L.p[2]}, {L.c[0], L.c[1], L.c[2]}, ob, f, pv,
                                                        R(xo * f.vth + dot3<R>(f.v, ko))};
                     } else {
-                        seed_emit<R>(g, o, L, f, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt, *sb, *sl);
+                        seed_emit<R>(g, o, L, f, ob, double(pv) / (2.0 * kPi), xo * f.vth + dot3<R>(f.v, ko), cnt,
+                                     *sb, *sl);
                     }
                 }
             });
@@ -869,7 +870,7 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
     auto set_inverse = [&]() {
         if constexpr (sizeof(R) == 4) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) ik[i] = pk.k[i] != R(0) ? 1.0 / double(pk.k[i]) : 0.0;
+            for (int i = 0; i < 3; ++i) ik[i] = pk.k[i] != R(0) ? rcp64(double(pk.k[i])) : 0.0;
         }
     };
     set_inverse();
@@ -901,7 +902,7 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
                 if (sl->left < uint32_t(o.n_obs)) break;
             }
             // interaction site where tau_current = tau_target along the step
-            const double s = (pk.tau_t - pk.tau_a) / kt;
+            const double s = div_tau<R>(pk.tau_t - pk.tau_a, kt);
 #pragma unroll
             for (int i = 0; i < 3; ++i) L.p[i] += s * double(pk.k[i]);
             pk.event++;
@@ -960,6 +961,7 @@ __device__ void finish(const GridDev& g, const ModelDev& m, const OutDev& o, con
         o.rec_fate[r] = fate;
     }
     if (m.done) atomicAdd(m.done, 1ull);
+    cnt.max_events = pk.event > cnt.max_events ? pk.event : cnt.max_events;
 }
 
 // ----------------------------------------------------------------- counters
@@ -969,7 +971,10 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
     return v;
 }
 
-__device__ __forceinline__ void flush_counters(const Counters& c, unsigned long long* g) {
+// Sums of the lanes' counters into g (one atomic per counter and wave); the
+// longest history into *gmax when given.
+__device__ __forceinline__ void flush_counters(const Counters& c, unsigned long long* g,
+                                               unsigned long long* gmax = nullptr) {
     const uint64_t vals[kNumU64Counters] = {c.emitted, c.escaped, c.absorbed, c.capped, c.handed_off,
                                             c.n_res, c.n_dust, c.main_visits, c.peel_visits,
                                             c.peel_contrib, c.peel_dropped, c.peel_cut, c.upar_trials};
@@ -978,6 +983,15 @@ __device__ __forceinline__ void flush_counters(const Counters& c, unsigned long 
     for (int i = 0; i < kNumU64Counters; ++i) {
         const uint64_t s = wave_sum_u64(vals[i]);
         if (lane == 0 && s) atomicAdd(g + i, (unsigned long long)s);
+    }
+    if (gmax) {
+        uint32_t mx = c.max_events;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t o = __shfl_xor(mx, off, 64);
+            mx = o > mx ? o : mx;
+        }
+        if (lane == 0 && mx) atomicMax(gmax, (unsigned long long)mx);
     }
 }
 

@@ -27,7 +27,7 @@ __constant__ float c_dawson32[kDawsonIntervals * (kDawsonDeg32 + 1)];
 // Plain path: one thread per packet, the whole history in one launch.
 template <class R, bool GRID>
 __global__ __launch_bounds__(256) void k_plain(GridDev g, const ModelDev* __restrict__ models, BatchDev b, OutDev o,
-                                               unsigned long long* gstats) {
+                                               unsigned long long* gstats, unsigned long long* gmax) {
     const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     Counters cnt = {};
     if (i < b.n) {
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_plain(GridDev g, const ModelDev* __rest
         while (fate == kFateNone) fate = advance<R, GRID>(g, m, o, pk, cnt, ~0u, ~0u, &ev);
         finish<R, GRID>(g, m, o, pk, fate, cnt);
     }
-    flush_counters(cnt, gstats);
+    flush_counters(cnt, gstats, gmax);
 }
 
 // Pool of packets parked between bounded persistent steps (one slot per lane).
@@ -87,7 +87,8 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
                                                     const BatchDev* __restrict__ batches,
                                                     const StepDesc* __restrict__ desc,
                                                     unsigned long long* cursor, OutDev o, PoolDev<R> pool,
-                                                    TailDev<R> tail, SeedBuf sb, unsigned long long* gstats) {
+                                                    TailDev<R> tail, SeedBuf sb, unsigned long long* gstats,
+                                                    unsigned long long* gmax) {
     const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t q_end = desc->q_end;
     const int nbatch = desc->nbatch;
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
         pool.alive[gid] = active ? 1 : 0;
         if (active) pool.pk[gid] = pk;
     }
-    flush_counters(cnt, gstats);
+    flush_counters(cnt, gstats, gmax);
 }
 
 // Tail of a persistent launch: the packets handed off by waves whose queue
@@ -222,7 +223,8 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
 template <class R, bool GRID, bool SEEDS>
 __global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restrict__ models,
                                              const StepDesc* __restrict__ desc, OutDev o, PoolDev<R> pool,
-                                             TailDev<R> tail, SeedBuf sb, unsigned long long* gstats) {
+                                             TailDev<R> tail, SeedBuf sb, unsigned long long* gstats,
+                                             unsigned long long* gmax) {
     constexpr bool useq = GRID && SEEDS;
     __shared__ EventDraws<R> wd[64];
     __shared__ PeelJob<R> wj[useq ? 64 : 1];
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restri
 #pragma unroll
                     for (int k = 0; k < 3; ++k) { L.p[k] = j.p[k]; L.c[k] = j.c[k]; }
                     L.region = kRegGas;
-                    keep = seed_make<R>(g, o, L, j.f, j.ob, j.w, j.dvp, cnt, sd);
+                    keep = seed_make<R>(g, o, L, j.f, j.ob, double(j.pv) / (2.0 * kPi), j.dvp, cnt, sd);
                 }
                 const uint64_t km = __ballot(keep);
                 if (keep) sb.s[base + lane_rank(km)] = sd;
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restri
         }
     }
     if (useq && stalled && lane == 0) atomicAdd(sb.parked, 1ull);
-    flush_counters(cnt, gstats);
+    flush_counters(cnt, gstats, gmax);
 }
 
 // Peel pass: marches the rays appended by the transport kernel.  Each wave
@@ -668,6 +670,7 @@ struct thor_ctx {
     uint64_t cube_elems = 0;
     int cube_shape[4] = {0, 0, 0, 0};
     unsigned long long* d_stats = nullptr;   // kNumU64Counters counters, then cursor
+    unsigned long long* d_xstats = nullptr;  // longest history, then the tail kernel's counters
     ModelDev* d_models = nullptr;
     size_t models_cap = 0;
     BatchDev* d_batches = nullptr;
@@ -709,7 +712,9 @@ struct thor_ctx {
     uint64_t seed_cap = 0;                 // slots
     unsigned long long* d_seedctl = nullptr;   // claimed slots, parked waves, then kXcds pass work counters
     hipEvent_t ev_a = nullptr, ev_b = nullptr;  // per-step split of transport and peel-pass time
+    hipEvent_t ev_c = nullptr;                  // end of the persistent kernel (the tail kernel follows)
     double split_tr = 0.0, split_pp = 0.0;     // ms of the last call's transport and peel-pass kernels
+    double split_tail = 0.0;                   // ms of the last call's tail kernels (part of split_tr)
     uint64_t split_passes = 0;
     hipGraphExec_t s_graph = nullptr;
     int s_graph_prec = -1, s_graph_grid = 0, s_graph_block = 0;
@@ -934,7 +939,7 @@ template <class R, bool GRID>
 void launch_plain(thor_ctx* ctx, const BatchDev& b, const OutDev& out) {
     const unsigned blocks = unsigned((b.n + 255) / 256);
     hipLaunchKernelGGL((k_plain<R, GRID>), dim3(blocks), dim3(256), 0, ctx->stream, ctx->grid, ctx->d_models, b,
-                       out, ctx->d_stats);
+                       out, ctx->d_stats, ctx->d_xstats);
 }
 
 template <class R>
@@ -948,17 +953,17 @@ template <class R, bool GRID>
 void launch_persistent(thor_ctx* ctx, hipStream_t stream, int grid, int block, const BatchDev* d_b,
                        const StepDesc* d_desc, unsigned long long* cursor, const OutDev& out,
                        const ModelDev* d_models, void* pool_pk, int* pool_alive, const SeedBuf& sb,
-                       bool hand_off = false) {
+                       bool hand_off = false, unsigned long long* gmax = nullptr) {
     PoolDev<R> pool{reinterpret_cast<Pkt<R>*>(pool_pk), pool_alive};
     const TailDev<R> tail = tail_dev<R>(ctx, hand_off);
     bool seeds = false;
     if constexpr (GRID) seeds = sb.s != nullptr;
     if (seeds)
         hipLaunchKernelGGL((k_persistent<R, GRID, GRID>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
-                           d_b, d_desc, cursor, out, pool, tail, sb, ctx->d_stats);
+                           d_b, d_desc, cursor, out, pool, tail, sb, ctx->d_stats, gmax);
     else
         hipLaunchKernelGGL((k_persistent<R, GRID, false>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
-                           d_b, d_desc, cursor, out, pool, tail, sb, ctx->d_stats);
+                           d_b, d_desc, cursor, out, pool, tail, sb, ctx->d_stats, gmax);
 }
 
 // The tail kernel over what the preceding persistent launch handed off (its
@@ -972,10 +977,10 @@ void launch_tail(thor_ctx* ctx, const StepDesc* d_desc, const OutDev& out, void*
     if constexpr (GRID) seeds = sb.s != nullptr;
     if (seeds)
         hipLaunchKernelGGL((k_tail<R, GRID, GRID>), dim3(ctx->num_cu * 4), dim3(64), 0, ctx->stream, ctx->grid,
-                           ctx->d_models, d_desc, out, pool, tail, sb, ctx->d_stats);
+                           ctx->d_models, d_desc, out, pool, tail, sb, ctx->d_xstats + 1, ctx->d_xstats);
     else
         hipLaunchKernelGGL((k_tail<R, GRID, false>), dim3(ctx->num_cu * 4), dim3(64), 0, ctx->stream, ctx->grid,
-                           ctx->d_models, d_desc, out, pool, tail, sb, ctx->d_stats);
+                           ctx->d_models, d_desc, out, pool, tail, sb, ctx->d_xstats + 1, ctx->d_xstats);
 }
 
 // Tail list of `slots` packets of either precision.
@@ -1093,8 +1098,10 @@ thor_status thor_create(thor_ctx** out, int hip_device, void* hip_stream, uint64
         hipMemcpyToSymbol(HIP_SYMBOL(c_dawson32), t32, sizeof t32) != hipSuccess)
         s = fail(THOR_E_DEVICE, "Dawson table upload failed");
     if (!s) s = dalloc(ctx, (void**)&ctx->d_stats, (kNumU64Counters + 1) * 8, "counters");
+    if (!s) s = dalloc(ctx, (void**)&ctx->d_xstats, (kNumU64Counters + 1) * 8, "tail counters");
     if (!s && (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
-               hipEventCreate(&ctx->ev_a) != hipSuccess || hipEventCreate(&ctx->ev_b) != hipSuccess))
+               hipEventCreate(&ctx->ev_a) != hipSuccess || hipEventCreate(&ctx->ev_b) != hipSuccess ||
+               hipEventCreate(&ctx->ev_c) != hipSuccess))
         s = fail(THOR_E_DEVICE, "hipEventCreate failed");
     if (!s) s = dalloc(ctx, (void**)&ctx->d_desc, sizeof(StepDesc), "step descriptor");
     if (!s && hipHostMalloc((void**)&ctx->h_desc, sizeof(StepDesc)) != hipSuccess)
@@ -1116,7 +1123,7 @@ void thor_destroy(thor_ctx* ctx) {
                     ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done,
                     ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
                     ctx->d_seeds, ctx->d_seedctl, ctx->d_axr[0], ctx->d_axr[1], ctx->d_axr[2],
-                    ctx->d_tail_pk, ctx->d_tail_home, ctx->d_tailctl};
+                    ctx->d_tail_pk, ctx->d_tail_home, ctx->d_tailctl, ctx->d_xstats};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& kv : ctx->s_reqs)
@@ -1133,6 +1140,7 @@ void thor_destroy(thor_ctx* ctx) {
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
     if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
+    if (ctx->ev_c) (void)hipEventDestroy(ctx->ev_c);
     delete ctx;
 }
 
@@ -1369,6 +1377,7 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
     } else {
         HIPCHK(ctx, hipMemsetAsync(ctx->d_stats, 0, kNumU64Counters * 8, ctx->stream));
     }
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_xstats, 0, (kNumU64Counters + 1) * 8, ctx->stream));
     if (grid && opt->path == THOR_PATH_PERSISTENT && !fp64 && opt->n_obs > 0 && opt->n_obs <= kMaxSeedObs &&
         !opt->inline_peel) {
         for (int i = 0; i < opt->n_obs; ++i) {
@@ -1378,6 +1387,7 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
     }
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     ctx->split_passes = 0;
+    ctx->split_tail = 0.0;
     if (opt->path == THOR_PATH_PLAIN) {
         for (size_t i = 0; i < nb; ++i) {
             if (fp64) grid ? launch_plain<double, true>(ctx, batches[i], out) : launch_plain<double, false>(ctx, batches[i], out);
@@ -1429,28 +1439,39 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
             hipLaunchKernelGGL(k_zero_u32, dim3(ctx->num_cu), dim3(256), 0, ctx->stream,
                                reinterpret_cast<unsigned*>(ctx->d_pool_alive), ctx->pool_slots);
         unsigned long long* cur = ctx->d_stats + kNumU64Counters;
-        double t_tr = 0.0, t_pp = 0.0;
+        double t_tr = 0.0, t_pp = 0.0, t_tail = 0.0;
         uint64_t passes = 0;
         for (;;) {
-            if (seeds) {
+            if (seeds)
                 hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_seedctl, 2 + kXcds);
-                HIPCHK(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
-            }
             if (hand_off)
                 hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_tailctl, 3);
-            if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off)
-                           : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off);
-            else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off)
-                      : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off);
+            if (seeds || hand_off) HIPCHK(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
+            if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats)
+                           : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats);
+            else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats)
+                      : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats);
             if (hand_off) {
+                HIPCHK(ctx, hipEventRecord(ctx->ev_c, ctx->stream));
                 if (fp64) grid ? launch_tail<double, true>(ctx, ctx->d_desc, out, ppk, pal, sb)
                                : launch_tail<double, false>(ctx, ctx->d_desc, out, ppk, pal, sb);
                 else grid ? launch_tail<float, true>(ctx, ctx->d_desc, out, ppk, pal, sb)
                           : launch_tail<float, false>(ctx, ctx->d_desc, out, ppk, pal, sb);
             }
             hipLaunchKernelGGL(k_clamp_cursor, dim3(1), dim3(64), 0, ctx->stream, cur, ctx->d_desc);
-            if (!seeds) break;
-            HIPCHK(ctx, hipEventRecord(ctx->ev_b, ctx->stream));
+            if (seeds || hand_off) HIPCHK(ctx, hipEventRecord(ctx->ev_b, ctx->stream));
+            if (!seeds) {
+                if (hand_off) {
+                    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+                    float ms_tl = 0.0f, ms_tr = 0.0f;
+                    HIPCHK(ctx, hipEventElapsedTime(&ms_tr, ctx->ev_a, ctx->ev_b));
+                    HIPCHK(ctx, hipEventElapsedTime(&ms_tl, ctx->ev_c, ctx->ev_b));
+                    ctx->split_tr = ms_tr;
+                    ctx->split_tail = ms_tl;
+                    ctx->split_passes = 1;
+                }
+                break;
+            }
             if (fp64) launch_peel_pass<double>(ctx, out, sb);
             else launch_peel_pass<float>(ctx, out, sb);
             HIPCHK(ctx, hipGetLastError());
@@ -1463,20 +1484,28 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
             HIPCHK(ctx, hipEventElapsedTime(&ms_pp, ctx->ev_b, ctx->ev1));
             t_tr += ms_tr;
             t_pp += ms_pp;
+            if (hand_off) {
+                float ms_tl = 0.0f;
+                HIPCHK(ctx, hipEventElapsedTime(&ms_tl, ctx->ev_c, ctx->ev_b));
+                t_tail += ms_tl;
+            }
             ++passes;
             if (ctl[1] == 0) break;     // no wave stopped on a full buffer
         }
         if (seeds) {
             ctx->split_tr = t_tr;
             ctx->split_pp = t_pp;
+            ctx->split_tail = t_tail;
             ctx->split_passes = passes;
         }
     }
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
-    unsigned long long h[kNumU64Counters + 1];
+    unsigned long long h[kNumU64Counters + 1], hx[kNumU64Counters + 1];
     HIPCHK(ctx, hipMemcpyAsync(h, ctx->d_stats, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(hx, ctx->d_xstats, sizeof hx, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < kNumU64Counters; ++i) h[i] += hx[1 + i];      // the tail kernel's share
     float ms = 0.0f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     if (!ctx->split_passes) {       // one kernel type: all device time is transport
@@ -1488,6 +1517,11 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
     ctx->last.transport_ms = ctx->split_tr;
     ctx->last.peel_ms = ctx->split_pp;
     ctx->last.passes = ctx->split_passes;
+    ctx->last.tail_ms = ctx->split_tail;
+    ctx->last.max_events = hx[0];
+    ctx->last.tail_events = hx[1 + 5] + hx[1 + 6];          // n_res + n_dust
+    ctx->last.tail_main_visits = hx[1 + 7];
+    ctx->last.tail_peel_visits = hx[1 + 8];
     if (out_stats) *out_stats = ctx->last;
     if (bounded) {
         // work left: queue not drained or packets parked in the pool

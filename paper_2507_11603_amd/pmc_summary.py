@@ -30,7 +30,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/thor_lib.hip", "csrc/thor_engine.hpp", "csrc/thor_device.hpp"]
-KERNELS = ("k_persistent", "k_peel_pass")
+KERNELS = ("k_persistent", "k_tail", "k_peel_pass")
 
 
 def source_hash() -> str:

@@ -78,7 +78,9 @@ STAT_U64 = ("emitted", "escaped", "absorbed", "capped", "handed_off", "n_res", "
 class thor_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in STAT_U64] + [
         ("w_escaped", C.c_double), ("w_absorbed", C.c_double), ("kernel_ms", C.c_double),
-        ("transport_ms", C.c_double), ("peel_ms", C.c_double), ("passes", C.c_uint64)]
+        ("transport_ms", C.c_double), ("peel_ms", C.c_double), ("passes", C.c_uint64),
+        ("tail_ms", C.c_double), ("max_events", C.c_uint64), ("tail_events", C.c_uint64),
+        ("tail_main_visits", C.c_uint64), ("tail_peel_visits", C.c_uint64)]
 
     def to_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -248,6 +248,14 @@ def test_wide_turns_same_histories(T, precision):
          % (a["records"]["n_res"].max(), a["stats"]["kernel_ms"], runs[16]["stats"]["kernel_ms"],
             runs[1]["stats"]["kernel_ms"]))
     assert a["records"]["n_res"].max() > 10000
+    # the longest history (interactions, the absorbing one included), and the
+    # tail kernel's share of the interactions
+    rec = a["records"]
+    ev = rec["n_res"].astype(np.int64) + rec["n_dust"] + (rec["fate"] == 2)
+    for w in (-1, 16, 1):
+        assert runs[w]["stats"]["max_events"] == ev.max(), w
+    assert runs[-1]["stats"]["tail_events"] == 0 and runs[-1]["stats"]["tail_ms"] == 0.0
+    assert 0 < runs[16]["stats"]["tail_events"] <= a["stats"]["n_res"] + a["stats"]["n_dust"]
     for w in (16, 1):
         b = runs[w]
         for k in ("n_res", "n_dust", "fate", "dv"):
