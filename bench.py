@@ -28,7 +28,8 @@ BYTES_PER_VISIT = 20.0         # (vx, vy, vz, n_HI, T) float32 per cell visit
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100,
+                    help="batches of 1e6 packets transported by one call (one persistent launch)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=int, default=1_000_000)
     ap.add_argument("--grid", type=int, default=128)
@@ -40,7 +41,8 @@ def parse():
     ap.add_argument("--turn-visits", type=int, default=0)
     ap.add_argument("--inline-peel", type=int, default=0, help="march peel rays in the scattering lane")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=400000, help="packets of the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=3_000_000,
+                    help="packets of the oracle sample (ids 0..n-1; about 20 s on 16 host cores)")
     ap.add_argument("--autotune", type=int, default=1, help="pick launch knobs with the autotuner")
     ap.add_argument("--serving", type=int, default=300, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serving-warmup", type=int, default=60)
