@@ -170,11 +170,12 @@ __device__ __forceinline__ double dawson64(double ax) {
     return fma(r1, s8, r0);
 }
 
-__device__ __forceinline__ float dawson32(float ax) {
+// `tab`: the FP32 coefficient table (c_dawson32, or a copy of it in LDS)
+__device__ __forceinline__ float dawson32(float ax, const float* tab) {
     int i = int(ax * 8.0f);
     i = i < kDawsonIntervals - 1 ? i : kDawsonIntervals - 1;
     const float s = (ax - (float(i) + 0.5f) * 0.125f) * 16.0f;
-    const float* c = c_dawson32 + i * (kDawsonDeg32 + 1);
+    const float* c = tab + i * (kDawsonDeg32 + 1);
     const float s2 = s * s, s4 = s2 * s2;
     const float p01 = fmaf(c[1], s, c[0]), p23 = fmaf(c[3], s, c[2]), p45 = fmaf(c[5], s, c[4]);
     return fmaf(fmaf(c[6], s2, p45), s4, fmaf(p23, s2, p01));
@@ -216,12 +217,12 @@ __device__ __forceinline__ double voigt64(double a, double x) {
     return h;
 }
 
-__device__ __forceinline__ float voigt32(float a, float x) {
+__device__ __forceinline__ float voigt32(float a, float x, const float* tab = c_dawson32) {
     const float ax = fabsf(x);
     constexpr float two_rsqpi = float(2.0 / kSqrtPi);
     if (ax <= 6.5f) {
         const float e = __expf(-ax * ax);
-        float wr_p = e, wi_p = two_rsqpi * dawson32(ax);
+        float wr_p = e, wi_p = two_rsqpi * dawson32(ax, tab);
         float wr = -2.0f * ax * wr_p, wi = fmaf(-2.0f * ax, wi_p, two_rsqpi);
         // n = 1: Re(i a w') = -a Im w'
         float sum = fmaf(-a, wi, wr_p);
@@ -426,11 +427,11 @@ __device__ __forceinline__ float upar_sample32(float x, float a, const Key& key,
     float u = 0.0f;
     if (!(xa < 1e30f) || !(a > 0.0f)) { *trials = 0; return 0.0f; }
     if (xa < float(kUparSwitch)) {
-        // any split in [0, xa] keeps the sampler exact, so its iteration
-        // runs on fast (approximate) exp and sqrt
+        // any split in [0, xa] keeps the sampler exact: one step of the
+        // iteration, on fast (approximate) exp and sqrt, gives the same
+        // expected number of proposals as two (within 0.4 % for xa < 2.25)
         float u0 = xa;
-        for (int it = 0; it < 2; ++it) {
-            if (u0 <= 0.0f) break;
+        if (u0 > 0.0f) {
             u0 = xa - __builtin_amdgcn_sqrtf(__fdividef(a * (__expf(u0 * u0) - 1.0f), 2.0f * pi * u0));
             u0 = fminf(fmaxf(u0, 0.0f), xa);
         }

@@ -850,12 +850,13 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
 // (kFateNone while it lives on); the packet state is complete on return, so
 // a later call resumes it exactly.  PRE: `pre` holds the draws of events
 // pre_event, pre_event + 1, ... evaluated ahead; max_events must not run
-// past them.
+// past them; `dtab` is the FP32 Dawson table to read (an LDS copy).
 template <class R, bool GRID, bool Q = false, bool PRE = false>
 __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt,
                        uint32_t max_visits, uint32_t max_events, uint32_t* events_done,
                        const SeedBuf* sb = nullptr, SeedLane* sl = nullptr, CellCache<R>* ccp = nullptr,
-                       const EventDraws<R>* pre = nullptr, uint32_t pre_event = 0, JobSink<R>* js = nullptr) {
+                       const EventDraws<R>* pre = nullptr, uint32_t pre_event = 0, JobSink<R>* js = nullptr,
+                       const float* dtab = nullptr) {
     const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
     Loc L;
 #pragma unroll
@@ -893,7 +894,8 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
         double kt = 0.0;
         if (f.k0 > 0.0 || f.kd > 0.0) {
             const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
-            kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+            if constexpr (PRE && sizeof(R) == 4) kt = f.k0 * double(voigt32(f.a, x, dtab)) + f.kd;
+            else kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
         }
         if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) {
             if constexpr (Q && !PRE) {

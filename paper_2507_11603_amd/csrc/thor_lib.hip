@@ -226,9 +226,15 @@ __global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restri
                                              TailDev<R> tail, SeedBuf sb, unsigned long long* gstats,
                                              unsigned long long* gmax) {
     constexpr bool useq = GRID && SEEDS;
+    constexpr int kDaw = kDawsonIntervals * (kDawsonDeg32 + 1);
     __shared__ EventDraws<R> wd[64];
     __shared__ PeelJob<R> wj[useq ? 64 : 1];
+    __shared__ float daw[kDaw];          // the FP32 Dawson table, read on the serial chain
     const int lane = int(threadIdx.x);
+    for (int k = lane; k < kDaw; k += 64) daw[k] = c_dawson32[k];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const uint64_t n = *tail.count;
     const uint32_t turn_visits = desc->turn_visits;
     // events per turn: at most one peel ray per lane
@@ -275,7 +281,7 @@ __global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restri
             if (lane == 0) {
                 uint32_t used = 0;
                 fate = advance<R, GRID, useq, true>(g, m, o, pk, cnt, turn_visits, per, &used, &sb, &sl, &cc, wd,
-                                                    pk.event + 1u, &js);
+                                                    pk.event + 1u, &js, daw);
             }
             fate = __shfl(fate, 0, 64);
             pk.event = __shfl(pk.event, 0, 64);
