@@ -327,8 +327,33 @@ __global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restri
 // marching while their neighbours' rays are long.  A ray advances
 // THOR_PEEL_LOOKAHEAD cells per round with their records fetched together;
 // segment lengths and the order of the tau sum are those of the serial march.
+// Contributions are summed per cube element in an LDS table of the workgroup
+// first and reach the cube once per element at the end (a point source
+// sends every emission ray to the same few elements).
 constexpr uint32_t kPassChunk = 1024;
 constexpr uint32_t kXcds = 8;           // accelerator complex dies of an MI355X
+constexpr uint32_t kAggSlots = 512;     // LDS sums per workgroup (power of two)
+constexpr int kAggProbes = 4;
+
+// Adds v to cube element ci through the workgroup's LDS table (keys: element
+// + 1, 0 = free; short linear probing); a crowded table passes v straight to
+// the cube.
+__device__ __forceinline__ void deposit_lds(uint32_t* keys, float* vals, float* cube, uint64_t ci, float v) {
+    if (ci < 0xFFFFFFFFull) {
+        const uint32_t k = uint32_t(ci) + 1u;
+        uint32_t h = (k * 2654435761u) & (kAggSlots - 1u);
+        for (int p = 0; p < kAggProbes; ++p) {
+            uint32_t cur = __hip_atomic_load(keys + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (cur == 0u) cur = atomicCAS(keys + h, 0u, k);
+            if (cur == 0u || cur == k) {
+                __hip_atomic_fetch_add(vals + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return;
+            }
+            h = (h + 1u) & (kAggSlots - 1u);
+        }
+    }
+    unsafeAtomicAdd(cube + ci, v);
+}
 
 template <class R>
 __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, const SeedBuf& sb,
@@ -350,6 +375,13 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
     R dvp = R(0);
     uint64_t cur = 0, end = 0;             // the wave's chunk, [cur, end)
     const uint32_t xcd = blockIdx.x % kXcds; // workgroups are dealt round-robin over the XCDs
+    __shared__ uint32_t agg_key[kAggSlots];
+    __shared__ float agg_val[kAggSlots];
+    for (uint32_t i = threadIdx.x; i < kAggSlots; i += blockDim.x) {
+        agg_key[i] = 0u;
+        agg_val[i] = 0.0f;
+    }
+    __syncthreads();
     uint32_t part = 0;
     for (;;) {
         uint64_t m = __ballot(!have);
@@ -472,11 +504,14 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
                 cnt.peel_cut++;
                 have = false;
             } else if (mm == left) {
-                unsafeAtomicAdd(o.cube + ci, float(w * exp(-tau)));
+                deposit_lds(agg_key, agg_val, o.cube, ci, float(w * exp(-tau)));
                 have = false;
             }
         }
     }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kAggSlots; i += blockDim.x)
+        if (agg_key[i]) unsafeAtomicAdd(o.cube + (agg_key[i] - 1u), agg_val[i]);
     flush_counters(cnt, gstats);
 }
 
