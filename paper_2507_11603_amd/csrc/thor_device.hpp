@@ -596,6 +596,7 @@ struct ModelDev {
     uint32_t seed, req;
     double* spec;               // escape spectrum of this model
     int spec_nb;
+    int spec_rep;               // copies of it (workgroup b adds into copy b mod spec_rep), folded after the call
     double spec_lo, spec_w, spec_scale;
     unsigned long long* done;   // packets finished (escaped, absorbed, capped)
 };

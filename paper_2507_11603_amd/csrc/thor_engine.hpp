@@ -949,7 +949,7 @@ __device__ void finish(const GridDev& g, const ModelDev& m, const OutDev& o, con
         cnt.escaped++;
         if (GRID && g.handoff) cnt.handed_off++;
         const int b = bin_of(double(pk.dv) * m.spec_scale, m.spec_lo, m.spec_w, m.spec_nb);
-        if (b >= 0) unsafeAtomicAdd(m.spec + b, 1.0);
+        if (b >= 0) unsafeAtomicAdd(m.spec + uint64_t(blockIdx.x % uint32_t(m.spec_rep)) * uint32_t(m.spec_nb) + b, 1.0);
     } else if (fate == kFateAbsorbed) {
         cnt.absorbed++;
     } else if (fate == kFateCapped) {

@@ -331,6 +331,7 @@ __global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restri
 // first and reach the cube once per element at the end (a point source
 // sends every emission ray to the same few elements).
 constexpr uint32_t kPassChunk = 1024;
+constexpr uint32_t kSpecCopies = 32;    // escape spectrum copies of a transport call
 constexpr uint32_t kXcds = 8;           // accelerator complex dies of an MI355X
 constexpr uint32_t kAggSlots = 512;     // LDS sums per workgroup (power of two)
 constexpr int kAggProbes = 4;
@@ -607,6 +608,19 @@ __global__ void k_clamp_cursor(unsigned long long* cursor, const StepDesc* desc)
     if (threadIdx.x == 0 && *cursor > desc->q_end) *cursor = desc->q_end;
 }
 
+// Adds copies 1..copies-1 of the escape spectrum into copy 0 and clears them
+// (sums of unit weights: exact in FP64, in any order).
+__global__ void k_spec_fold(double* spec, int nb, int copies) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+        double s = spec[i];
+        for (int c = 1; c < copies; ++c) {
+            s += spec[uint64_t(c) * nb + i];
+            spec[uint64_t(c) * nb + i] = 0.0;
+        }
+        spec[i] = s;
+    }
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int n) {
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
@@ -868,6 +882,7 @@ thor_status make_model(thor_ctx* ctx, const thor_source& s, const thor_transport
     }
     m.spec = ctx->d_spec;
     m.spec_nb = o.spec_nb;
+    m.spec_rep = int(kSpecCopies);
     m.spec_lo = o.spec_lo;
     m.spec_w = (o.spec_hi - o.spec_lo) / o.spec_nb;
     m.spec_scale = 1.0;
@@ -903,13 +918,13 @@ thor_status check_opts(const thor_transport_opts* o) {
 
 thor_status ensure_outputs(thor_ctx* ctx, const thor_transport_opts* o) {
     if (o->spec_nb != ctx->spec_nb) {
-        dfree(ctx, ctx->d_spec, uint64_t(ctx->spec_nb) * 8);
+        dfree(ctx, ctx->d_spec, uint64_t(ctx->spec_nb) * 8 * kSpecCopies);
         ctx->d_spec = nullptr;
         ctx->spec_nb = 0;
-        thor_status s = dalloc(ctx, (void**)&ctx->d_spec, uint64_t(o->spec_nb) * 8, "spectrum");
+        thor_status s = dalloc(ctx, (void**)&ctx->d_spec, uint64_t(o->spec_nb) * 8 * kSpecCopies, "spectrum");
         if (s) return s;
         ctx->spec_nb = o->spec_nb;
-        HIPCHK(ctx, hipMemsetAsync(ctx->d_spec, 0, uint64_t(o->spec_nb) * 8, ctx->stream));
+        HIPCHK(ctx, hipMemsetAsync(ctx->d_spec, 0, uint64_t(o->spec_nb) * 8 * kSpecCopies, ctx->stream));
     }
     const int shape[4] = {o->n_obs, o->cube_ny, o->cube_nx, o->cube_nb};
     if (std::memcmp(shape, ctx->cube_shape, sizeof shape) != 0) {
@@ -1344,7 +1359,8 @@ thor_status thor_emit(thor_ctx* ctx, const thor_source* src, uint64_t n_packets,
 
 thor_status thor_reset_outputs(thor_ctx* ctx) {
     CHECK_CTX(ctx);
-    if (ctx->d_spec) HIPCHK(ctx, hipMemsetAsync(ctx->d_spec, 0, uint64_t(ctx->spec_nb) * 8, ctx->stream));
+    if (ctx->d_spec)
+        HIPCHK(ctx, hipMemsetAsync(ctx->d_spec, 0, uint64_t(ctx->spec_nb) * 8 * kSpecCopies, ctx->stream));
     if (ctx->d_cube) HIPCHK(ctx, hipMemsetAsync(ctx->d_cube, 0, ctx->cube_elems * 4, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return THOR_OK;
@@ -1540,6 +1556,8 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
             ctx->split_passes = passes;
         }
     }
+    hipLaunchKernelGGL(k_spec_fold, dim3(std::max(1, std::min(ctx->num_cu, (ctx->spec_nb + 255) / 256))), dim3(256),
+                       0, ctx->stream, ctx->d_spec, ctx->spec_nb, int(kSpecCopies));
     HIPCHK(ctx, hipGetLastError());
     HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
     unsigned long long h[kNumU64Counters + 1], hx[kNumU64Counters + 1];
@@ -1755,6 +1773,7 @@ thor_status thor_submit(thor_ctx* ctx, const thor_shell_request* r, uint64_t* re
     m.req = r->request_id;
     m.spec = d_spec;
     m.spec_nb = r->spec_nb;
+    m.spec_rep = 1;
     m.spec_lo = r->spec_lo;
     m.spec_w = (r->spec_hi - r->spec_lo) / r->spec_nb;
     m.spec_scale = 1.0;
