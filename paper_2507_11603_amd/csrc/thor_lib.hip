@@ -79,9 +79,9 @@ __device__ __forceinline__ int find_batch(const BatchDev* b, int nb, uint64_t q)
 // parks live packets in the pool for the next launch.
 //
 // Tail hand-off (desc->wide > 0, unbounded calls): once the queue is drained,
-// at most tail.max_waves waves are still running and a wave holds at most
-// desc->wide live packets, it appends them to the tail list and exits; k_tail
-// then runs each of them in a wave of its own.
+// at most tail.max_waves waves (four per CU) are still running and a wave
+// holds at most desc->wide live packets, it appends them to the tail list and
+// exits; k_tail then runs each of them in a wave of its own.
 template <class R, bool GRID, bool SEEDS>
 __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* __restrict__ models,
                                                     const BatchDev* __restrict__ batches,
@@ -1002,7 +1002,7 @@ template <class R>
 TailDev<R> tail_dev(thor_ctx* ctx, bool on) {
     if (!on) return TailDev<R>{nullptr, nullptr, nullptr, nullptr, nullptr, 0};
     return TailDev<R>{reinterpret_cast<Pkt<R>*>(ctx->d_tail_pk), ctx->d_tail_home, ctx->d_tailctl,
-                      ctx->d_tailctl + 1, ctx->d_tailctl + 2, uint64_t(ctx->num_cu)};
+                      ctx->d_tailctl + 1, ctx->d_tailctl + 2, uint64_t(ctx->num_cu) * 4};
 }
 
 template <class R, bool GRID>
