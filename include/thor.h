@@ -172,8 +172,9 @@ typedef struct {
                                    instead of the peel-seed pass */
     int32_t records;            /* 1: keep per-packet records of this call */
     uint64_t seed_slots;        /* PERSISTENT, grid, 1-3 observers: slots (48 B each) of
-                                   the peel-seed buffer; 0 = max(2^26, 128 per lane of
-                                   the launch); at least observers x lanes.  A full
+                                   the peel-seed buffer; 0 = 2^28 (12.9 GB), or
+                                   max(2^26, 128 per lane of the launch) when that
+                                   cannot be allocated; at least observers x lanes.  A full
                                    buffer ends a transport kernel early (packets wait
                                    in device memory), the peel pass empties it and
                                    transport resumes. */

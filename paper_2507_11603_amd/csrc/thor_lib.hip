@@ -1467,16 +1467,22 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         std::memset(&sb, 0, sizeof sb);
         const bool seeds = grid && opt->n_obs > 0 && opt->n_obs <= kMaxSeedObs && !opt->inline_peel;
         if (seeds) {
-            // default: 2^26 slots (3.2 GB) or two runs of kSeedChunk per lane;
-            // a smaller buffer shrinks the runs, down to one event's rays
+            // default: 2^28 slots (12.9 GB; fewer transport / peel-pass rounds),
+            // else 2^26 (3.2 GB) or two runs of kSeedChunk per lane when that
+            // much cannot be had; a smaller buffer shrinks the runs, down to
+            // one event's rays
             const uint64_t lanes = uint64_t(gsize) * block;
             const uint64_t ev_rays = uint64_t(opt->n_obs);
-            const uint64_t slots = opt->seed_slots ? opt->seed_slots
-                                                   : std::max<uint64_t>(uint64_t(1) << 26, lanes * 2 * kSeedChunk);
+            const uint64_t small = std::max<uint64_t>(uint64_t(1) << 26, lanes * 2 * kSeedChunk);
+            uint64_t slots = opt->seed_slots ? opt->seed_slots : std::max<uint64_t>(uint64_t(1) << 28, small);
             if (slots < lanes * ev_rays)
                 return fail(THOR_E_INVAL, "seed_slots must be at least %llu (observers per lane)",
                             (unsigned long long)(lanes * ev_rays));
             s = ensure_seeds(ctx, slots, &sb);
+            if (s && !opt->seed_slots && slots != small) {
+                slots = small;
+                s = ensure_seeds(ctx, slots, &sb);
+            }
             if (s) return s;
             sb.chunk = uint32_t(std::max<uint64_t>(ev_rays, std::min<uint64_t>(kSeedChunk, slots / (2 * lanes))));
             if (!bounded) {
