@@ -851,12 +851,15 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
 // a later call resumes it exactly.  PRE: `pre` holds the draws of events
 // pre_event, pre_event + 1, ... evaluated ahead; max_events must not run
 // past them; `dtab` is the FP32 Dawson table to read (an LDS copy).
+// early_end (persistent waves): the call also ends once a quarter of the
+// lanes that entered it have left, so that the wave refills them without
+// waiting for its longest flight.
 template <class R, bool GRID, bool Q = false, bool PRE = false>
 __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt,
                        uint32_t max_visits, uint32_t max_events, uint32_t* events_done,
                        const SeedBuf* sb = nullptr, SeedLane* sl = nullptr, CellCache<R>* ccp = nullptr,
                        const EventDraws<R>* pre = nullptr, uint32_t pre_event = 0, JobSink<R>* js = nullptr,
-                       const float* dtab = nullptr) {
+                       const float* dtab = nullptr, bool early_end = false) {
     const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
     Loc L;
 #pragma unroll
@@ -878,7 +881,11 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
     const uint64_t emax = o.max_events ? o.max_events : 100000000ull;
     int fate = kFateNone;
     uint32_t ev = 0;
+    const int n_in = early_end ? __popcll(__ballot(1)) : 0;
     for (uint32_t vis = 0; vis < max_visits && ev < max_events; ++vis) {
+        // a quarter of the lanes that entered have left (finished packets
+        // wait for a refill): end the turn for all
+        if (early_end && 4 * __popcll(__ballot(1)) <= 3 * n_in) break;
         int nr, cm;
         double t;
         Fields<R> fl;

@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
         if (work) {
             const ModelDev& m = models[pk.model];
             const int fate = advance<R, GRID, useq>(g, m, o, pk, cnt, turn_visits, budget - used, &used, &sb, &sl,
-                                                    &cc);
+                                                    &cc, nullptr, 0u, nullptr, nullptr, true);
             if (fate != kFateNone) {
                 finish<R, GRID>(g, m, o, pk, fate, cnt);
                 active = false;
