@@ -41,8 +41,8 @@ def parse():
     ap.add_argument("--turn-visits", type=int, default=0)
     ap.add_argument("--inline-peel", type=int, default=0, help="march peel rays in the scattering lane")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=3_000_000,
-                    help="packets of the oracle sample (ids 0..n-1; about 20 s on 16 host cores)")
+    ap.add_argument("--cpu-sample", type=int, default=8_000_000,
+                    help="packets of the oracle sample (ids 0..n-1; about 15 s on 16 host cores)")
     ap.add_argument("--autotune", type=int, default=1, help="pick launch knobs with the autotuner")
     ap.add_argument("--serving", type=int, default=300, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serving-warmup", type=int, default=60)
