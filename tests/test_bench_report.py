@@ -1,0 +1,40 @@
+"""bench.py's split of a call's device time and cell visits among its kernels
+(host logic, no GPU)."""
+import importlib.util
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_split_with_tail_kernel():
+    b = _bench()
+    st = {"transport_ms": 2500.0, "tail_ms": 2000.0, "peel_ms": 80.0, "passes": 1,
+          "main_visits": 1_000_000, "peel_visits": 3_000_000, "peel_contrib": 500_000,
+          "tail_main_visits": 100_000, "tail_peel_visits": 20_000, "tail_events": 90_000}
+    s = b.kernel_split(st)
+    assert set(s) == {"transport", "tail", "peel_pass"}
+    # first segments of every ray are marched by the transport kernels, the rest by the pass
+    assert s["peel_pass"]["visits"] == 3_000_000 - 500_000
+    assert s["tail"]["visits"] == 120_000 and s["tail"]["events"] == 90_000
+    assert s["transport"]["visits"] == 1_000_000 + 500_000 - 120_000
+    assert s["transport"]["ms"] == 500.0 and s["tail"]["ms"] == 2000.0
+    assert max(s, key=lambda k: s[k]["ms"]) == "tail"
+    # achieved bytes: 20 B per visit over the kernel's own time
+    assert abs(s["peel_pass"]["achieved_GBps"] - 20 * 2_500_000 / 0.080 / 1e9) < 1e-9
+
+
+def test_split_without_tail_or_seeds():
+    b = _bench()
+    st = {"transport_ms": 100.0, "tail_ms": 0.0, "peel_ms": 0.0, "passes": 1,
+          "main_visits": 10, "peel_visits": 30, "peel_contrib": 5,
+          "tail_main_visits": 0, "tail_peel_visits": 0, "tail_events": 0}
+    s = b.kernel_split(st)
+    assert "tail" not in s
+    assert s["transport"]["visits"] == 40 and s["peel_pass"]["visits"] == 0
