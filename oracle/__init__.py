@@ -108,6 +108,13 @@ def lib():
         L.or_transport.argtypes = [C.POINTER(Geometry), C.POINTER(Source), C.POINTER(Opts),
                                    u64, u64, C.c_void_p, C.c_void_p, C.POINTER(Stats),
                                    C.c_void_p]
+        i32 = C.c_int32
+        L.or_project.restype = C.c_int
+        L.or_project.argtypes = [C.c_void_p, C.c_void_p, i32, i32, i32, i32, d,
+                                 C.c_void_p, C.c_void_p]
+        L.or_forest.restype = C.c_int
+        L.or_forest.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, i32, i32, i32, i32, d, d,
+                                i32, C.c_void_p, u32, u32, d, d, C.c_void_p]
         _lib = L
     return _lib
 
@@ -297,3 +304,52 @@ def run_parallel(geom, src, opts, first_id, n, workers=None, records=False):
     if records:
         out["records"] = np.concatenate([p["records"] for p in parts])
     return out
+
+
+# ------------------------------------------------------------- raytracing
+def _grid32(a):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.ndim != 3:
+        raise ValueError("fields are [z][y][x] arrays")
+    return a
+
+
+def ray_image_shape(shape, axis: int):
+    """(n_j, n_i) of the image of rays along `axis` through a [z][y][x] grid."""
+    nz, ny, nx = shape
+    if axis not in (0, 1, 2):
+        raise ValueError("axis must be 0 (x), 1 (y) or 2 (z)")
+    return {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[axis]
+
+
+def project(q, w=None, axis: int = 2, ds: float = 1.0):
+    """Projection Q = int q w ds and Q_hat = int w ds along `axis` (Section 3.5.1).
+    Returns (Q, Q_hat) as [j][i] float64 images."""
+    q = _grid32(q)
+    w = None if w is None else _grid32(w)
+    Q = np.zeros(ray_image_shape(q.shape, axis))
+    W = np.zeros_like(Q)
+    nz, ny, nx = q.shape
+    rc = lib().or_project(q.ctypes.data, None if w is None else w.ctypes.data, nx, ny, nz,
+                          int(axis), float(ds), Q.ctypes.data, W.ctypes.data)
+    if rc != 0:
+        raise ValueError("or_project: invalid arguments")
+    return Q, W
+
+
+def forest(n_HI, T, v_los, axis: int, ds: float, hubble: float, n_sub: int, los,
+           nb: int, u_lo: float, u_hi: float):
+    """Lyman-alpha optical depth tau[n_los][nb] along axis-parallel rays
+    (Section 3.5.2, eq. abs); `los` is an (n_los, 2) array of (i, j)."""
+    n_HI, T, v_los = _grid32(n_HI), _grid32(T), _grid32(v_los)
+    if not (n_HI.shape == T.shape == v_los.shape):
+        raise ValueError("field shapes differ")
+    los = np.ascontiguousarray(np.asarray(los, dtype=np.int32).reshape(-1, 2))
+    tau = np.zeros((los.shape[0], int(nb)))
+    nz, ny, nx = n_HI.shape
+    rc = lib().or_forest(n_HI.ctypes.data, T.ctypes.data, v_los.ctypes.data, nx, ny, nz,
+                         int(axis), float(ds), float(hubble), int(n_sub), los.ctypes.data,
+                         los.shape[0], int(nb), float(u_lo), float(u_hi), tau.ctypes.data)
+    if rc != 0:
+        raise ValueError("or_forest: invalid arguments")
+    return tau

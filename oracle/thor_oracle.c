@@ -916,3 +916,102 @@ int or_transport(const or_geometry *g, const or_source *s, const or_opts *o, uin
     free(m.cdf);
     return 0;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Raytracing driver (Section 3.5).  Rays run parallel to one grid axis    */
+/* through cell centres, from the low face (s = 0) to the high face; the    */
+/* fields are constant within a cell (the zeroth-order assumption of        */
+/* Section 3.4).  A ray is named by its cell indices (i, j) along the two   */
+/* other axes, i along the lower-numbered one: axis z -> (x, y),            */
+/* axis y -> (x, z), axis x -> (y, z).                                      */
+/* ---------------------------------------------------------------------- */
+static size_t ray_cell(int axis, int nx, int ny, int i, int j, int k)
+{
+    int c[3];
+    if (axis == 0) { c[0] = k; c[1] = i; c[2] = j; }
+    else if (axis == 1) { c[0] = i; c[1] = k; c[2] = j; }
+    else { c[0] = i; c[1] = j; c[2] = k; }
+    return ((size_t)c[2] * (size_t)ny + (size_t)c[1]) * (size_t)nx + (size_t)c[0];
+}
+
+static void ray_dims(int axis, int nx, int ny, int nz, int *ni, int *nj, int *nk)
+{
+    int n[3] = {nx, ny, nz};
+    *nk = n[axis];
+    *ni = axis == 0 ? ny : nx;
+    *nj = axis == 2 ? ny : nz;
+}
+
+/* Section 3.5.1: the projection Q = int q w ds and its normalisation       */
+/* Q_hat = int w ds along every ray of the axis (w = 1 when w is NULL).      */
+/* Images are [j][i].  Returns 0, or -1 for invalid arguments.              */
+int or_project(const float *q, const float *w, int nx, int ny, int nz, int axis, double ds,
+               double *Q, double *W)
+{
+    if (axis < 0 || axis > 2 || nx <= 0 || ny <= 0 || nz <= 0 || !(ds > 0.0))
+        return -1;
+    int ni, nj, nk;
+    ray_dims(axis, nx, ny, nz, &ni, &nj, &nk);
+    for (int j = 0; j < nj; ++j)
+        for (int i = 0; i < ni; ++i) {
+            double acc_q = 0.0, acc_w = 0.0;
+            for (int k = 0; k < nk; ++k) {
+                size_t c = ray_cell(axis, nx, ny, i, j, k);
+                double wk = w ? (double)w[c] : 1.0;
+                acc_q += (double)q[c] * wk * ds;
+                acc_w += wk * ds;
+            }
+            Q[(size_t)j * ni + i] = acc_q;
+            if (W)
+                W[(size_t)j * ni + i] = acc_w;
+        }
+    return 0;
+}
+
+/* Section 3.5.2, eq. (abs): tau(nu) = int n_HI(s) sigma(nu(s), T(s)) ds     */
+/* with nu(s) = nu_i [1 - (v(s) + H s)/c].  The spectrum is sampled at the  */
+/* centres u_b of nb bins over [u_lo, u_hi), where u = c (nu_i/nu0 - 1) is  */
+/* the photon's velocity offset at s = 0.  To first order in v/c, the gas   */
+/* at s sees x = (u - v(s) - H s) / v_th(T(s)), so a cell adds               */
+/* n_HI sigma0(T) H(a(T), x) ds to every bin.  Each cell is split into      */
+/* n_sub equal steps evaluated at their midpoints (the sub-cell stepping    */
+/* that keeps the Hubble shift per step below the line width).  vlos is     */
+/* the velocity component along +axis (cm/s); hubble is H(z) in 1/s.        */
+/* los holds (i, j) per ray; tau is [n_los][nb].                            */
+int or_forest(const float *nHI, const float *T, const float *vlos, int nx, int ny, int nz,
+              int axis, double ds, double hubble, int n_sub, const int32_t *los,
+              uint32_t n_los, uint32_t nb, double u_lo, double u_hi, double *tau)
+{
+    if (axis < 0 || axis > 2 || nx <= 0 || ny <= 0 || nz <= 0 || !(ds > 0.0) || n_sub < 1 ||
+        nb < 1 || !(u_hi > u_lo))
+        return -1;
+    int ni, nj, nk;
+    ray_dims(axis, nx, ny, nz, &ni, &nj, &nk);
+    double du = (u_hi - u_lo) / (double)nb;
+    for (uint32_t l = 0; l < n_los; ++l) {
+        int i = los[2 * l], j = los[2 * l + 1];
+        if (i < 0 || i >= ni || j < 0 || j >= nj)
+            return -1;
+        double *row = tau + (size_t)l * nb;
+        for (uint32_t b = 0; b < nb; ++b)
+            row[b] = 0.0;
+        for (int k = 0; k < nk; ++k) {
+            size_t c = ray_cell(axis, nx, ny, i, j, k);
+            double n = (double)nHI[c];
+            if (n == 0.0)
+                continue;   /* adds exactly zero */
+            double vth, a, sigma0;
+            or_line_params((double)T[c], &vth, &a, &sigma0);
+            double step = ds / (double)n_sub;
+            for (int m = 0; m < n_sub; ++m) {
+                double s = ((double)k + ((double)m + 0.5) / (double)n_sub) * ds;
+                for (uint32_t b = 0; b < nb; ++b) {
+                    double u = u_lo + ((double)b + 0.5) * du;
+                    double x = (u - (double)vlos[c] - hubble * s) / vth;
+                    row[b] += n * sigma0 * or_voigt(a, x) * step;
+                }
+            }
+        }
+    }
+    return 0;
+}

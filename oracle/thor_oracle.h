@@ -113,6 +113,15 @@ int or_transport(const or_geometry *g, const or_source *s, const or_opts *o,
                  uint64_t first_id, uint64_t n,
                  double *spectrum, double *cube, or_stats *st, or_record *records);
 
+/* raytracing driver (Section 3.5): rays parallel to grid axis `axis` (0 x, 1 y, 2 z)  */
+/* projection Q = int q w ds, Q_hat = int w ds (w may be NULL: w = 1); images [j][i]  */
+int or_project(const float *q, const float *w, int nx, int ny, int nz, int axis, double ds,
+               double *Q, double *W);
+/* Lyman-alpha absorption spectra tau[n_los][nb] at bin centres of [u_lo, u_hi) cm/s */
+int or_forest(const float *nHI, const float *T, const float *vlos, int nx, int ny, int nz,
+              int axis, double ds, double hubble, int n_sub, const int32_t *los,
+              uint32_t n_los, uint32_t nb, double u_lo, double u_hi, double *tau);
+
 #ifdef __cplusplus
 }
 #endif
