@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--web-only", type=int, default=0,
                     help="measure only the cosmic-web box and print its record (for counter runs)")
     ap.add_argument("--web-warmup", type=int, default=1, help="untimed web run of a tenth of the packets first")
+    ap.add_argument("--rays-only", type=int, default=0,
+                    help="time only the raytracing driver (projections and forest spectra) on the web box")
+    ap.add_argument("--rays-grid", type=int, default=512)
+    ap.add_argument("--rays-reps", type=int, default=20, help="timed launches per raytracing kernel")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (PMC calibration)")
     return ap.parse_args()
@@ -224,12 +228,72 @@ def web_box(a, kw):
             "roofline": roof}
 
 
+def rays_box(a):
+    """Raytracing driver on the forest workload (web box at z = 2): column-
+    density projections along each axis (HBM-bound: 4 B read per cell) and
+    the absorption spectra of one tomography plane, FP64 and mixed (bound by
+    the Voigt evaluations: rays x cells x sub-steps x bins)."""
+    import torch
+
+    import workloads as W
+    from paper_2507_11603_amd import thor
+    wl = W.forest(a.rays_grid)
+    o = wl["opts"]
+    n, T, v = (torch.from_numpy(f).cuda() for f in wl["fields"])
+    cells = n.numel()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()                                           # warm-up launch
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    out = {"workload": "forest%d" % a.rays_grid, "cells": cells, "projection": {}, "forest": {}}
+    for axis, name in enumerate("xyz"):
+        img = thor.ray_project(n, None, axis, o["ds"])
+        ms = timed(lambda: thor.ray_project(n, None, axis, o["ds"], out=img), a.rays_reps)
+        nbytes = 4 * cells + 2 * 8 * img[0].numel()
+        gbs = nbytes / (ms / 1e3) / 1e9
+        out["projection"][name] = {"ms": ms, "bytes": nbytes, "achieved_GBps": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+    i0, ni, j0, nj = o["rays"]
+    evals = ni * nj * a.rays_grid * o["n_sub"] * o["nb"]
+    for prec in ("fp64", "mixed"):
+        tau = thor.ray_forest(n, T, v, o["axis"], o["ds"], o["hubble"], o["n_sub"], o["rays"], o["nb"],
+                              o["u_lo"], o["u_hi"], prec)
+        ms = timed(lambda: thor.ray_forest(n, T, v, o["axis"], o["ds"], o["hubble"], o["n_sub"], o["rays"],
+                                           o["nb"], o["u_lo"], o["u_hi"], prec, out=tau),
+                   max(1, a.rays_reps // 4))
+        out["forest"][prec] = {"ms": ms, "rays": ni * nj, "voigt_evals": evals,
+                               "voigt_evals_per_s": evals / (ms / 1e3),
+                               "median_tau": float(tau.median().item())}
+    z = out["projection"]["z"]
+    out["roofline"] = {"bound": "hbm", "kernel": "k_project_cols (axis z)", "achieved": z["achieved_GBps"],
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": z["hbm_frac"], "traffic": None}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+    if a.rays_only:
+        import torch
+
+        from paper_2507_11603_amd import thor
+        if not torch.cuda.is_available():
+            print("no HIP device", file=sys.stderr)
+            sys.exit(1)
+        thor.lib()
+        calib_copy(a)
+        print(json.dumps({"rays": rays_box(a)}), flush=True)
+        return
     if a.web_only:
         import torch
 

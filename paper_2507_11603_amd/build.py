@@ -7,10 +7,10 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "thor_lib.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("thor_lib.hip", "thor_rays.hip")]
 LIB = os.path.join(HERE, "libthor.so")
 HEADERS = [os.path.join(HERE, "csrc", f) for f in ("thor_device.hpp", "thor_engine.hpp")] + \
-          [os.path.join(ROOT, "include", "thor.h")]
+          [os.path.join(ROOT, "include", f) for f in ("thor.h", "thor_rays.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -26,11 +26,11 @@ HIPCC_FLAGS = [
 
 def build(force: bool = True, verbose: bool = False) -> str:
     if not force and os.path.exists(LIB):
-        newest = max(os.path.getmtime(p) for p in [SRC] + HEADERS)
+        newest = max(os.path.getmtime(p) for p in SRCS + HEADERS)
         if os.path.getmtime(LIB) >= newest:
             return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp, SRC]
+    cmd = ["hipcc"] + HIPCC_FLAGS + ["-o", tmp] + SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd, cwd=HERE)

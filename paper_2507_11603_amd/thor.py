@@ -30,7 +30,8 @@ OBS = {"+x": 0, "+y": 1, "+z": 2, "-x": 3, "-y": 4, "-z": 5}
 OUT = {"spectrum": 0, "cube": 1, "records": 2, "stats": 3}
 SYMBOLS = ["thor_create", "thor_destroy", "thor_load_grid", "thor_emit", "thor_transport",
            "thor_reset_outputs", "thor_read_spectra", "thor_output_bytes", "thor_last_error",
-           "thor_eval_voigt", "thor_sample_upar", "thor_submit", "thor_step", "thor_poll"]
+           "thor_eval_voigt", "thor_sample_upar", "thor_submit", "thor_step", "thor_poll",
+           "thor_ray_project", "thor_ray_forest", "thor_ray_last_error"]
 
 
 class ThorError(RuntimeError):
@@ -104,6 +105,17 @@ class thor_shell_request(C.Structure):
                 ("spec_hi", C.c_double)]
 
 
+class thor_ray_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("axis", C.c_int32),
+                ("ds", C.c_double)]
+
+
+class thor_forest_opts(C.Structure):
+    _fields_ = [("i0", C.c_int32), ("ni", C.c_int32), ("j0", C.c_int32), ("nj", C.c_int32),
+                ("hubble", C.c_double), ("n_sub", C.c_int32), ("nb", C.c_uint32),
+                ("u_lo", C.c_double), ("u_hi", C.c_double), ("precision", C.c_int32)]
+
+
 _lib = None
 
 
@@ -130,6 +142,10 @@ def lib():
             "thor_submit": ([vp, C.POINTER(thor_shell_request), C.POINTER(u64)], C.c_int),
             "thor_step": ([vp, u32, C.POINTER(thor_transport_opts)], C.c_int),
             "thor_poll": ([vp, u64, vp, C.POINTER(thor_stats), C.POINTER(C.c_int)], C.c_int),
+            "thor_ray_project": ([C.POINTER(thor_ray_grid), vp, vp, vp, vp, vp], C.c_int),
+            "thor_ray_forest": ([C.POINTER(thor_ray_grid), C.POINTER(thor_forest_opts), vp, vp, vp,
+                                 vp, vp], C.c_int),
+            "thor_ray_last_error": ([], C.c_char_p),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -209,6 +225,19 @@ def thor_poll(ctx, req_id: int, spectrum: np.ndarray | None):
 
 
 # ------------------------------------------------------------------ struct builders
+def _check_ray(code):
+    if code != OK:
+        raise ThorError(code, lib().thor_ray_last_error().decode())
+
+
+def thor_ray_project(grid: thor_ray_grid, q_ptr, w_ptr, Q_ptr, W_ptr, stream):
+    _check_ray(lib().thor_ray_project(C.byref(grid), q_ptr, w_ptr, Q_ptr, W_ptr, stream))
+
+
+def thor_ray_forest(grid: thor_ray_grid, opts: thor_forest_opts, n_ptr, T_ptr, v_ptr, tau_ptr, stream):
+    _check_ray(lib().thor_ray_forest(C.byref(grid), C.byref(opts), n_ptr, T_ptr, v_ptr, tau_ptr, stream))
+
+
 def make_geometry(geom: dict, device_fields=None) -> thor_geometry:
     """Plain-dict medium description (see ``workloads``) -> thor_geometry.
     For grids, ``device_fields`` holds the five float32 device tensors
@@ -382,3 +411,62 @@ def run(wl: dict, n: int | None = None, first_id: int = 0, precision="fp64", pat
         return out
     finally:
         T.close()
+
+
+# ------------------------------------------------------------- raytracing
+def ray_image_shape(shape, axis: int):
+    """(n_j, n_i) of the image of rays along `axis` through a [z][y][x] grid."""
+    nz, ny, nx = shape
+    return {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[axis]
+
+
+def _field(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.dim() == 3
+            and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous float32 [z][y][x] CUDA tensor" % name)
+    return t
+
+
+def ray_project(q, w=None, axis: int = 2, ds: float = 1.0, out=None):
+    """Projection along `axis` (Section 3.5.1): returns device float64 images
+    (Q, W) = (int q w ds, int w ds), each [j][i].  `out` may pass both images."""
+    import torch
+    q = _field(q, "q")
+    if w is not None:
+        w = _field(w, "w")
+        if w.shape != q.shape or w.device != q.device:
+            raise ValueError("w must match q")
+    nz, ny, nx = q.shape
+    g = thor_ray_grid(nx, ny, nz, int(axis), float(ds))
+    if out is None:
+        shape = ray_image_shape(q.shape, axis) if axis in (0, 1, 2) else (1, 1)
+        out = (torch.empty(shape, dtype=torch.float64, device=q.device),
+               torch.empty(shape, dtype=torch.float64, device=q.device))
+    Q, W = out
+    with torch.cuda.device(q.device):
+        thor_ray_project(g, q.data_ptr(), None if w is None else w.data_ptr(), Q.data_ptr(),
+                         W.data_ptr(), torch.cuda.current_stream(q.device).cuda_stream)
+    return Q, W
+
+
+def ray_forest(n_HI, T, v_los, axis: int, ds: float, hubble: float, n_sub: int,
+               rays, nb: int, u_lo: float, u_hi: float, precision: str = "fp64", out=None):
+    """Lyman-alpha optical depth along rays parallel to `axis` (Section 3.5.2,
+    eq. abs).  `rays` = (i0, ni, j0, nj); returns a device float64 tensor
+    tau[nj][ni][nb]."""
+    import torch
+    n_HI, T, v_los = _field(n_HI, "n_HI"), _field(T, "T"), _field(v_los, "v_los")
+    if not (n_HI.shape == T.shape == v_los.shape):
+        raise ValueError("field shapes differ")
+    nz, ny, nx = n_HI.shape
+    i0, ni, j0, nj = (int(r) for r in rays)
+    g = thor_ray_grid(nx, ny, nz, int(axis), float(ds))
+    o = thor_forest_opts(i0, ni, j0, nj, float(hubble), int(n_sub), int(nb), float(u_lo),
+                         float(u_hi), PREC[precision])
+    tau = out if out is not None else torch.empty((max(nj, 0), max(ni, 0), int(nb)),
+                                                  dtype=torch.float64, device=n_HI.device)
+    with torch.cuda.device(n_HI.device):
+        thor_ray_forest(g, o, n_HI.data_ptr(), T.data_ptr(), v_los.data_ptr(), tau.data_ptr(),
+                        torch.cuda.current_stream(n_HI.device).cuda_stream)
+    return tau

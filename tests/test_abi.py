@@ -10,11 +10,12 @@ import pytest
 from paper_2507_11603_amd import thor
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "thor.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(thor_[a-z_]+)\s*\(", text)))
 
@@ -44,13 +45,16 @@ def test_struct_layouts_match_header():
     src = r'''
 #include <stdio.h>
 #include <stddef.h>
-#include "thor.h"
+#include "thor_rays.h"
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(thor_geometry), sizeof(thor_source),
          sizeof(thor_transport_opts), sizeof(thor_stats), sizeof(thor_record),
          sizeof(thor_shell_request));
   printf("%zu %zu %zu %zu\n", offsetof(thor_geometry, n_HI_field), offsetof(thor_geometry, g_hg),
          offsetof(thor_transport_opts, step_events), offsetof(thor_transport_opts, records));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(thor_ray_grid), sizeof(thor_forest_opts),
+         offsetof(thor_ray_grid, ds), offsetof(thor_forest_opts, u_lo),
+         offsetof(thor_forest_opts, precision));
   return 0;
 }
 '''
@@ -59,7 +63,7 @@ int main(void) {
         p = os.path.join(d, "t.c")
         open(p, "w").write(src)
         exe = os.path.join(d, "t")
-        subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), "-o", exe, p])
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, p])
         lines = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split("\n")
     sizes = list(map(int, lines[0].split()))
     offs = list(map(int, lines[1].split()))
@@ -69,6 +73,10 @@ int main(void) {
     assert offs == [thor.thor_geometry.n_HI_field.offset, thor.thor_geometry.g_hg.offset,
                     thor.thor_transport_opts.step_events.offset, thor.thor_transport_opts.records.offset]
     assert thor.RECORD_DTYPE.itemsize == C.sizeof(thor.thor_record)
+    rays = list(map(int, lines[2].split()))
+    assert rays == [C.sizeof(thor.thor_ray_grid), C.sizeof(thor.thor_forest_opts),
+                    thor.thor_ray_grid.ds.offset, thor.thor_forest_opts.u_lo.offset,
+                    thor.thor_forest_opts.precision.offset]
 
 
 def test_create_without_device_fails_cleanly(lib):
@@ -80,3 +88,25 @@ def test_create_without_device_fails_cleanly(lib):
     code = lib.thor_create(C.byref(h), 0, None, 0)
     assert code < 0 and not h.value
     assert lib.thor_last_error()
+
+
+def test_ray_calls_validate_on_the_host(lib):
+    """Invalid raytracing arguments are refused before any device work, with
+    a message; a call with no rays is a no-op (no GPU needed for either)."""
+    g = thor.thor_ray_grid(4, 4, 4, 3, 1.0)
+    assert lib.thor_ray_project(C.byref(g), None, None, None, None, None) == -1
+    assert b"axis" in lib.thor_ray_last_error()
+    g.axis, g.ds = 2, -1.0
+    assert lib.thor_ray_project(C.byref(g), None, None, None, None, None) == -1
+    g.ds = 1.0
+    o = thor.thor_forest_opts(0, 5, 0, 1, 0.0, 1, 8, 0.0, 1.0, 0)
+    assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == -1
+    assert b"outside" in lib.thor_ray_last_error()
+    o.ni, o.n_sub = 4, 0
+    assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == -1
+    o.n_sub, o.u_hi = 1, 0.0
+    assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == -1
+    o.u_hi, o.precision = 1.0, 7
+    assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == -1
+    o.precision, o.nj = 0, 0
+    assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == 0

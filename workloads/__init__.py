@@ -16,6 +16,8 @@ Workloads (the paper's datasets are not available; these stand in for them):
            (one rank's share of the weak-scaling runs of Section 6.3)
   serving  stream of meshless shell-model solves (the parameter grid of
            Section 5.1)
+  forest   Lyman-alpha absorption sightlines through the web box at z = 2
+           (the forest and tomography example of Section 5.5)
 """
 from __future__ import annotations
 
@@ -150,6 +152,43 @@ def web_fields_torch(n: int = 1024, sigma_ln: float = 2.0, n_mean: float = 1e-5,
     temp = torch.sqrt(dens / n_mean).mul_(T0)
     vel = [grf_torch(n, slope, s, device).mul_(sigma_v_kms * KMS) for s in seeds[1:]]
     return dens, temp, vel[0], vel[1], vel[2]
+
+
+def forest_fields(n: int = 512, n_mean: float = 2e-11, entropy: int = 2507_11603):
+    """n_HI, T and v_z of the web box: the same random fields as
+    `web_fields(n)` (density and z velocity streams), with the neutral density
+    rescaled to a forest-like mean (the Gunn-Peterson depth of the mean is
+    then about 0.4 at z = 2)."""
+    seqs = np.random.SeedSequence(entropy).spawn(4)
+    delta = grf(n, -2.5, np.random.default_rng(seqs[0]))
+    delta *= np.float32(2.0)
+    dens = np.exp(delta, dtype=np.float32)
+    del delta
+    dens *= np.float32(n_mean / dens.mean(dtype=np.float64))
+    temp = (np.float32(1e4) * np.sqrt(dens / np.float32(n_mean))).astype(np.float32)
+    vz = grf(n, -2.5, np.random.default_rng(seqs[3]))
+    vz *= np.float32(100.0 * KMS)
+    return dens, temp, vz
+
+
+_FOREST_CACHE = {}
+
+
+def forest(n_grid: int = 512, box_pmpc: float = 17.22, hubble_kms_mpc: float = 203.6,
+           n_sub: int = 4, nb: int = 2048):
+    """Absorption spectra along z through the web box at z = 2 (box 17.22
+    proper Mpc, H(z = 2) = 203.6 km/s/Mpc for a flat Omega_m = 0.309
+    cosmology): one tomography plane of n_grid rays (all x at y = n_grid/2),
+    n_sub steps per cell (H ds / n_sub = 1.7 km/s at 512^3, well below the
+    12.8 km/s thermal speed at 1e4 K), nb bins over -500 .. 4000 km/s (the
+    Hubble span of the box is 3505 km/s).  Fields are cached per size."""
+    if n_grid not in _FOREST_CACHE:
+        _FOREST_CACHE[n_grid] = forest_fields(n_grid)
+    L = box_pmpc * 1e3 * KPC
+    H = hubble_kms_mpc * KMS / (1e3 * KPC)
+    opts = dict(axis=2, ds=L / n_grid, hubble=H, n_sub=n_sub, rays=(0, n_grid, n_grid // 2, 1),
+                nb=nb, u_lo=-500.0 * KMS, u_hi=4000.0 * KMS)
+    return {"fields": _FOREST_CACHE[n_grid], "opts": opts}
 
 
 def web(n_grid: int = 1024, n_packets: int = 100_000_000, seed: int = 3, box_pmpc: float = 17.22,
