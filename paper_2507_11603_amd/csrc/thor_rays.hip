@@ -88,6 +88,47 @@ __global__ __launch_bounds__(kThreads) void k_project_cols(
     }
 }
 
+// The same with four adjacent columns per thread and 16-byte loads (the
+// inner extent a multiple of 4, the fields 16-byte aligned).
+__global__ __launch_bounds__(kThreads) void k_project_cols4(
+    const float4* __restrict__ q, const float4* __restrict__ w, size_t n_inner4, size_t n_col4,
+    int n_ray, int seg, double ds, double* Q, double* W, bool atomic) {
+    const size_t c4 = size_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (c4 >= n_col4) return;
+    const size_t o = c4 / n_inner4, in4 = c4 - o * n_inner4;
+    const int k0 = int(blockIdx.y) * seg, k1 = min(n_ray, k0 + seg);
+    const size_t first = (o * size_t(n_ray) + size_t(k0)) * n_inner4 + in4;
+    double aq[4] = {0.0, 0.0, 0.0, 0.0}, aw[4] = {0.0, 0.0, 0.0, 0.0};
+    if (w) {
+#pragma unroll 4
+        for (int k = k0; k < k1; ++k) {
+            const size_t at = first + size_t(k - k0) * n_inner4;
+            const float4 qv = q[at], wv = w[at];
+            aq[0] += double(qv.x) * double(wv.x); aw[0] += double(wv.x);
+            aq[1] += double(qv.y) * double(wv.y); aw[1] += double(wv.y);
+            aq[2] += double(qv.z) * double(wv.z); aw[2] += double(wv.z);
+            aq[3] += double(qv.w) * double(wv.w); aw[3] += double(wv.w);
+        }
+    } else {
+#pragma unroll 4
+        for (int k = k0; k < k1; ++k) {
+            const float4 qv = q[first + size_t(k - k0) * n_inner4];
+            aq[0] += double(qv.x); aq[1] += double(qv.y); aq[2] += double(qv.z); aq[3] += double(qv.w);
+        }
+        aw[0] = aw[1] = aw[2] = aw[3] = double(k1 - k0);
+    }
+    const size_t col = 4 * c4;                  // = o * n_inner + 4 * in4
+    for (int c = 0; c < 4; ++c) {
+        if (atomic) {
+            atomicAdd(Q + col + c, aq[c] * ds);
+            if (W) atomicAdd(W + col + c, aw[c] * ds);
+        } else {
+            Q[col + c] = aq[c] * ds;
+            if (W) W[col + c] = aw[c] * ds;
+        }
+    }
+}
+
 // Rays along x: each ray is contiguous.  One wave per (ray, segment); the
 // lanes stride the segment and reduce across the wave at the end.
 __global__ __launch_bounds__(kThreads) void k_project_rows(
@@ -124,6 +165,84 @@ __global__ __launch_bounds__(kThreads) void k_project_rows(
             if (W) W[row] = aw * ds;
         }
     }
+}
+
+// Rays along x with 16-byte loads (ray length a multiple of 4, aligned
+// fields): segments are whole multiples of 64 float4 (one per lane).
+__global__ __launch_bounds__(kThreads) void k_project_rows4(
+    const float4* __restrict__ q, const float4* __restrict__ w, size_t n_rows, int n_ray4, int seg4,
+    double ds, double* Q, double* W, bool atomic) {
+    const int lane = threadIdx.x & 63;
+    const size_t row = size_t(blockIdx.x) * (kThreads / 64) + (threadIdx.x >> 6);
+    if (row >= n_rows) return;              // the whole wave leaves together
+    const int k0 = int(blockIdx.y) * seg4, k1 = min(n_ray4, k0 + seg4);
+    const float4* qr = q + row * size_t(n_ray4);
+    const float4* wr = w ? w + row * size_t(n_ray4) : nullptr;
+    double aq = 0.0, aw = 0.0;
+    if (wr) {
+#pragma unroll 4
+        for (int k = k0 + lane; k < k1; k += 64) {
+            const float4 qv = qr[k], wv = wr[k];
+            aq += double(qv.x) * double(wv.x) + double(qv.y) * double(wv.y) +
+                  (double(qv.z) * double(wv.z) + double(qv.w) * double(wv.w));
+            aw += (double(wv.x) + double(wv.y)) + (double(wv.z) + double(wv.w));
+        }
+    } else {
+#pragma unroll 4
+        for (int k = k0 + lane; k < k1; k += 64) {
+            const float4 qv = qr[k];
+            aq += (double(qv.x) + double(qv.y)) + (double(qv.z) + double(qv.w));
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        aq += __shfl_xor(aq, off);
+        aw += __shfl_xor(aw, off);
+    }
+    if (!wr) aw = 4.0 * double(k1 - k0);
+    if (lane == 0) {
+        if (atomic) {
+            atomicAdd(Q + row, aq * ds);
+            if (W) atomicAdd(W + row, aw * ds);
+        } else {
+            Q[row] = aq * ds;
+            if (W) W[row] = aw * ds;
+        }
+    }
+}
+
+// Far from the line centre H(a, x) follows the asymptotic series of
+// w(z) = (i/pi) int exp(-t^2) / (z - t) dt at z = x + i a:
+//   w(z) ~ (i / sqrt(pi)) sum_n (2n - 1)!! / 2^n  z^-(2n+1),
+// so H = Re w = -Im(S) / sqrt(pi) with S that sum (the Gaussian part,
+// exp(-x^2), is below 1e-43 there).  Dropping the terms after n = N changes H
+// by about (2N + 3) c_(N+1) / x^(2N+2) relative: N = 6 from |x| = 20 in FP64
+// (1e-14), N = 4 from |x| = 10 in FP32 (3e-8).
+template <class R> struct Wing;
+template <> struct Wing<double> { static constexpr double x0 = 20.0; static constexpr int n = 6; };
+template <> struct Wing<float> { static constexpr float x0 = 10.0f; static constexpr int n = 4; };
+
+template <class R>
+__device__ __forceinline__ R voigt_wing(R a, R x) {
+    constexpr R c[7] = {R(1.0), R(0.5), R(0.75), R(1.875), R(6.5625), R(29.53125), R(162.421875)};
+    R r;
+    if constexpr (sizeof(R) == 8) r = 1.0 / (x * x + a * a);
+    else r = __builtin_amdgcn_rcpf(x * x + a * a);
+    const R zr = x * r, zi = -a * r;                        // zeta = 1 / z
+    const R qr = zr * zr - zi * zi, qi = R(2) * zr * zi;    // zeta^2
+    R pr = c[Wing<R>::n], pi = R(0);
+#pragma unroll
+    for (int k = Wing<R>::n - 1; k >= 0; --k) {
+        const R nr = pr * qr - pi * qi + c[k];
+        pi = pr * qi + pi * qr;
+        pr = nr;
+    }
+    return -(zr * pi + zi * pr) * R(1.0 / kSqrtPi);         // -Im(zeta P) / sqrt(pi)
+}
+
+template <class R>
+__device__ __forceinline__ R voigt_forest(R a, R x) {
+    return fabs(x) >= Wing<R>::x0 ? voigt_wing<R>(a, x) : voigt<R>(a, x);
 }
 
 // eq. (abs): one workgroup per (ray, block of kThreads bins).  Per cell the
@@ -165,7 +284,7 @@ __global__ __launch_bounds__(kThreads) void k_forest(
                 const double c0 = s_c[t];
                 for (int m = 0; m < n_sub; ++m) {
                     const R x = R(u - fma(double(m), dc, c0)) * iv;
-                    acc = fma(k0, double(voigt<R>(a, x)), acc);
+                    acc = fma(k0, double(voigt_forest<R>(a, x)), acc);
                 }
             }
         }
@@ -281,7 +400,23 @@ thor_status thor_ray_project(const thor_ray_grid* g, const float* q, const float
     ray_dims(g, &ni, &nj, &nk);
     const size_t n_img = size_t(ni) * size_t(nj);
     const double ds = g->ds;
-    if (g->axis == 0) {
+    const bool aligned = (reinterpret_cast<uintptr_t>(q) % 16 == 0) &&
+                         (!w || reinterpret_cast<uintptr_t>(w) % 16 == 0);
+    if (g->axis == 0 && aligned && nk % 4 == 0) {
+        const size_t blocks = (n_img + kThreads / 64 - 1) / (kThreads / 64);
+        const int nk4 = nk / 4;
+        const int nseg = segments(blocks, nk4, 256);
+        const int seg4 = ((nk4 + nseg - 1) / nseg + 63) / 64 * 64;
+        const int nseg_used = (nk4 + seg4 - 1) / seg4;
+        if (nseg_used > 1) {
+            const unsigned zb = unsigned((n_img + kThreads - 1) / kThreads);
+            k_zero<<<zb, kThreads, 0, st>>>(Q, n_img);
+            if (W) k_zero<<<zb, kThreads, 0, st>>>(W, n_img);
+        }
+        k_project_rows4<<<dim3(unsigned(blocks), unsigned(nseg_used)), kThreads, 0, st>>>(
+            reinterpret_cast<const float4*>(q), reinterpret_cast<const float4*>(w), n_img, nk4, seg4, ds, Q, W,
+            nseg_used > 1);
+    } else if (g->axis == 0) {
         const size_t blocks = (n_img + kThreads / 64 - 1) / (kThreads / 64);
         const int nseg = segments(blocks, nk, 1024);
         const int seg = (nk + nseg - 1) / nseg;
@@ -296,6 +431,22 @@ thor_status thor_ray_project(const thor_ray_grid* g, const float* q, const float
     } else {
         // [outer][ray][inner]: axis y -> outer z, inner x; axis z -> outer 1, inner y*x
         const size_t n_inner = g->axis == 1 ? size_t(g->nx) : size_t(g->nx) * size_t(g->ny);
+        if (aligned && n_inner % 4 == 0) {
+            const size_t n_col4 = n_img / 4;
+            const size_t blocks = (n_col4 + kThreads - 1) / kThreads;
+            const int nseg = segments(blocks, nk, 32);
+            const int seg = (nk + nseg - 1) / nseg;
+            const int nseg_used = (nk + seg - 1) / seg;
+            if (nseg_used > 1) {
+                const unsigned zb = unsigned((n_img + kThreads - 1) / kThreads);
+                k_zero<<<zb, kThreads, 0, st>>>(Q, n_img);
+                if (W) k_zero<<<zb, kThreads, 0, st>>>(W, n_img);
+            }
+            k_project_cols4<<<dim3(unsigned(blocks), unsigned(nseg_used)), kThreads, 0, st>>>(
+                reinterpret_cast<const float4*>(q), reinterpret_cast<const float4*>(w), n_inner / 4, n_col4,
+                nk, seg, ds, Q, W, nseg_used > 1);
+            return launched("thor_ray_project");
+        }
         const size_t blocks = (n_img + kThreads - 1) / kThreads;
         const int nseg = segments(blocks, nk, 64);
         const int seg = (nk + nseg - 1) / nseg;

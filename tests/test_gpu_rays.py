@@ -145,3 +145,22 @@ def test_projection_web512_column_density():
         torch.cuda.synchronize()
         Qo, _ = oracle.project(n, None, axis, wl["opts"]["ds"])
         np.testing.assert_allclose(Q.cpu().numpy(), Qo, rtol=1e-12)
+
+
+@pytest.mark.parametrize("axis", [0, 2])
+def test_projection_unaligned_fields(axis):
+    """Fields that start 4 bytes past a 16-byte boundary take the scalar
+    loads; the result is the same."""
+    shape = (9, 16, 64)
+    rng = np.random.default_rng(21)
+    q = rng.lognormal(0, 1, shape).astype(np.float32)
+    w = rng.random(shape, dtype=np.float32)
+    def shifted(a):
+        buf = torch.empty(a.size + 1, dtype=torch.float32, device="cuda")
+        buf[1:] = torch.from_numpy(a.ravel()).cuda()
+        return buf[1:].view(shape)
+    Qo, Wo = oracle.project(q, w, axis, 2.0e21)
+    Q, Wd = thor.ray_project(shifted(q), shifted(w), axis, 2.0e21)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(Q.cpu().numpy(), Qo, rtol=1e-12)
+    np.testing.assert_allclose(Wd.cpu().numpy(), Wo, rtol=1e-12)
