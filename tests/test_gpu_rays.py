@@ -43,7 +43,7 @@ def fields(shape, seed, empty_frac=0.3):
     return n, T, v
 
 
-@pytest.mark.parametrize("shape", [(37, 45, 70), (600, 3, 5), (2, 3, 5000)])
+@pytest.mark.parametrize("shape", [(37, 45, 70), (600, 3, 5), (2, 3, 5000), (300, 4, 16)])
 @pytest.mark.parametrize("axis", [0, 1, 2])
 @pytest.mark.parametrize("weighted", [False, True])
 def test_projection_matches_oracle(shape, axis, weighted):
