@@ -220,24 +220,25 @@ __global__ __launch_bounds__(kThreads) void k_project_rows4(
 // w(z) = (i/pi) int exp(-t^2) / (z - t) dt at z = x + i a:
 //   w(z) ~ (i / sqrt(pi)) sum_n (2n - 1)!! / 2^n  z^-(2n+1),
 // so H = Re w = -Im(S) / sqrt(pi) with S that sum (the Gaussian part,
-// exp(-x^2), is below 1e-43 there).  Dropping the terms after n = N changes H
-// by about (2N + 3) c_(N+1) / x^(2N+2) relative: N = 6 from |x| = 20 in FP64
-// (1e-14), N = 4 from |x| = 10 in FP32 (3e-8).
-template <class R> struct Wing;
-template <> struct Wing<double> { static constexpr double x0 = 20.0; static constexpr int n = 6; };
-template <> struct Wing<float> { static constexpr float x0 = 10.0f; static constexpr int n = 4; };
-
-template <class R>
+// exp(-x^2), is below 1e-18 of H there).  Dropping the terms after n = N
+// changes H by about (2N + 3) c_(N+1) / x^(2N+2) relative.  FP64: N = 6 from
+// |x| = 20 and N = 9 from |x| = 12 (both below 4e-15); nearer the line the
+// FP64 Voigt function.  FP32: N = 4 from |x| = 6.5 (3e-6), where the FP32
+// Taylor branch takes over, so the continued fraction is never used in FP32.
+template <class R, int N>
 __device__ __forceinline__ R voigt_wing(R a, R x) {
-    constexpr R c[7] = {R(1.0), R(0.5), R(0.75), R(1.875), R(6.5625), R(29.53125), R(162.421875)};
+    // c_n = (2n - 1)!! / 2^n
+    constexpr R c[10] = {R(1.0), R(0.5), R(0.75), R(1.875), R(6.5625), R(29.53125), R(162.421875),
+                         R(1055.7421875), R(7918.06640625), R(67303.564453125)};
+    static_assert(N >= 1 && N <= 9, "series length");
     R r;
     if constexpr (sizeof(R) == 8) r = 1.0 / (x * x + a * a);
     else r = __builtin_amdgcn_rcpf(x * x + a * a);
     const R zr = x * r, zi = -a * r;                        // zeta = 1 / z
     const R qr = zr * zr - zi * zi, qi = R(2) * zr * zi;    // zeta^2
-    R pr = c[Wing<R>::n], pi = R(0);
+    R pr = c[N], pi = R(0);
 #pragma unroll
-    for (int k = Wing<R>::n - 1; k >= 0; --k) {
+    for (int k = N - 1; k >= 0; --k) {
         const R nr = pr * qr - pi * qi + c[k];
         pi = pr * qi + pi * qr;
         pr = nr;
@@ -247,7 +248,14 @@ __device__ __forceinline__ R voigt_wing(R a, R x) {
 
 template <class R>
 __device__ __forceinline__ R voigt_forest(R a, R x) {
-    return fabs(x) >= Wing<R>::x0 ? voigt_wing<R>(a, x) : voigt<R>(a, x);
+    const R ax = fabs(x);
+    if constexpr (sizeof(R) == 8) {
+        if (ax >= 20.0) return voigt_wing<double, 6>(a, x);
+        if (ax >= 12.0) return voigt_wing<double, 9>(a, x);
+        return voigt64(a, x);
+    } else {
+        return ax >= 6.5f ? voigt_wing<float, 4>(a, x) : voigt32(a, x);
+    }
 }
 
 // eq. (abs): one workgroup per (ray, block of kThreads bins).  Per cell the
