@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--web-warmup", type=int, default=1, help="untimed web run of a tenth of the packets first")
     ap.add_argument("--rays-only", type=int, default=0,
                     help="time only the raytracing driver (projections and forest spectra) on the web box")
+    ap.add_argument("--rays", type=int, default=1,
+                    help="add the raytracing driver's figures (device-built fields) to the bench line")
     ap.add_argument("--rays-grid", type=int, default=512)
     ap.add_argument("--rays-reps", type=int, default=20, help="timed launches per raytracing kernel")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -228,7 +230,7 @@ def web_box(a, kw):
             "roofline": roof}
 
 
-def rays_box(a):
+def rays_box(a, device_fields=False):
     """Raytracing driver on the forest workload (web box at z = 2): column-
     density projections along each axis (HBM-bound: 4 B read per cell) and
     the absorption spectra of one tomography plane, FP64 and mixed (bound by
@@ -237,9 +239,9 @@ def rays_box(a):
 
     import workloads as W
     from paper_2507_11603_amd import thor
-    wl = W.forest(a.rays_grid)
+    wl = W.forest(a.rays_grid, device="cuda" if device_fields else None)
     o = wl["opts"]
-    n, T, v = (torch.from_numpy(f).cuda() for f in wl["fields"])
+    n, T, v = (f if device_fields else torch.from_numpy(f).cuda() for f in wl["fields"])
     cells = n.numel()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -392,6 +394,14 @@ def main():
         out["serving"] = serving(a, kw)
     if a.web_grid:
         out["web"] = web_box(a, kw)
+    if a.rays:
+        r = rays_box(a, device_fields=True)
+        out["rays"] = {"workload": r["workload"] + " (device-built fields)",
+                       "projection_GBps": {k: v["achieved_GBps"] for k, v in r["projection"].items()},
+                       "projection_hbm_frac": {k: v["hbm_frac"] for k, v in r["projection"].items()},
+                       "forest_ms": {k: v["ms"] for k, v in r["forest"].items()},
+                       "forest_voigt_evals_per_s": {k: v["voigt_evals_per_s"] for k, v in r["forest"].items()},
+                       "forest_rays": r["forest"]["fp64"]["rays"]}
     if cpu:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

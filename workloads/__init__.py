@@ -171,24 +171,42 @@ def forest_fields(n: int = 512, n_mean: float = 2e-11, entropy: int = 2507_11603
     return dens, temp, vz
 
 
+def forest_fields_torch(n: int = 512, n_mean: float = 2e-11, entropy: int = 2507_11603, device="cuda"):
+    """Device-tensor version of `forest_fields` (the torch streams of
+    `web_fields_torch`: different numbers, same statistics)."""
+    import torch
+    seeds = [int(s.generate_state(1)[0]) for s in np.random.SeedSequence(entropy).spawn(4)]
+    dens = grf_torch(n, -2.5, seeds[0], device)
+    dens.mul_(2.0).exp_()
+    dens.mul_(n_mean / dens.mean(dtype=torch.float64).item())
+    temp = torch.sqrt(dens / n_mean).mul_(1e4)
+    vz = grf_torch(n, -2.5, seeds[3], device).mul_(100.0 * KMS)
+    return dens, temp, vz
+
+
 _FOREST_CACHE = {}
 
 
 def forest(n_grid: int = 512, box_pmpc: float = 17.22, hubble_kms_mpc: float = 203.6,
-           n_sub: int = 4, nb: int = 2048):
+           n_sub: int = 4, nb: int = 2048, device=None):
     """Absorption spectra along z through the web box at z = 2 (box 17.22
     proper Mpc, H(z = 2) = 203.6 km/s/Mpc for a flat Omega_m = 0.309
     cosmology): one tomography plane of n_grid rays (all x at y = n_grid/2),
     n_sub steps per cell (H ds / n_sub = 1.7 km/s at 512^3, well below the
     12.8 km/s thermal speed at 1e4 K), nb bins over -500 .. 4000 km/s (the
-    Hubble span of the box is 3505 km/s).  Fields are cached per size."""
-    if n_grid not in _FOREST_CACHE:
-        _FOREST_CACHE[n_grid] = forest_fields(n_grid)
+    Hubble span of the box is 3505 km/s).  Host fields are cached per size;
+    device="cuda" builds device tensors instead (not cached)."""
+    if device is not None:
+        fields = forest_fields_torch(n_grid, device=device)
+    else:
+        if n_grid not in _FOREST_CACHE:
+            _FOREST_CACHE[n_grid] = forest_fields(n_grid)
+        fields = _FOREST_CACHE[n_grid]
     L = box_pmpc * 1e3 * KPC
     H = hubble_kms_mpc * KMS / (1e3 * KPC)
     opts = dict(axis=2, ds=L / n_grid, hubble=H, n_sub=n_sub, rays=(0, n_grid, n_grid // 2, 1),
                 nb=nb, u_lo=-500.0 * KMS, u_hi=4000.0 * KMS)
-    return {"fields": _FOREST_CACHE[n_grid], "opts": opts}
+    return {"fields": fields, "opts": opts}
 
 
 def web(n_grid: int = 1024, n_packets: int = 100_000_000, seed: int = 3, box_pmpc: float = 17.22,
