@@ -223,8 +223,8 @@ __global__ __launch_bounds__(kThreads) void k_project_rows4(
 // so H = Re w = -Im(S) / sqrt(pi) with S that sum (the Gaussian part,
 // exp(-x^2), is below 1e-18 of H there).  Dropping the terms after n = N
 // changes H by about (2N + 3) c_(N+1) / x^(2N+2) relative.  FP64: N = 6 from
-// |x| = 20 and N = 9 from |x| = 12 (both below 4e-15); nearer the line the
-// FP64 Voigt function.  FP32: N = 4 from |x| = 6.5 (3e-6), where the FP32
+// |x| = 20 (1e-14) and N = 9 from |x| = 12 (4e-15); nearer the line the FP64
+// Voigt function.  FP32: N = 4 from |x| = 6.5 (3e-6), where the FP32
 // Taylor branch takes over, so the continued fraction is never used in FP32.
 template <class R, int N>
 __device__ __forceinline__ R voigt_wing(R a, R x) {

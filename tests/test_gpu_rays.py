@@ -164,3 +164,34 @@ def test_projection_unaligned_fields(axis):
     torch.cuda.synchronize()
     np.testing.assert_allclose(Q.cpu().numpy(), Qo, rtol=1e-12)
     np.testing.assert_allclose(Wd.cpu().numpy(), Wo, rtol=1e-12)
+
+
+def test_ray_calls_replay_in_a_graph():
+    """Both calls record no memset and allocate nothing once the Dawson tables
+    are on the device, so they can be captured: three replays, with eager
+    work and synchronisation between them, each equal to the eager result."""
+    shape = (300, 4, 16)                          # axis z: a split 16-byte projection
+    n, T, v = fields(shape, 9)
+    dn, dT, dv = dev(n), dev(T), dev(v)
+    Qe, We = thor.ray_project(dn, dT, 2, 1.0e21)
+    te = thor.ray_forest(dn, dT, dv, 1, 2.0e21, 6.6e-18, 2, (0, 16, 0, 3), 300, -1e7, 3e7)
+    torch.cuda.synchronize()
+    Q = torch.zeros_like(Qe); Wd = torch.zeros_like(We); tau = torch.zeros_like(te)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            thor.ray_project(dn, dT, 2, 1.0e21, out=(Q, Wd))
+            thor.ray_forest(dn, dT, dv, 1, 2.0e21, 6.6e-18, 2, (0, 16, 0, 3), 300, -1e7, 3e7, out=tau)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        Q.fill_(-1.0); Wd.fill_(-1.0); tau.fill_(-1.0)
+        junk = torch.randn(1 << 20, device="cuda").sum()       # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        torch.testing.assert_close(Q, Qe, rtol=1e-12, atol=0)
+        torch.testing.assert_close(Wd, We, rtol=1e-12, atol=0)
+        assert torch.equal(tau, te), rep
