@@ -57,7 +57,7 @@ typedef struct {
     int32_t n_sub;         /* equal steps per cell, each evaluated at its midpoint
                               (1 .. 65536); H ds / n_sub well below v_th keeps the
                               Hubble shift per step below the line width */
-    uint32_t nb;           /* spectral bins (>= 1) */
+    uint32_t nb;           /* spectral bins (1 .. 2^22) */
     double u_lo, u_hi;     /* bin range, cm/s (u_hi > u_lo) */
     int32_t precision;     /* THOR_PREC_FP64, or THOR_PREC_MIXED: the Voigt
                               function and its argument in FP32, sums in FP64 */

@@ -486,7 +486,7 @@ thor_status thor_ray_forest(const thor_ray_grid* g, const thor_forest_opts* o, c
         return fail(THOR_E_INVAL, "rays [%d, %d) x [%d, %d) outside the %d x %d rays of the axis",
                     o->i0, o->i0 + o->ni, o->j0, o->j0 + o->nj, ni, nj);
     if (o->n_sub < 1 || o->n_sub > 65536) return fail(THOR_E_INVAL, "n_sub must be in 1..65536");
-    if (o->nb < 1 || o->nb > (1u << 24)) return fail(THOR_E_INVAL, "nb must be in 1..2^24");
+    if (o->nb < 1 || o->nb > (1u << 22)) return fail(THOR_E_INVAL, "nb must be in 1..2^22");
     if (!(o->u_hi > o->u_lo) || !std::isfinite(o->u_lo) || !std::isfinite(o->u_hi))
         return fail(THOR_E_INVAL, "need finite u_lo < u_hi");
     if (!std::isfinite(o->hubble)) return fail(THOR_E_INVAL, "hubble must be finite");

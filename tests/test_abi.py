@@ -104,7 +104,9 @@ def test_ray_calls_validate_on_the_host(lib):
     assert b"outside" in lib.thor_ray_last_error()
     o.ni, o.n_sub = 4, 0
     assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == -1
-    o.n_sub, o.u_hi = 1, 0.0
+    o.n_sub, o.nb = 1, (1 << 22) + 1
+    assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == -1
+    o.nb, o.u_hi = 8, 0.0
     assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == -1
     o.u_hi, o.precision = 1.0, 7
     assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == -1
