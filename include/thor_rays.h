@@ -43,10 +43,10 @@ typedef struct {
  * The mean of q weighted by w along a ray is Q / W (a mass-weighted
  * temperature map takes q = T and w = the gas mass of a cell).
  * q, w: device float32 fields; Q, W: device float64 images [j][i] (W may be
- * NULL).  Sums are FP64; for long rays the ray is split into segments whose
- * partial sums are added atomically, so the last bits of Q depend on their
- * order.  Errors: THOR_E_INVAL (bad grid, NULL q or Q), THOR_E_DEVICE
- * (launch failed). */
+ * NULL).  Sums are FP64.  When an image has too few rays to fill the GPU,
+ * each ray is split into segments whose partial sums are added atomically,
+ * so the last bits of Q and W then depend on their order.  Errors:
+ * THOR_E_INVAL (bad grid, NULL q or Q), THOR_E_DEVICE (launch failed). */
 thor_status thor_ray_project(const thor_ray_grid *g, const float *q, const float *w,
                              double *Q, double *W, void *hip_stream);
 
