@@ -177,12 +177,12 @@ def _wing_series(a, x, n_terms):
 @pytest.mark.parametrize("a", [1e-4, 5e-4, 1.3e-2, 0.05])
 def test_far_wing_series_lengths(a):
     """The absorption-spectrum kernels evaluate H(a, x) far from the line by
-    the asymptotic series of w(z): FP64 with 6 terms from |x| = 20 and 9 from
-    |x| = 12, FP32 with 4 terms from |x| = 6.5.  At and beyond those
-    thresholds the truncated series stays within 1.1e-14 (FP64) and 3e-6
-    (FP32) of the oracle's Voigt function, for damping parameters of 10 K to
-    1e6 K gas."""
-    for x0, n, tol in ((20.0, 6, 1.1e-14), (12.0, 9, 1.1e-14), (6.5, 4, 3e-6)):
+    the asymptotic series of w(z): FP64 with 4 terms from |x| = 40, 6 from
+    |x| = 20 and 9 from |x| = 12, FP32 with 4 terms from |x| = 6.5.  At and
+    beyond those thresholds the truncated series stays within 3.5e-14 (FP64)
+    and 3e-6 (FP32) of the oracle's Voigt function, for damping parameters of
+    10 K to 1e6 K gas."""
+    for x0, n, tol in ((40.0, 4, 3.5e-14), (20.0, 6, 1.1e-14), (12.0, 9, 1.1e-14), (6.5, 4, 3e-6)):
         for x in (x0, x0 * 1.5, x0 * 4, -x0):
             h = oracle.voigt(a, x)
             assert abs(_wing_series(a, x, n) / h - 1) < tol, (x0, n, x)
