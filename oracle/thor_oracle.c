@@ -9,7 +9,8 @@
  * Style: each step is written in the order the paper states it, with no
  * blocking, fusion or reordering, so a reader can check it against the
  * paper.  Where the paper is silent (constants, RNG slot map, image plane,
- * u_parallel envelope split) the readings are the ones listed in the design doc.
+ * u_parallel envelope split) the reading taken is stated in the comment
+ * beside the code that takes it.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared thor_oracle.c -lm
  */
@@ -170,7 +171,9 @@ enum { SLOT_TYPE = 0, SLOT_UPERP = 1, SLOT_MU = 2, SLOT_TAU = 3, SLOT_UPAR = 4 }
 /* exp(-u^2) x^-2 exp(2u/x + c u^2/x^2) >= f, with c = h(u0/x),              */
 /* h(t) = (-2 ln(1-t) - 2t)/t^2 (h increases with t, so                      */
 /* (1 - u/x)^-2 <= exp(2t + c t^2) for all u <= u0).  Exact as well.        */
-/* u0 rules (speed only): see the design doc.                                    */
+/* u0 rules (speed only; any u0 gives exact samples): |x| < 2.25, two steps */
+/* of u0 <- x - sqrt(a expm1(u0^2) / (2 pi u0)) from u0 = x; |x| >= 2.25,     */
+/* u0 = min(sqrt(ln(sqrt(pi) x^2 / a) + 3), x - 0.3/x).                      */
 /* Trial j draws from slot 4 + 2j (choice, acceptance) and, for a Gaussian  */
 /* proposal, slot 5 + 2j (radius, angle).                                    */
 /* ---------------------------------------------------------------------- */
