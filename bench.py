@@ -282,7 +282,7 @@ def rays_box(a, device_fields=False):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % a.gpus,
+        print("bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus %d" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     if a.rays_only:
