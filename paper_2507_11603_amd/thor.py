@@ -1,7 +1,8 @@
-"""ctypes binding of libthor.so (include/thor.h).
+"""ctypes binding of libthor.so (include/thor.h: the transport; include/thor_rays.h:
+the raytracing driver's projections and absorption spectra).
 
-Argument marshalling only: every step of the transport runs in the HIP
-kernels of libthor.so.  PyTorch supplies device memory and the stream.
+Argument marshalling only: every step of the transport and of the raytracing
+runs in the HIP kernels of libthor.so.  PyTorch supplies device memory and the stream.
 Importing works without a GPU; any call that needs the library raises if
 libthor.so has not been built (``__graft_entry__.build()``).
 """
