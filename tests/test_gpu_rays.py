@@ -79,16 +79,17 @@ def test_forest_matches_oracle(axis, precision, rtol):
     np.testing.assert_allclose(got, ref, rtol=rtol, atol=0)
 
 
-def test_forest_long_ray_spans_lds_chunks():
+@pytest.mark.parametrize("precision,rtol", [("fp64", 1e-10), ("mixed", 1e-4)])
+def test_forest_long_ray_spans_lds_chunks(precision, rtol):
     shape = (1, 2, 1100)                          # 1100 cells: three LDS passes
     n, T, v = fields(shape, 7)
     args = dict(ds=1.0e21, hubble=6.6e-18, n_sub=2, nb=257, u_lo=-5e6, u_hi=7.5e7)
     ref = oracle.forest(n, T, v, 0, args["ds"], args["hubble"], args["n_sub"], [(0, 0), (1, 0)],
                         args["nb"], args["u_lo"], args["u_hi"])
     tau = thor.ray_forest(dev(n), dev(T), dev(v), 0, args["ds"], args["hubble"], args["n_sub"],
-                          (0, 2, 0, 1), args["nb"], args["u_lo"], args["u_hi"], "fp64")
+                          (0, 2, 0, 1), args["nb"], args["u_lo"], args["u_hi"], precision)
     torch.cuda.synchronize()
-    np.testing.assert_allclose(tau.cpu().numpy().reshape(2, -1), ref, rtol=1e-10)
+    np.testing.assert_allclose(tau.cpu().numpy().reshape(2, -1), ref, rtol=rtol)
 
 
 def test_forest_degenerate_inputs():
