@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--rays", type=int, default=1,
                     help="add the raytracing driver's figures (device-built fields) to the bench line")
     ap.add_argument("--rays-grid", type=int, default=512)
+    ap.add_argument("--rays-fields", default="cpu", choices=["cpu", "gpu"],
+                    help="--rays-only fields: numpy-built (as the parity tests) or device-built")
     ap.add_argument("--rays-reps", type=int, default=20, help="timed launches per raytracing kernel")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (PMC calibration)")
@@ -294,7 +296,7 @@ def main():
             sys.exit(1)
         thor.lib()
         calib_copy(a)
-        print(json.dumps({"rays": rays_box(a)}), flush=True)
+        print(json.dumps({"rays": rays_box(a, device_fields=a.rays_fields == "gpu")}), flush=True)
         return
     if a.web_only:
         import torch
