@@ -108,6 +108,17 @@ def lib():
         L.or_transport.argtypes = [C.POINTER(Geometry), C.POINTER(Source), C.POINTER(Opts),
                                    u64, u64, C.c_void_p, C.c_void_p, C.POINTER(Stats),
                                    C.c_void_p]
+        L.or_prepare.restype = C.c_void_p
+        L.or_prepare.argtypes = [C.POINTER(Geometry), C.POINTER(Source), C.POINTER(Opts)]
+        L.or_transport_prepared.restype = C.c_int
+        L.or_transport_prepared.argtypes = [C.c_void_p, u64, u64, C.c_void_p, C.c_void_p,
+                                            C.POINTER(Stats), C.c_void_p]
+        L.or_release.restype = None
+        L.or_release.argtypes = [C.c_void_p]
+        L.or_emit.restype = C.c_int
+        L.or_emit.argtypes = [C.POINTER(Geometry), C.POINTER(Source), u64, u64, C.c_void_p]
+        L.or_scatter_resonant.restype = C.c_int
+        L.or_scatter_resonant.argtypes = [d, d, C.POINTER(d), d, C.c_int, u32, u32, u64, C.c_void_p]
         i32 = C.c_int32
         L.or_project.restype = C.c_int
         L.or_project.argtypes = [C.c_void_p, C.c_void_p, i32, i32, i32, i32, d,
@@ -268,6 +279,77 @@ def run(geom: dict, src: dict, opts: dict, first_id: int, n: int, records: bool 
     out = {"spectrum": spec, "cube": cube, "stats": stats}
     if records:
         out["records"] = rec
+    return out
+
+
+def emit(geom: dict, src: dict, first_id: int, n: int):
+    """The generator alone (Section 3.4 "Emission") for photon ids
+    [first_id, first_id + n): position, direction, lab-frame dv, gas-frame dv
+    (THERMAL spectra) and the emitting cell of every packet."""
+    g, s, _, keep = make_structs(geom, src, {"spectrum": {"nb": 1, "lo": 0.0, "hi": 1.0}})
+    out = np.zeros((n, 11))
+    rc = lib().or_emit(C.byref(g), C.byref(s), int(first_id), int(n), out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("or_emit failed with code %d" % rc)
+    del keep
+    return {"pos": out[:, 0:3], "dir": out[:, 3:6], "dv": out[:, 6], "dv_loc": out[:, 7],
+            "cell": out[:, 8:11].astype(np.int64)}
+
+
+def scatter_resonant(x: float, a: float, k, n: int, x_crit: float = 0.0, phase: str = "iso",
+                     seed: int = 11, event: int = 1):
+    """n resonant scatterings of a photon at gas-frame x along unit k (photon
+    ids 0..n-1): u_par, u_perp (n, 2), x_atom, x_out, k_out (n, 3), trials and
+    the phase function used."""
+    kk = (C.c_double * 3)(*map(float, k))
+    out = np.zeros((n, 10))
+    rc = lib().or_scatter_resonant(float(x), float(a), kk, float(x_crit), PHASE[phase], seed, event,
+                                   int(n), out.ctypes.data)
+    if rc != 0:
+        raise ValueError("or_scatter_resonant: invalid arguments")
+    return {"upar": out[:, 0], "uperp": out[:, 1:3], "x_atom": out[:, 3], "x_out": out[:, 4],
+            "kout": out[:, 5:8], "trials": out[:, 8].astype(np.int64), "phase": out[:, 9].astype(int)}
+
+
+def run_threaded(geom: dict, src: dict, opts: dict, first_id: int, n: int, threads: int,
+                 records: bool = False):
+    """Same result as ``run`` (up to summation order of the FP64 accumulators)
+    with the id range split over `threads` host threads that share one prepared
+    medium (one emission CDF, the caller's field arrays); each thread has its
+    own outputs.  ctypes releases the GIL for the duration of each call."""
+    from concurrent.futures import ThreadPoolExecutor
+    g, s, o, keep = make_structs(geom, src, opts)
+    L = lib()
+    prep = L.or_prepare(C.byref(g), C.byref(s), C.byref(o))
+    if not prep:
+        raise RuntimeError("or_prepare failed")
+    threads = max(1, min(int(threads), n))
+    bounds = np.linspace(0, n, threads + 1).astype(np.int64)
+
+    def part(i):
+        lo, hi = int(bounds[i]), int(bounds[i + 1])
+        spec = np.zeros(o.spec_nb)
+        cube = np.zeros((o.n_obs, o.cube_ny, o.cube_nx, o.cube_nb)) if o.n_obs > 0 else None
+        st = Stats()
+        rec = np.zeros(hi - lo, dtype=RECORD_DTYPE) if records else None
+        rc = L.or_transport_prepared(prep, first_id + lo, hi - lo, spec.ctypes.data,
+                                     None if cube is None else cube.ctypes.data, C.byref(st),
+                                     None if rec is None else rec.ctypes.data)
+        if rc != 0:
+            raise RuntimeError("oracle transport failed with code %d" % rc)
+        return spec, cube, {name: getattr(st, name) for name, _ in Stats._fields_}, rec
+
+    try:
+        with ThreadPoolExecutor(threads) as ex:
+            parts = list(ex.map(part, range(threads)))
+    finally:
+        L.or_release(prep)
+    del keep
+    out = {"spectrum": sum(p[0] for p in parts),
+           "cube": None if parts[0][1] is None else sum(p[1] for p in parts),
+           "stats": {k: sum(p[2][k] for p in parts) for k in parts[0][2]}}
+    if records:
+        out["records"] = np.concatenate([p[3] for p in parts])
     return out
 
 

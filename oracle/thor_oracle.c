@@ -13,6 +13,30 @@
  * beside the code that takes it.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared thor_oracle.c -lm
+ *
+ * What pins each part (tests/test_oracle_*.py, all CPU-only):
+ *   line constants       literature values at 1e4 K
+ *   or_voigt, dawson     scipy's Faddeeva function, 40-digit mpmath, special
+ *                        cases, far-wing series, normalisation
+ *   Philox               published known-answer vectors; AMD rocRAND's header
+ *   u_parallel           exact CDF by quadrature (KS, chi^2), closed-form first
+ *                        and second moments, expected trial counts
+ *   phase functions      exact inverse CDFs, E[mu^2], Henyey-Greenstein E[mu]
+ *   emission             cell frequencies against n^2 / sum n^2, uniform offsets,
+ *                        isotropy, thermal gas-frame profile, Gaussian lines
+ *   resonant scattering  x_out moments and the direction correlation in closed
+ *                        form; core-skip truncation against brute-force
+ *                        rejection sampling and the Exp(1) law of rho^2 - x_c^2
+ *   transport            flux conservation, pure absorber, optically thin
+ *                        limit, single-scattering probability, exact grid peel
+ *                        depth, escape fraction by quadrature, peel
+ *                        normalisation, frame invariance of a moving grid,
+ *                        fitted emergent peaks of the slab and sphere solutions
+ *   raytracing           Gunn-Peterson depth, equivalent width, damping wing,
+ *                        closed-form projections, transposition invariance
+ * Parity unpinned: the spectra and cubes of the expanding-shell and
+ * cosmic-web grids, beyond the invariants above (no independent result
+ * exists for them).
  */
 #include "thor_oracle.h"
 
@@ -664,17 +688,27 @@ static void rotate(const double kin[3], double mu, double phi, double kout[3], d
         kout[i] = mu * kin[i] + s * (c * e1[i] + sn * e2[i]);
 }
 
-static void transport_one(const model_t *m, const or_source *src, uint64_t id, double *spectrum,
-                          double *cube, or_stats *st, or_record *rec)
+/* A packet as the generator hands it over (Section 3.4 "Emission"). */
+typedef struct {
+    loc_t L;
+    double k[3];
+    cellf_t f0;        /* fields at the emission point */
+    double dv;         /* lab-frame frequency offset */
+    double dv_loc;     /* gas-frame offset (THERMAL spectra; 0 otherwise) */
+} emitted_t;
+
+/* Emission (Section 3.4, event 0): isotropic direction, position (the       */
+/* source point, or a cell drawn with probability n_HI^2 / sum n_HI^2 and a   */
+/* uniform point inside it), frequency (delta, Gaussian, or the gas-frame     */
+/* thermal profile of the emitting cell shifted to the lab frame by v.k).     */
+static void emit_packet(const model_t *m, const or_source *src, uint64_t id, emitted_t *e)
 {
     const or_geometry *g = m->g;
-    const or_opts *op = m->o;
     const uint32_t seed = src->seed, req = src->request_id;
     double ua, ub;
     loc_t L;
-    double k[3];
+    double *k = e->k;
 
-    /* Emission (Section 3.4): direction, position, frequency, tau_target. */
     draw2(seed, req, SLOT_E_DIR, 0, id, &ua, &ub);
     double mu = 2.0 * ua - 1.0, phi = 2.0 * PI * ub;
     double st_ = sqrt(fmax(0.0, 1.0 - mu * mu));
@@ -727,6 +761,80 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
     } else {
         dv = src->dv0;
     }
+    e->L = L;
+    e->f0 = f0;
+    e->dv = dv;
+    e->dv_loc = dv_loc;
+}
+
+/* One resonant scattering (Sections 2.3.1, 3.4, 3.4.2). */
+typedef struct {
+    double upar;          /* atom velocity along k_in, units of v_th */
+    double uperp[2];      /* its components along the basis e1, e2 of k_in */
+    double u[3];          /* the atom velocity */
+    double x_atom;        /* x - u_par: frequency in the atom's frame */
+    int phase;            /* phase function used (core/wing picks per x_atom) */
+    double kout[3];
+    double x_out;         /* outgoing gas-frame frequency */
+    uint64_t trials;      /* u_par proposals */
+} scatter_t;
+
+/* Atom velocity u = u_par k + u_perp: u_par from eq. (uparallel), u_perp     */
+/* a 2D Gaussian of variance 1/2 per component (eq. uperp) whose radius is    */
+/* truncated below x_crit when core skipping applies (|x| < x_crit, Section   */
+/* 3.4.2); new direction from the phase function; outgoing frequency          */
+/* x_out = x - u_par + u.k_out (eq. doublelorentztransform, recoil ignored).  */
+static void resonant_scatter(double x, double a, const double k[3], double xcrit, int phase,
+                             uint32_t seed, uint32_t req, uint32_t event, uint64_t id, scatter_t *s)
+{
+    uint64_t trials = 0;
+    double upar = sample_upar_keyed(x, a, seed, req, event, id, &trials);
+    double ur, upsi;
+    draw2(seed, req, SLOT_UPERP, event, id, &ur, &upsi);
+    double rho2 = -log(1.0 - ur);
+    if (xcrit > 0.0 && fabs(x) < xcrit)
+        rho2 += xcrit * xcrit;
+    double rho = sqrt(rho2);
+    double up1 = rho * cos(2.0 * PI * upsi), up2 = rho * sin(2.0 * PI * upsi);
+    double e1[3], e2[3];
+    or_basis(k, e1, e2);
+    for (int i = 0; i < 3; ++i)
+        s->u[i] = upar * k[i] + up1 * e1[i] + up2 * e2[i];
+    double x_atom = x - upar;
+    int ph = phase;
+    if (ph == OR_PHASE_CORE_WING && fabs(x_atom) >= 0.2)
+        ph = OR_PHASE_DIPOLE;
+    double um, uf;
+    draw2(seed, req, SLOT_MU, event, id, &um, &uf);
+    double muo = or_sample_mu(ph, um, 0.0);
+    rotate(k, muo, 2.0 * PI * uf, s->kout, e1, e2);
+    s->upar = upar;
+    s->uperp[0] = up1;
+    s->uperp[1] = up2;
+    s->x_atom = x_atom;
+    s->phase = ph;
+    s->x_out = x_atom + dot3(s->u, s->kout);
+    s->trials = trials;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Transport of one packet (Sections 3.4, 2.2-2.3).                          */
+/* ---------------------------------------------------------------------- */
+static void transport_one(const model_t *m, const or_source *src, uint64_t id, double *spectrum,
+                          double *cube, or_stats *st, or_record *rec)
+{
+    const or_geometry *g = m->g;
+    const or_opts *op = m->o;
+    const uint32_t seed = src->seed, req = src->request_id;
+    double ua, ub;
+
+    /* Emission (Section 3.4): direction, position, frequency, tau_target. */
+    emitted_t em;
+    emit_packet(m, src, id, &em);
+    loc_t L = em.L;
+    double k[3] = { em.k[0], em.k[1], em.k[2] };
+    cellf_t f0 = em.f0;
+    double dv = em.dv, dv_loc = em.dv_loc;
     st->emitted++;
     for (int o = 0; o < op->n_obs; ++o) {
         double ko[3];
@@ -797,37 +905,18 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
             } else {
                 /* Resonant scattering (Sections 2.3.1, 3.4, 3.4.2). */
                 double x = (dv - dot3(f.v, k)) / f.vth;
-                uint64_t trials = 0;
-                double upar = sample_upar_keyed(x, f.a, seed, req, event, id, &trials);
-                st->upar_trials += trials;
-                double ur, upsi;
-                draw2(seed, req, SLOT_UPERP, event, id, &ur, &upsi);
-                double rho2 = -log(1.0 - ur);
-                if (m->xcrit > 0.0 && fabs(x) < m->xcrit)
-                    rho2 += m->xcrit * m->xcrit;
-                double rho = sqrt(rho2);
-                double up1 = rho * cos(2.0 * PI * upsi), up2 = rho * sin(2.0 * PI * upsi);
-                or_basis(k, e1, e2);
-                double u[3];
-                for (int i = 0; i < 3; ++i)
-                    u[i] = upar * k[i] + up1 * e1[i] + up2 * e2[i];
-                double x_atom = x - upar;
-                int ph = op->phase;
-                if (ph == OR_PHASE_CORE_WING && fabs(x_atom) >= 0.2)
-                    ph = OR_PHASE_DIPOLE;
-                double um, uf;
-                draw2(seed, req, SLOT_MU, event, id, &um, &uf);
-                double muo = or_sample_mu(ph, um, 0.0);
-                rotate(k, muo, 2.0 * PI * uf, kout, e1, e2);
+                scatter_t sc;
+                resonant_scatter(x, f.a, k, m->xcrit, op->phase, seed, req, event, id, &sc);
+                st->upar_trials += sc.trials;
+                for (int i = 0; i < 3; ++i) kout[i] = sc.kout[i];
                 for (int o = 0; o < op->n_obs; ++o) {
                     double ko[3];
                     obs_dir(op->obs_axis[o], ko);
-                    double c = w * phase_value(ph, dot3(k, ko), 0.0) / (2.0 * PI);
-                    double xo = x_atom + dot3(u, ko);
+                    double c = w * phase_value(sc.phase, dot3(k, ko), 0.0) / (2.0 * PI);
+                    double xo = sc.x_atom + dot3(sc.u, ko);
                     peel(m, &L, o, c, xo * f.vth + dot3(f.v, ko), cube, st);
                 }
-                double x_out = x_atom + dot3(u, kout);
-                dv = x_out * f.vth + dot3(f.v, kout);
+                dv = sc.x_out * f.vth + dot3(f.v, kout);
                 ++n_res;
                 st->n_res++;
             }
@@ -871,52 +960,155 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
     }
 }
 
-int or_transport(const or_geometry *g, const or_source *s, const or_opts *o, uint64_t first_id,
-                 uint64_t n, double *spectrum, double *cube, or_stats *st, or_record *records)
+/* Medium constants of a run: meshless line quantities, grid spacing, the    */
+/* n_HI^2 emission CDF (inclusive prefix, x-fastest order) and x_crit.        */
+static int model_init(model_t *m, const or_geometry *g, const or_source *s, const or_opts *o)
 {
-    model_t m;
-    memset(&m, 0, sizeof m);
-    m.g = g;
-    m.o = o;
+    memset(m, 0, sizeof *m);
+    m->g = g;
+    m->o = o;
     if (g->kind == OR_GRID) {
-        m.dims[0] = g->nx; m.dims[1] = g->ny; m.dims[2] = g->nz;
+        m->dims[0] = g->nx; m->dims[1] = g->ny; m->dims[2] = g->nz;
         for (int ax = 0; ax < 3; ++ax)
-            m.dx[ax] = (g->hi[ax] - g->lo[ax]) / (double)m.dims[ax];
+            m->dx[ax] = (g->hi[ax] - g->lo[ax]) / (double)m->dims[ax];
         if (s->kind == OR_SRC_CELL_N2) {
             size_t nc = (size_t)g->nx * g->ny * g->nz;
-            m.cdf = (double *)malloc(nc * sizeof(double));
-            if (!m.cdf)
+            m->cdf = (double *)malloc(nc * sizeof(double));
+            if (!m->cdf)
                 return -2;
             double acc = 0.0;
             for (size_t i = 0; i < nc; ++i) {
                 double nn = (double)g->f_n[i];
                 acc += nn * nn;
-                m.cdf[i] = acc;
+                m->cdf[i] = acc;
             }
-            m.cdf_total = acc;
+            m->cdf_total = acc;
         }
-        if (o->core_skip == OR_CS_FIXED)
-            m.xcrit = o->x_crit;
-        else if (o->core_skip == OR_CS_ADAPTIVE)
+        if (o && o->core_skip == OR_CS_FIXED)
+            m->xcrit = o->x_crit;
+        else if (o && o->core_skip == OR_CS_ADAPTIVE)
             return -6;
     } else {
         double L = g->r_outer - g->r_inner;
-        or_line_params(g->T, &m.vth, &m.a, &m.sig0);
-        m.n = g->tau0 > 0.0 ? g->tau0 / (m.sig0 * L) : g->n_HI;
-        m.k0 = m.n * m.sig0;
-        m.sigd = g->tau_d > 0.0 ? g->tau_d / (m.n * L) : g->sigma_d;
-        m.kd = m.sigd * m.n;
-        if (o->core_skip == OR_CS_FIXED) {
-            m.xcrit = o->x_crit;
-        } else if (o->core_skip == OR_CS_ADAPTIVE) {
+        or_line_params(g->T, &m->vth, &m->a, &m->sig0);
+        m->n = g->tau0 > 0.0 ? g->tau0 / (m->sig0 * L) : g->n_HI;
+        m->k0 = m->n * m->sig0;
+        m->sigd = g->tau_d > 0.0 ? g->tau_d / (m->n * L) : g->sigma_d;
+        m->kd = m->sigd * m->n;
+        if (o && o->core_skip == OR_CS_FIXED) {
+            m->xcrit = o->x_crit;
+        } else if (o && o->core_skip == OR_CS_ADAPTIVE) {
             /* Section 3.4.2: x_crit = 0.2 (a tau0)^(1/3) for a tau0 >= 1 */
-            double atau = m.a * m.k0 * L;
-            m.xcrit = atau >= 1.0 ? 0.2 * cbrt(atau) : 0.0;
+            double atau = m->a * m->k0 * L;
+            m->xcrit = atau >= 1.0 ? 0.2 * cbrt(atau) : 0.0;
         }
+    }
+    return 0;
+}
+
+struct or_prepared {
+    or_geometry g;
+    or_source s;
+    or_opts o;
+    model_t m;
+};
+
+or_prepared *or_prepare(const or_geometry *g, const or_source *s, const or_opts *o)
+{
+    or_prepared *p = (or_prepared *)calloc(1, sizeof *p);
+    if (!p)
+        return NULL;
+    p->g = *g;
+    p->s = *s;
+    p->o = *o;
+    if (model_init(&p->m, &p->g, &p->s, &p->o) != 0) {
+        free(p->m.cdf);
+        free(p);
+        return NULL;
+    }
+    return p;
+}
+
+int or_transport_prepared(const or_prepared *p, uint64_t first_id, uint64_t n, double *spectrum,
+                          double *cube, or_stats *st, or_record *records)
+{
+    if (!p)
+        return -1;
+    for (uint64_t i = 0; i < n; ++i)
+        transport_one(&p->m, &p->s, first_id + i, spectrum, cube, st, records ? &records[i] : NULL);
+    return 0;
+}
+
+void or_release(or_prepared *p)
+{
+    if (!p)
+        return;
+    free(p->m.cdf);
+    free(p);
+}
+
+int or_transport(const or_geometry *g, const or_source *s, const or_opts *o, uint64_t first_id,
+                 uint64_t n, double *spectrum, double *cube, or_stats *st, or_record *records)
+{
+    model_t m;
+    int rc = model_init(&m, g, s, o);
+    if (rc != 0) {
+        free(m.cdf);
+        return rc;
     }
     for (uint64_t i = 0; i < n; ++i)
         transport_one(&m, s, first_id + i, spectrum, cube, st, records ? &records[i] : NULL);
     free(m.cdf);
+    return 0;
+}
+
+/* Emission only (test access to the generator): rows of 11 doubles per       */
+/* packet: position (3), direction (3), lab dv, gas-frame dv_loc, cell (3).   */
+int or_emit(const or_geometry *g, const or_source *s, uint64_t first_id, uint64_t n, double *out)
+{
+    model_t m;
+    int rc = model_init(&m, g, s, NULL);
+    if (rc != 0) {
+        free(m.cdf);
+        return rc;
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        emitted_t e;
+        emit_packet(&m, s, first_id + i, &e);
+        double *r = out + 11 * i;
+        for (int j = 0; j < 3; ++j) {
+            r[j] = e.L.p[j];
+            r[3 + j] = e.k[j];
+            r[8 + j] = (double)e.L.cell[j];
+        }
+        r[6] = e.dv;
+        r[7] = e.dv_loc;
+    }
+    free(m.cdf);
+    return 0;
+}
+
+/* n resonant scatterings at fixed (x, a, k_in), photon ids 0..n-1, event    */
+/* `event`, key (seed, 0): rows of 10 doubles: u_par, u_perp (2), x_atom,     */
+/* x_out, k_out (3), trials, phase used.                                      */
+int or_scatter_resonant(double x, double a, const double k[3], double x_crit, int phase,
+                        uint32_t seed, uint32_t event, uint64_t n, double *out)
+{
+    if (!(a > 0.0) || phase < 0 || phase > 2)
+        return -1;
+    for (uint64_t i = 0; i < n; ++i) {
+        scatter_t sc;
+        resonant_scatter(x, a, k, x_crit, phase, seed, 0u, event, i, &sc);
+        double *r = out + 10 * i;
+        r[0] = sc.upar;
+        r[1] = sc.uperp[0];
+        r[2] = sc.uperp[1];
+        r[3] = sc.x_atom;
+        r[4] = sc.x_out;
+        r[5] = sc.kout[0]; r[6] = sc.kout[1]; r[7] = sc.kout[2];
+        r[8] = (double)sc.trials;
+        r[9] = (double)sc.phase;
+    }
     return 0;
 }
 

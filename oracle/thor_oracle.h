@@ -113,6 +113,26 @@ int or_transport(const or_geometry *g, const or_source *s, const or_opts *o,
                  uint64_t first_id, uint64_t n,
                  double *spectrum, double *cube, or_stats *st, or_record *records);
 
+/* The same run split over threads: or_prepare copies the three structs and
+ * builds the medium constants (the n_HI^2 emission CDF of a grid) once; the
+ * field arrays must outlive it.  or_transport_prepared may then run from
+ * several threads at once on disjoint id ranges, each with its own outputs. */
+typedef struct or_prepared or_prepared;
+or_prepared *or_prepare(const or_geometry *g, const or_source *s, const or_opts *o);
+int or_transport_prepared(const or_prepared *p, uint64_t first_id, uint64_t n,
+                          double *spectrum, double *cube, or_stats *st, or_record *records);
+void or_release(or_prepared *p);
+
+/* the generator alone: rows of 11 doubles per packet, position (3),
+ * direction (3), lab dv, gas-frame dv (THERMAL; else 0), cell (3) */
+int or_emit(const or_geometry *g, const or_source *s, uint64_t first_id, uint64_t n, double *out);
+
+/* n resonant scatterings at fixed (x, a, k_in) with photon ids 0..n-1 at
+ * `event`, key (seed, 0); phase 0 iso, 1 dipole, 2 core/wing: rows of 10
+ * doubles, u_par, u_perp (2), x_atom, x_out, k_out (3), trials, phase used */
+int or_scatter_resonant(double x, double a, const double k[3], double x_crit, int phase,
+                        uint32_t seed, uint32_t event, uint64_t n, double *out);
+
 /* raytracing driver (Section 3.5): rays parallel to grid axis `axis` (0 x, 1 y, 2 z)  */
 /* projection Q = int q w ds, Q_hat = int w ds (w may be NULL: w = 1); images [j][i]  */
 int or_project(const float *q, const float *w, int nx, int ny, int nz, int axis, double ds,

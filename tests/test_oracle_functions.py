@@ -194,6 +194,8 @@ def test_upar_distribution(x, a):
     m1 = a * w.imag / w.real
     s = x - u
     assert abs(s.mean() - m1) < 5 * s.std() / np.sqrt(n) + 1e-12
+    m2 = a / (np.sqrt(np.pi) * w.real) - a * a
+    assert abs(np.mean(s * s) - m2) < 5 * np.std(s * s) / np.sqrt(n) + 1e-12
     # expected trials = envelope mass / target mass
     et = oracle.upar_expected_trials(x, a)
     assert abs(tr.mean() - et) < 5 * np.sqrt(max(et * (et - 1), 1e-3) / n) + 1e-9
