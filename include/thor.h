@@ -318,6 +318,45 @@ thor_status thor_step(thor_ctx *ctx, uint32_t max_events_per_packet, const thor_
  * the request's memory is released (the handle becomes invalid). */
 thor_status thor_poll(thor_ctx *ctx, uint64_t req_id, double *spectrum, thor_stats *st, int *done);
 
+/* ------------------------------------------------ no-allocation transport */
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * Transports every packet queued by thor_emit, like thor_transport with
+ * path PERSISTENT run to completion (the same kernels, so the same packet
+ * histories), but allocates nothing: besides the caller's outputs, every
+ * device buffer of the call (step descriptor, batch and model tables,
+ * counters, queue cursor, the escape spectrum's 32 partial copies) lives in
+ * one static device array of the library, THOR_NOALLOC_SCRATCH_BYTES on each
+ * GPU the library runs on, held until the process ends.  Its address is
+ * looked up once per device in thor_create.
+ *
+ * Limits (THOR_E_INVAL beyond them, context unchanged): at most
+ * THOR_NOALLOC_MAX_BATCHES queued batches and THOR_NOALLOC_MAX_BINS spectrum
+ * bins.  Not supported (THOR_E_UNSUPPORTED): path PLAIN, step_events > 0,
+ * records.  The last packets of a launch are not handed to a tail kernel,
+ * and on a grid with observers every peel ray is marched by the scattering
+ * lane (inline_peel), since the tail list and the peel-seed buffer are not
+ * of a modest size.  Packet histories, spectrum and counters equal those of
+ * thor_transport; cube sums differ only by the order of float atomics.
+ *
+ * Outputs, device memory of the context's device, added to (not cleared):
+ *   d_spectrum  float64[opt->spec_nb], escaped weight per bin as in
+ *               thor_transport;
+ *   d_cube      float32[n_obs][cube_ny][cube_nx][cube_nb] (NULL when
+ *               opt->n_obs = 0).
+ * out_stats (host, may be NULL): this call's counters; the call then waits
+ * for its work.  With out_stats NULL the call only enqueues kernels on the
+ * context's stream and returns (no host synchronisation, no copies).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind; calls that overlap on one GPU (two streams or two contexts) race
+ * and must not be made. */
+#define THOR_NOALLOC_MAX_BATCHES 64
+#define THOR_NOALLOC_MAX_BINS 4096
+#define THOR_NOALLOC_SCRATCH_BYTES 1081344
+thor_status thor_transport_noalloc(thor_ctx *ctx, const thor_transport_opts *opt, double *d_spectrum,
+                                   float *d_cube, thor_stats *out_stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -630,7 +631,61 @@ __global__ void k_zero_u32(unsigned* p, uint64_t n) {
         p[i] = 0u;
 }
 
+// ---------------------------------------------------- no-allocation scratch
+// Layout of the static array that thor_transport_noalloc uses instead of
+// allocated buffers (byte offsets, each 256-aligned): counters and queue
+// cursor, longest history, step descriptor, batch table, model table, the
+// escape spectrum's partial copies.
+constexpr uint64_t na_align(uint64_t b) { return (b + 255) & ~uint64_t(255); }
+constexpr uint64_t kNaMaxBatches = THOR_NOALLOC_MAX_BATCHES;
+constexpr uint64_t kNaMaxBins = THOR_NOALLOC_MAX_BINS;
+constexpr uint64_t kNaCounters = 0;                                      // kNumU64Counters + cursor
+constexpr uint64_t kNaMax = na_align(kNaCounters + (kNumU64Counters + 1) * 8);
+constexpr uint64_t kNaDesc = na_align(kNaMax + 8);
+constexpr uint64_t kNaBatches = na_align(kNaDesc + sizeof(StepDesc));
+constexpr uint64_t kNaModels = na_align(kNaBatches + kNaMaxBatches * sizeof(BatchDev));
+constexpr uint64_t kNaSpec = na_align(kNaModels + kNaMaxBatches * sizeof(ModelDev));
+constexpr uint64_t kNaEnd = kNaSpec + uint64_t(kSpecCopies) * kNaMaxBins * 8;
+static_assert(kNaEnd <= THOR_NOALLOC_SCRATCH_BYTES, "no-allocation scratch too small for its layout");
+
+// Clears the counters, cursor, longest history and the first `spec_words`
+// doubles of the spectrum copies, and writes the step descriptor.
+__global__ void k_na_setup(unsigned char* s, StepDesc d, uint64_t spec_words) {
+    const uint64_t tid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid < kNumU64Counters + 1) reinterpret_cast<unsigned long long*>(s + kNaCounters)[tid] = 0ull;
+    if (tid == 0) {
+        *reinterpret_cast<unsigned long long*>(s + kNaMax) = 0ull;
+        *reinterpret_cast<StepDesc*>(s + kNaDesc) = d;
+    }
+    double* spec = reinterpret_cast<double*>(s + kNaSpec);
+    for (uint64_t i = tid; i < spec_words; i += uint64_t(gridDim.x) * blockDim.x) spec[i] = 0.0;
+}
+
+// Writes entry i of the batch and model tables.
+__global__ void k_na_put(unsigned char* s, uint32_t i, ModelDev m, BatchDev b) {
+    if (threadIdx.x == 0) {
+        reinterpret_cast<ModelDev*>(s + kNaModels)[i] = m;
+        reinterpret_cast<BatchDev*>(s + kNaBatches)[i] = b;
+    }
+}
+
+// Adds the spectrum copies of the scratch into the caller's spectrum.
+__global__ void k_na_fold(const unsigned char* s, double* dst, int nb, int copies) {
+    const double* spec = reinterpret_cast<const double*>(s + kNaSpec);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int c = 0; c < copies; ++c) v += spec[uint64_t(c) * nb + i];
+        dst[i] += v;
+    }
+}
+
 }  // namespace thor
+
+// The scratch of thor_transport_noalloc: one copy per GPU, held until the
+// process ends.  Host code never passes this name to a kernel or a copy (on
+// the host it is only a stand-in for the symbol); it uses the device address
+// that thor_create looks up with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[THOR_NOALLOC_SCRATCH_BYTES];
 
 using namespace thor;
 
@@ -697,6 +752,12 @@ struct ServingReq {
 
 constexpr int kServingMaxModels = 1 << 16;
 constexpr int kServingMaxBatches = 1 << 14;
+
+// Device address of the no-allocation scratch, per device, looked up once
+// (with that device current) by the first thor_create on it.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
 
 }  // namespace
 
@@ -773,6 +834,7 @@ struct thor_ctx {
     uint64_t split_passes = 0;
     hipGraphExec_t s_graph = nullptr;
     int s_graph_prec = -1, s_graph_grid = 0, s_graph_block = 0;
+    unsigned char* d_scratch = nullptr;    // this device's no-allocation scratch (device address)
 
     // serving (continuous batching of shell-model requests)
     bool s_init = false;
@@ -1009,17 +1071,19 @@ template <class R, bool GRID>
 void launch_persistent(thor_ctx* ctx, hipStream_t stream, int grid, int block, const BatchDev* d_b,
                        const StepDesc* d_desc, unsigned long long* cursor, const OutDev& out,
                        const ModelDev* d_models, void* pool_pk, int* pool_alive, const SeedBuf& sb,
-                       bool hand_off = false, unsigned long long* gmax = nullptr) {
+                       bool hand_off = false, unsigned long long* gmax = nullptr,
+                       unsigned long long* gstats = nullptr) {
     PoolDev<R> pool{reinterpret_cast<Pkt<R>*>(pool_pk), pool_alive};
     const TailDev<R> tail = tail_dev<R>(ctx, hand_off);
+    if (!gstats) gstats = ctx->d_stats;
     bool seeds = false;
     if constexpr (GRID) seeds = sb.s != nullptr;
     if (seeds)
         hipLaunchKernelGGL((k_persistent<R, GRID, GRID>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
-                           d_b, d_desc, cursor, out, pool, tail, sb, ctx->d_stats, gmax);
+                           d_b, d_desc, cursor, out, pool, tail, sb, gstats, gmax);
     else
         hipLaunchKernelGGL((k_persistent<R, GRID, false>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
-                           d_b, d_desc, cursor, out, pool, tail, sb, ctx->d_stats, gmax);
+                           d_b, d_desc, cursor, out, pool, tail, sb, gstats, gmax);
 }
 
 // The tail kernel over what the preceding persistent launch handed off (its
@@ -1159,6 +1223,18 @@ thor_status thor_create(thor_ctx** out, int hip_device, void* hip_stream, uint64
                hipEventCreate(&ctx->ev_a) != hipSuccess || hipEventCreate(&ctx->ev_b) != hipSuccess ||
                hipEventCreate(&ctx->ev_c) != hipSuccess))
         s = fail(THOR_E_DEVICE, "hipEventCreate failed");
+    if (!s) {
+        // the no-allocation scratch of this device (hipSetDevice above made it current)
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (hip_device < kMaxDevices && !g_scratch_ptr[hip_device]) {
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+                s = fail(THOR_E_DEVICE, "hipGetSymbolAddress of the no-allocation scratch failed");
+            else
+                g_scratch_ptr[hip_device] = static_cast<unsigned char*>(p);
+        }
+        if (hip_device < kMaxDevices) ctx->d_scratch = g_scratch_ptr[hip_device];
+    }
     if (!s) s = dalloc(ctx, (void**)&ctx->d_desc, sizeof(StepDesc), "step descriptor");
     if (!s && hipHostMalloc((void**)&ctx->h_desc, sizeof(StepDesc)) != hipSuccess)
         s = fail(THOR_E_NOMEM, "pinned host allocation failed");
@@ -1600,6 +1676,84 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         if (left) return THOR_INCOMPLETE;
     }
     ctx->pending.clear();
+    return THOR_OK;
+}
+
+thor_status thor_transport_noalloc(thor_ctx* ctx, const thor_transport_opts* opt, double* d_spectrum,
+                                   float* d_cube, thor_stats* out_stats) {
+    CHECK_CTX(ctx);
+    thor_status s = check_opts(opt);
+    if (s) return s;
+    if (!ctx->has_geom) return fail(THOR_E_STATE, "thor_load_grid first");
+    if (opt->path != THOR_PATH_PERSISTENT) return fail(THOR_E_UNSUPPORTED, "no-allocation transport: PERSISTENT path only");
+    if (opt->step_events) return fail(THOR_E_UNSUPPORTED, "no-allocation transport: no bounded steps");
+    if (opt->records) return fail(THOR_E_UNSUPPORTED, "no-allocation transport: no per-packet records");
+    if (uint64_t(opt->spec_nb) > kNaMaxBins)
+        return fail(THOR_E_INVAL, "no-allocation transport: %d spectrum bins exceed the maximum of %d", opt->spec_nb,
+                    int(kNaMaxBins));
+    if (ctx->pending.size() > kNaMaxBatches)
+        return fail(THOR_E_INVAL, "no-allocation transport: %zu queued batches exceed the maximum of %d",
+                    ctx->pending.size(), int(kNaMaxBatches));
+    if (!d_spectrum) return fail(THOR_E_INVAL, "null spectrum output");
+    if (opt->n_obs > 0 && !d_cube) return fail(THOR_E_INVAL, "null cube output (observers given)");
+    if (!ctx->d_scratch) return fail(THOR_E_UNSUPPORTED, "no scratch address for device %d", ctx->device);
+    if (out_stats) std::memset(out_stats, 0, sizeof *out_stats);
+    if (ctx->pending.empty()) return THOR_OK;
+    const bool grid = ctx->geom.kind == THOR_GEOM_GRID;
+    const bool fp64 = opt->precision == THOR_PREC_FP64;
+    const size_t nb = ctx->pending.size();
+    unsigned char* sc = ctx->d_scratch;
+    std::vector<ModelDev> models(nb);
+    std::vector<BatchDev> batches(nb);
+    uint64_t q = 0;
+    for (size_t i = 0; i < nb; ++i) {
+        s = make_model(ctx, ctx->pending[i].src, *opt, models[i]);
+        if (s) return s;
+        models[i].spec = reinterpret_cast<double*>(sc + kNaSpec);
+        models[i].spec_rep = int(kSpecCopies);
+        batches[i] = BatchDev{q, ctx->pending[i].first_id, ctx->pending[i].n, int(i), 0};
+        q += ctx->pending[i].n;
+    }
+    OutDev out = make_out(ctx, opt);
+    out.cube = d_cube;
+    const int block = opt->block > 0 ? opt->block : 256;
+    const int gsize = launch_grid_size(ctx, opt, block);
+    const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
+    const StepDesc desc{q, int(nb), 0u, turn, 0u};
+    if (out_stats) HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    const uint64_t spec_words = uint64_t(kSpecCopies) * uint64_t(opt->spec_nb);
+    hipLaunchKernelGGL(k_na_setup, dim3(std::max<uint64_t>(1, std::min<uint64_t>(1024, (spec_words + 255) / 256))),
+                       dim3(256), 0, ctx->stream, sc, desc, spec_words);
+    for (size_t i = 0; i < nb; ++i)
+        hipLaunchKernelGGL(k_na_put, dim3(1), dim3(64), 0, ctx->stream, sc, uint32_t(i), models[i], batches[i]);
+    const BatchDev* d_b = reinterpret_cast<const BatchDev*>(sc + kNaBatches);
+    const StepDesc* d_desc = reinterpret_cast<const StepDesc*>(sc + kNaDesc);
+    const ModelDev* d_m = reinterpret_cast<const ModelDev*>(sc + kNaModels);
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(sc + kNaCounters);
+    unsigned long long* gmax = reinterpret_cast<unsigned long long*>(sc + kNaMax);
+    SeedBuf sb;
+    std::memset(&sb, 0, sizeof sb);    // no seed buffer: grid peel rays are marched inline
+    unsigned long long* cur = cnt + kNumU64Counters;
+    if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, d_b, d_desc, cur, out, d_m, nullptr, nullptr, sb, false, gmax, cnt)
+                   : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, d_b, d_desc, cur, out, d_m, nullptr, nullptr, sb, false, gmax, cnt);
+    else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, d_b, d_desc, cur, out, d_m, nullptr, nullptr, sb, false, gmax, cnt)
+              : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, d_b, d_desc, cur, out, d_m, nullptr, nullptr, sb, false, gmax, cnt);
+    hipLaunchKernelGGL(k_na_fold, dim3(std::max(1, std::min(ctx->num_cu, (opt->spec_nb + 255) / 256))), dim3(256), 0,
+                       ctx->stream, sc, d_spectrum, opt->spec_nb, int(kSpecCopies));
+    HIPCHK(ctx, hipGetLastError());
+    ctx->pending.clear();
+    if (!out_stats) return THOR_OK;
+    HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    unsigned long long h[kNumU64Counters + 1], hmax = 0;
+    HIPCHK(ctx, hipMemcpyAsync(h, cnt, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(&hmax, gmax, 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    float ms = 0.0f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    collect_stats(ctx, h, ms, out_stats);
+    out_stats->transport_ms = ms;
+    out_stats->passes = 1;
+    out_stats->max_events = hmax;
     return THOR_OK;
 }
 

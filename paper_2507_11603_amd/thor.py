@@ -32,7 +32,7 @@ OUT = {"spectrum": 0, "cube": 1, "records": 2, "stats": 3}
 SYMBOLS = ["thor_create", "thor_destroy", "thor_load_grid", "thor_emit", "thor_transport",
            "thor_reset_outputs", "thor_read_spectra", "thor_output_bytes", "thor_last_error",
            "thor_eval_voigt", "thor_sample_upar", "thor_submit", "thor_step", "thor_poll",
-           "thor_ray_project", "thor_ray_forest", "thor_ray_last_error"]
+           "thor_ray_project", "thor_ray_forest", "thor_ray_last_error", "thor_transport_noalloc"]
 
 
 class ThorError(RuntimeError):
@@ -147,6 +147,8 @@ def lib():
             "thor_ray_forest": ([C.POINTER(thor_ray_grid), C.POINTER(thor_forest_opts), vp, vp, vp,
                                  vp, vp], C.c_int),
             "thor_ray_last_error": ([], C.c_char_p),
+            "thor_transport_noalloc": ([vp, C.POINTER(thor_transport_opts), vp, vp, C.POINTER(thor_stats)],
+                                       C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -185,6 +187,13 @@ def thor_transport(ctx, opts: thor_transport_opts):
     st = thor_stats()
     code = _check(lib().thor_transport(ctx, C.byref(opts), C.byref(st)), allow_incomplete=True)
     return code, st
+
+
+def thor_transport_noalloc(ctx, opts: thor_transport_opts, spec_ptr, cube_ptr, want_stats: bool = True):
+    st = thor_stats() if want_stats else None
+    _check(lib().thor_transport_noalloc(ctx, C.byref(opts), spec_ptr, cube_ptr,
+                                        C.byref(st) if want_stats else None))
+    return st
 
 
 def thor_reset_outputs(ctx):
@@ -356,6 +365,26 @@ class Transport:
     def transport(self, opts: dict, **kw):
         code, st = thor_transport(self.ctx, make_opts(opts, **kw))
         return code, st.to_dict()
+
+    def transport_noalloc(self, opts: dict, spectrum, cube=None, want_stats=True, **kw):
+        """thor_transport_noalloc into the caller's device tensors `spectrum`
+        (float64[spec_nb]) and `cube` (float32[n_obs][ny][nx][nb] or None),
+        which it adds to; returns the counters (None without want_stats)."""
+        t = self.torch
+        sp = opts["spectrum"]
+        if not (isinstance(spectrum, t.Tensor) and spectrum.is_cuda and spectrum.dtype == t.float64
+                and spectrum.is_contiguous() and spectrum.numel() == sp["nb"]):
+            raise ValueError("spectrum must be a contiguous float64 CUDA tensor of %d bins" % sp["nb"])
+        obs = opts.get("observers", [])
+        if obs:
+            c = opts["cube"]
+            shape = (len(obs), c["ny"], c["nx"], c["nb"])
+            if not (isinstance(cube, t.Tensor) and cube.is_cuda and cube.dtype == t.float32
+                    and cube.is_contiguous() and tuple(cube.shape) == shape):
+                raise ValueError("cube must be a contiguous float32 CUDA tensor of shape %s" % (shape,))
+        st = thor_transport_noalloc(self.ctx, make_opts(opts, path="persistent", **kw), spectrum.data_ptr(),
+                                    cube.data_ptr() if obs else None, want_stats)
+        return st.to_dict() if st is not None else None
 
     def reset(self):
         thor_reset_outputs(self.ctx)
