@@ -1,14 +1,18 @@
 """Benchmark of the Lyman-alpha packet-transport hot path on one MI355X.
 
-One step = one whole pass of the hot path over one batch: emit 1e6 packets
-from the central source of the 128^3 expanding-shell grid, march them with
-the Voigt cross-section in the gas frame, scatter (resonant and dust), peel
-off to the +z cube and bin the escapes.  Inputs are resident in HBM before
-the timed region (the grid is loaded once, untimed).
+Headline workload: the synthetic cosmic-web box on a 1024^3 grid (one GPU's
+share of a large run).  One step = one thor_transport call over 1e8 packets
+emitted in proportion to n_HI^2 with a thermal spectrum: march with the Voigt
+cross-section in the gas frame, resonant scattering with core skipping at
+x_crit = 3, dipole phase, peel-off to three axis observers (512^2 x 200
+cubes), hand-off at the box faces.  Fields are built on the GPU (torch) and
+loaded untimed; pencil records and allocations are made by the warm-up.
 
-Prints one JSON line (see the keys below).  `value` is photon scatterings
-per second (resonant + dust) of the persistent mixed-precision path; the
-plain one-launch-per-batch FP64 path is timed on the same GPU beside it.
+Prints one JSON line.  `value` is photon scatterings per second (resonant +
+dust) of the persistent mixed-precision path over the timed steps; beside it:
+the plain one-launch FP64 path on a sample of the same box, the roofline of
+the dominant kernel, the 128^3 expanding shell, the serving stream, the
+raytracing driver and the CPU oracle on a sample of the same box.
 """
 from __future__ import annotations
 
@@ -22,54 +26,51 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+VALU_PEAK_IPS = 256 * 4 * 2.4e9 / 4    # wave64 VALU instructions/s: 256 CUs x 4 SIMDs, 1 per 4 cycles each
 BYTES_PER_VISIT = 20.0         # (vx, vy, vz, n_HI, T) float32 per cell visit
+METRIC = "photon scatterings/s on 1 MI355X (vs FP64 plain path); p50/p99 shell-request latency"
+KERNEL_NAMES = {"transport": "k_persistent<float, true, true>", "tail": "k_tail<float, true, true>",
+                "peel_pass": "k_peel_pass_f32"}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100,
-                    help="batches of 1e6 packets transported by one call (one persistent launch)")
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--packets", type=int, default=1_000_000)
-    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--steps", type=int, default=1, help="timed thor_transport calls of --packets packets")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed calls of --warmup-packets packets first")
+    ap.add_argument("--warmup-packets", type=int, default=1_000_000)
+    ap.add_argument("--packets", type=int, default=100_000_000)
+    ap.add_argument("--grid", type=int, default=1024)
+    ap.add_argument("--fields", default="gpu",
+                    help="gpu: torch on the device; cpu: numpy on the host; npy:DIR: saved numpy fields")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--path", default="persistent", choices=["persistent", "plain"])
-    ap.add_argument("--plain-steps", type=int, default=2, help="steps of the plain FP64 path (0: skip)")
-    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--waves-per-cu", type=int, default=8)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--turn-visits", type=int, default=0)
-    ap.add_argument("--inline-peel", type=int, default=0, help="march peel rays in the scattering lane")
-    ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=8_000_000,
-                    help="packets of the oracle sample (ids 0..n-1; about 15 s on 16 host cores)")
-    ap.add_argument("--autotune", type=int, default=1, help="pick launch knobs with the autotuner")
-    ap.add_argument("--serving", type=int, default=300, help="requests of the serving stream (0: skip)")
+    ap.add_argument("--wide-lanes", type=int, default=0)
+    ap.add_argument("--plain-packets", type=int, default=20_000,
+                    help="packets of the plain FP64 path on the same box (0: skip)")
+    ap.add_argument("--shell", type=int, default=20, help="batches of 1e6 packets of the 128^3 shell (0: skip)")
+    ap.add_argument("--serving", type=int, default=300, help="measured requests of the serving stream (0: skip)")
     ap.add_argument("--serving-warmup", type=int, default=60)
     ap.add_argument("--serving-rate", type=float, default=200.0)
-    ap.add_argument("--serving-step-events", type=int, default=4096,
-                    help="interactions per lane per serving step (longer steps: fewer launches and host syncs)")
-    ap.add_argument("--web-grid", type=int, default=0,
-                    help="also measure the cosmic-web box at this grid size (fields generated on the GPU)")
-    ap.add_argument("--web-packets", type=int, default=100_000)
-    ap.add_argument("--web-fields", default="gpu", choices=["gpu", "cpu"],
-                    help="make the web fields with torch on the GPU or with numpy on the host")
-    ap.add_argument("--web-only", type=int, default=0,
-                    help="measure only the cosmic-web box and print its record (for counter runs)")
-    ap.add_argument("--web-warmup", type=int, default=1, help="untimed web run of a tenth of the packets first")
-    ap.add_argument("--rays-only", type=int, default=0,
-                    help="time only the raytracing driver (projections and forest spectra) on the web box")
-    ap.add_argument("--rays", type=int, default=1,
-                    help="add the raytracing driver's figures (device-built fields) to the bench line")
+    ap.add_argument("--serving-step-events", type=int, default=4096)
+    ap.add_argument("--serving-only", type=int, default=0, help="print only the serving record")
+    ap.add_argument("--rays", type=int, default=1, help="raytracing driver figures (0: skip)")
+    ap.add_argument("--rays-only", type=int, default=0)
     ap.add_argument("--rays-grid", type=int, default=512)
-    ap.add_argument("--rays-fields", default="cpu", choices=["cpu", "gpu"],
-                    help="--rays-only fields: numpy-built (as the parity tests) or device-built")
-    ap.add_argument("--rays-reps", type=int, default=20, help="timed launches per raytracing kernel")
+    ap.add_argument("--rays-fields", default="cpu", choices=["cpu", "gpu"])
+    ap.add_argument("--rays-reps", type=int, default=20)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
+    ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (PMC calibration)")
+    ap.add_argument("--save-fields", default="", help="write the numpy fields to this directory and exit")
     return ap.parse_args()
 
 
+# ------------------------------------------------------------------ helpers
 def kernel_split(st):
     """Device time and algorithmic cell visits of the kernels of a call.
     Persistent path: the persistent kernel marches main flights and, on the
@@ -95,10 +96,20 @@ def kernel_split(st):
     return out
 
 
+def add_stats(tot, st):
+    if tot is None:
+        return dict(st)
+    for k, v in st.items():
+        if k == "max_events":
+            tot[k] = max(tot[k], v)
+        else:
+            tot[k] = tot[k] + v
+    return tot
+
+
 def counter_record(name):
-    """The committed counter record for workload `name` (two HBM byte passes
-    calibrated on a plain copy, one VALU pass), or None when it is missing or
-    the kernel sources have changed since it was taken."""
+    """The committed counter record for workload `name`, or None when it is
+    missing or the kernel sources have changed since it was taken."""
     from paper_2507_11603_amd import pmc_summary
     path = os.path.join(ROOT, "profiles", "%s_counters.json" % name)
     if not os.path.exists(path):
@@ -109,20 +120,6 @@ def counter_record(name):
         return None
     rec["path"] = os.path.relpath(path, ROOT)
     return rec
-
-
-def attach_counters(roof, split, dom, rec, batches):
-    """HBM traffic per launch of the dominant kernel and VALU activity of both
-    kernels from a counter record (per batch there, scaled to this run)."""
-    kname = {"transport": "k_persistent", "tail": "k_tail", "peel_pass": "k_peel_pass"}[dom]
-    kr = rec["kernels"].get(kname)
-    if kr and "read_bytes_per_batch" in kr and "write_bytes_per_batch" in kr:
-        launches = max(split[dom]["launches"], 1)
-        per_batch = kr["read_bytes_per_batch"] + kr["write_bytes_per_batch"]
-        roof["traffic"] = per_batch * batches / launches
-        roof["traffic_over_algorithmic"] = roof["traffic"] / (BYTES_PER_VISIT * split[dom]["visits"] / launches)
-    roof["counters"] = {"record": rec["path"], "kernels": rec["kernels"],
-                        "read_check": rec.get("read_check"), "write_scale": rec.get("write_scale")}
 
 
 def calib_copy(a):
@@ -138,45 +135,195 @@ def calib_copy(a):
     del x, y
 
 
-def run_steps(T, wl, n, steps, first_id, **kw):
-    """Queue `steps` batches of n packets (distinct photon ids) and transport
-    them with one thor_transport call: the persistent path runs all batches
-    in one launch of resident waves, the plain path one launch per batch."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_call(T, wl, n, first_id, **kw):
+    """Queue n packets (ids first_id..) and transport them with one call."""
     import torch
-    T.reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(steps):
-        T.emit(wl["src"], n, first_id + s * n)
+    T.emit(wl["src"], n, first_id)
     code, st = T.transport(wl["opts"], **kw)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    assert st["emitted"] == n * steps
-    return dt, st
+    assert st["emitted"] == n
+    return st
 
 
-def cpu_baseline(wl, n):
+# ------------------------------------------------------------------ web box
+def web_fields(a):
+    import numpy as np
+
+    import workloads as W
+    if a.fields == "gpu":
+        return W.web_fields_torch(a.grid)
+    if a.fields == "cpu":
+        return W.web_fields(a.grid)
+    if a.fields.startswith("npy:"):
+        d = a.fields[4:]
+        return tuple(np.load(os.path.join(d, "%s.npy" % k), mmap_mode="r")
+                     for k in ("n_HI", "T", "vx", "vy", "vz"))
+    raise ValueError("--fields gpu | cpu | npy:DIR")
+
+
+def web_headline(a, kw):
+    """Warm-up, then K timed calls of --packets packets on the web box.
+    Returns the per-call totals, the wall time, the plain FP64 sample and
+    (when the CPU baseline is asked for) host copies of the fields."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2507_11603_amd import thor
+    f = web_fields(a)
+    host = None
+    if a.cpu_baseline:
+        host = tuple(t.cpu().numpy() if isinstance(t, torch.Tensor) else np.asarray(t) for t in f)
+    wl = W.web(n_grid=a.grid, fields=f, n_packets=a.packets)
+    T = thor.Transport(0)
+    try:
+        T.load(wl["geom"])
+        for k in ("n_HI_field", "T_field", "vx", "vy", "vz"):
+            wl["geom"][k] = None
+        del f
+        torch.cuda.empty_cache()
+        for s in range(a.warmup):      # code loading, seed buffer, packet pool, pencil records
+            run_call(T, wl, a.warmup_packets, 10**13 + s * a.warmup_packets, **kw)
+        T.reset()
+        tot = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(a.steps):
+            st = run_call(T, wl, a.packets, s * a.packets, **kw)
+            tot = add_stats(tot, st)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plain = None
+        if a.plain_packets:
+            t1 = time.perf_counter()
+            pst = run_call(T, wl, a.plain_packets, 3 * 10**12, precision="fp64", path="plain")
+            pdt = time.perf_counter() - t1
+            plain = {"value": (pst["n_res"] + pst["n_dust"]) / pdt, "unit": "scatterings/s",
+                     "packets": a.plain_packets, "seconds": pdt, "packets_per_s": a.plain_packets / pdt,
+                     "scatterings_per_packet": (pst["n_res"] + pst["n_dust"]) / a.plain_packets,
+                     "sample": "ids 3e12.. of the same box, one launch, one thread per packet, peel rays inline"}
+    finally:
+        T.close()
+    return wl, tot, dt, plain, host
+
+
+def roofline_web(tot):
+    split = kernel_split(tot)
+    dom = max(split, key=lambda k: split[k]["ms"])
+    d = split[dom]
+    launches = max(d["launches"], 1)
+    roof = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": d["achieved_GBps"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": d["hbm_frac"], "traffic": None,
+            "launches": d["launches"], "avg_launch_ms": d["ms"] / launches,
+            "algorithmic_bytes_per_launch": BYTES_PER_VISIT * d["visits"] / launches,
+            "bytes_per_visit": BYTES_PER_VISIT}
+    return roof, split, dom
+
+
+def attach_traffic(roof, split, dom, rec, packets):
+    """HBM bytes per launch of the dominant kernel from a counter record of
+    the same workload (per packet there, scaled to this run's launches)."""
+    kname = {"transport": "k_persistent", "tail": "k_tail", "peel_pass": "k_peel_pass"}[dom]
+    kr = rec["kernels"].get(kname)
+    if not kr or "read_bytes_per_batch" not in kr:
+        return
+    per_packet = (kr["read_bytes_per_batch"] + kr["write_bytes_per_batch"]) / max(rec["packets"], 1)
+    launches = max(split[dom]["launches"], 1)
+    roof["traffic"] = per_packet * packets / launches
+    roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes_per_launch"]
+    roof["counters"] = rec["path"]
+
+
+# ------------------------------------------------------------------ CPU oracle
+def cpu_baseline(a, wl, host):
+    """The oracle on a bounded sample of the same box (same fields, ids from
+    0), on --cpu-threads host threads sharing one prepared medium, and on one
+    thread; the sample is sized from a short calibration run."""
     import oracle
-    workers = min(16, os.cpu_count() or 1)
     oracle.build()
-    t0 = time.perf_counter()
-    r = oracle.run_parallel(wl["geom"], wl["src"], wl["opts"], 0, n, workers=workers)
-    dt = time.perf_counter() - t0
+    geom = dict(wl["geom"])
+    for k, v in zip(("n_HI_field", "T_field", "vx", "vy", "vz"), host):
+        geom[k] = v
+    threads = max(1, min(a.cpu_threads, os.cpu_count() or 1))
+    cal = oracle.run_threaded(geom, wl["src"], wl["opts"], 0, 16 * threads, threads, reduce=False)
+    per_packet = max(cal["transport_seconds"], 1e-3) / (16 * threads)
+    n = int(max(8 * threads, min(2_000_000, a.cpu_seconds / per_packet)))
+    r = oracle.run_threaded(geom, wl["src"], wl["opts"], 0, n, threads, reduce=False)
     scat = r["stats"]["n_res"] + r["stats"]["n_dust"]
-    return dict(value=scat / dt, unit="scatterings/s", cores=workers, kind="oracle",
-                sample="%d packets of the same 128^3 shell workload (ids 0..%d, seed 2), "
-                       "%d scatterings in %.1f s over %d processes" % (n, n - 1, scat, dt, workers),
-                packets_per_s=n / dt)
+    dt = r["transport_seconds"]
+    n1 = int(max(4, min(200_000, a.cpu_seconds / 3.0 / (dt / n * threads))))
+    r1 = oracle.run_threaded(geom, wl["src"], wl["opts"], 0, n1, 1, reduce=False)
+    scat1 = r1["stats"]["n_res"] + r1["stats"]["n_dust"]
+    return dict(value=scat / dt, unit="scatterings/s", cores=threads, kind="oracle",
+                sample="packets 0..%d of the same %d^3 web box (seed 3), %d scatterings in %.1f s on %d "
+                       "threads; the same box's first %d packets on 1 thread: %.3g scatterings/s"
+                       % (n - 1, a.grid, scat, dt, threads, n1, scat1 / r1["transport_seconds"]),
+                packets_per_s=n / dt, one_core_value=scat1 / r1["transport_seconds"],
+                one_core_packets=n1, cpu_model=cpu_model(), host_cpus=os.cpu_count())
 
 
-def serving(a, kw):
+# ------------------------------------------------------------------ shell (secondary)
+def shell_box(a):
+    """Expanding shell on 128^3: a.shell batches of 1e6 packets in one call
+    (one persistent launch); bound by VALU and by the longest history."""
+    import torch
+
+    import workloads as W
+    from paper_2507_11603_amd import thor
+    wl = W.shell(n_grid=128, n_packets=1_000_000)
+    T = thor.Transport(0)
+    try:
+        T.load(wl["geom"])
+        kw = dict(precision="mixed", path="persistent", waves_per_cu=8)
+        run_call(T, wl, 1_000_000, 10**12, **kw)
+        T.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(a.shell):
+            T.emit(wl["src"], 1_000_000, s * 1_000_000)
+        _, st = T.transport(wl["opts"], **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        T.close()
+    split = kernel_split(st)
+    dom = max(split, key=lambda k: split[k]["ms"])
+    scat = st["n_res"] + st["n_dust"]
+    out = {"workload": "expanding shell r in [0.8, 1] on a 128^3 grid, N_HI 1e19, v_exp 200 km/s, tau_d 0.5, "
+                       "Gaussian source 20 km/s, dipole, +z cube 128x128x256",
+           "batches": a.shell, "packets": st["emitted"], "seconds": dt, "scatterings_per_s": scat / dt,
+           "packets_per_s": st["emitted"] / dt, "longest_history": st["max_events"],
+           "kernels": split, "dominant": KERNEL_NAMES[dom]}
+    rec = counter_record("shell128")
+    roof = {"bound": "valu", "kernel": KERNEL_NAMES[dom], "achieved": None, "peak": VALU_PEAK_IPS,
+            "unit": "wave64 VALU instructions/s", "frac": None}
+    if rec is not None and dom in ("transport", "tail"):
+        kr = rec["kernels"].get({"transport": "k_persistent", "tail": "k_tail"}[dom], {})
+        if "valu_insts_per_batch" in kr and split[dom]["ms"] > 0:
+            ips = kr["valu_insts_per_batch"] * a.shell / (split[dom]["ms"] / 1e3)
+            roof.update(achieved=ips, frac=ips / VALU_PEAK_IPS, counters=rec["path"])
+    out["roofline"] = roof
+    return out
+
+
+def serving(a):
     """Open-loop stream of shell-model requests through the continuous-batching
     server: p50/p99 latency (completion - arrival) and sustained throughput."""
     import workloads as W
     from paper_2507_11603_amd import serve
     stream = W.request_stream(a.serving + a.serving_warmup, rate_hz=a.serving_rate)
-    srv = serve.ShellServer(precision=a.precision, step_events=a.serving_step_events,
-                            waves_per_cu=kw.get("waves_per_cu", 0), visits_per_turn=kw.get("visits_per_turn", 0))
+    srv = serve.ShellServer(precision=a.precision, step_events=a.serving_step_events)
     try:
         r = srv.run_stream(stream, warmup=a.serving_warmup)
     finally:
@@ -189,47 +336,6 @@ def serving(a, kw):
             "sustained_scatterings_per_s": r["scatterings"] / r["wall_s"], "wall_s": r["wall_s"],
             "steps": r["steps"], "step_events": a.serving_step_events, "budget_deferrals": r["deferrals"],
             "graph_steps": True}
-
-
-def web_box(a, kw):
-    """Cosmic-web box (n_HI^2 thermal emission, x_crit = 3, three observers):
-    cell visits per second and the HBM-gather fraction at 20 B per visit."""
-    import torch
-
-    import workloads as W
-    from paper_2507_11603_amd import thor
-    f = W.web_fields_torch(a.web_grid) if a.web_fields == "gpu" else W.web_fields(a.web_grid)
-    wl = W.web(n_grid=a.web_grid, fields=f)
-    T = thor.Transport(0)
-    try:
-        T.load(wl["geom"])
-        del f, wl["geom"]["n_HI_field"], wl["geom"]["T_field"], wl["geom"]["vx"], wl["geom"]["vy"], wl["geom"]["vz"]
-        if a.web_fields == "gpu":
-            torch.cuda.empty_cache()
-        wkw = {k: v for k, v in kw.items() if k != "visits_per_turn"}
-        if a.web_warmup:
-            run_steps(T, wl, a.web_packets // 10, 1, 10**13, **wkw)       # warm-up (caches, allocations)
-        dt, st = run_steps(T, wl, a.web_packets, 1, 0, **wkw)
-    finally:
-        T.close()
-    visits = st["main_visits"] + st["peel_visits"]
-    ks = st["kernel_ms"] / 1e3
-    ach = BYTES_PER_VISIT * visits / ks / 1e9
-    split = kernel_split(st)
-    dom = max(split, key=lambda k: split[k]["ms"])
-    roof = {"bound": "hbm", "kernel": dom, "achieved": split[dom]["achieved_GBps"], "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": split[dom]["hbm_frac"], "traffic": None}
-    rec = counter_record("web%d" % a.web_grid) if (a.path == "persistent" and a.precision == "mixed") else None
-    # the counter record was taken on the numpy-built fields (no torch kernels under the profiler)
-    if rec is not None and rec.get("packets") == a.web_packets and a.web_fields == "cpu":
-        attach_counters(roof, split, dom, rec, 1)
-    return {"grid": a.web_grid, "packets": a.web_packets, "seconds": dt, "kernel_ms": st["kernel_ms"],
-            "scatterings_per_s": (st["n_res"] + st["n_dust"]) / dt, "packets_per_s": st["emitted"] / dt,
-            "main_visits": st["main_visits"], "peel_visits": st["peel_visits"],
-            "cell_visits_per_s": visits / ks, "passes": st["passes"],
-            "path_hbm": {"achieved": ach, "frac": ach / HBM_PEAK_GBS},
-            "kernels": split,
-            "roofline": roof}
 
 
 def rays_box(a, device_fields=False):
@@ -281,71 +387,56 @@ def rays_box(a, device_fields=False):
     return out
 
 
+def save_fields(a):
+    """Numpy fields of the web box to a directory (for the counter runs,
+    which load them instead of generating them once per pass)."""
+    import numpy as np
+
+    import workloads as W
+    os.makedirs(a.save_fields, exist_ok=True)
+    for k, v in zip(("n_HI", "T", "vx", "vy", "vz"), W.web_fields(a.grid)):
+        np.save(os.path.join(a.save_fields, "%s.npy" % k), v)
+        print("saved %s" % k, flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus %d" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
-    if a.rays_only:
-        import torch
-
-        from paper_2507_11603_amd import thor
-        if not torch.cuda.is_available():
-            print("no HIP device", file=sys.stderr)
-            sys.exit(1)
-        thor.lib()
-        calib_copy(a)
-        print(json.dumps({"rays": rays_box(a, device_fields=a.rays_fields == "gpu")}), flush=True)
+    if a.save_fields:
+        save_fields(a)
         return
-    if a.web_only:
-        import torch
-
-        from paper_2507_11603_amd import thor
-        if not torch.cuda.is_available():
-            print("no HIP device", file=sys.stderr)
-            sys.exit(1)
-        thor.lib()
-        calib_copy(a)
-        kw = dict(precision=a.precision, path=a.path, waves_per_cu=a.waves_per_cu, block=a.block,
-                  inline_peel=bool(a.inline_peel))
-        print(json.dumps({"web": web_box(a, kw)}), flush=True)
-        return
-    import workloads as W
-    wl = W.shell(n_grid=a.grid, n_packets=a.packets)
-    # the CPU baseline runs first, in forked workers, before anything touches the GPU
-    cpu = cpu_baseline(wl, a.cpu_sample) if a.cpu_baseline else None
-
     import torch
 
     from paper_2507_11603_amd import thor
-
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     thor.lib()
     calib_copy(a)
-    T = thor.Transport(0)
-    T.load(wl["geom"])
-    kw = dict(precision=a.precision, path=a.path, waves_per_cu=a.waves_per_cu, block=a.block,
-              visits_per_turn=a.turn_visits, inline_peel=bool(a.inline_peel))
-    tuned = None
-    if a.autotune and a.path == "persistent" and not (a.waves_per_cu or a.block or a.turn_visits or a.inline_peel):
-        from paper_2507_11603_amd import autotune
-        tuned, _ = autotune.tune(T, wl, "shell%d" % a.grid, a.precision,
-                                 log=lambda m: print(m, file=sys.stderr, flush=True))
-        kw.update(tuned)
-    if a.warmup:
-        run_steps(T, wl, a.packets, a.warmup, 10**12, **kw)
-    dt, tot = run_steps(T, wl, a.packets, a.steps, 0, **kw)
+    if a.rays_only:
+        print(json.dumps({"rays": rays_box(a, device_fields=a.rays_fields == "gpu")}), flush=True)
+        return
+    if a.serving_only:
+        print(json.dumps({"serving": serving(a)}), flush=True)
+        return
+    kw = dict(precision=a.precision, path="persistent", waves_per_cu=a.waves_per_cu, block=a.block,
+              visits_per_turn=a.turn_visits, wide_lanes=a.wide_lanes)
+    wl, tot, dt, plain, host = web_headline(a, kw)
+    print("[bench] web %d^3: %d packets in %.2f s" % (a.grid, tot["emitted"], dt), file=sys.stderr, flush=True)
     scat = tot["n_res"] + tot["n_dust"]
     value = scat / dt
+    roof, split, dom = roofline_web(tot)
+    rec = counter_record("web%d" % a.grid) if a.precision == "mixed" else None
+    if rec is not None and rec.get("fields") == a.fields:
+        attach_traffic(roof, split, dom, rec, a.packets)
     visits = tot["main_visits"] + tot["peel_visits"]
-    split = kernel_split(tot)
-    dom = max(split, key=lambda k: split[k]["ms"])
-    achieved = split[dom]["achieved_GBps"]
+    ks = tot["kernel_ms"] / 1e3
+    path_gbs = BYTES_PER_VISIT * visits / ks / 1e9
     out = {
-        "metric": "photon scatterings/s on 1 MI355X (vs FP64 plain path)",
+        "metric": METRIC,
         "value": value,
         "unit": "scatterings/s",
         "n_gpus": 1,
@@ -357,45 +448,32 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if a.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "expanding shell r in [0.8, 1] on a %d^3 grid, N_HI 1e19, v_exp 200 km/s, "
-                               "tau_d 0.5 (albedo 0.3), Gaussian source 20 km/s, dipole, +z peel cube "
-                               "%dx%dx256" % (a.grid, a.grid, a.grid),
-                   "packets_per_step": a.packets, "precision": a.precision, "path": a.path,
-                   "waves_per_cu": kw["waves_per_cu"], "block": kw["block"],
-                   "visits_per_turn": kw["visits_per_turn"], "autotuned": tuned is not None},
+        "config": {"workload": "cosmic-web box %d^3 (L = 17.22 pMpc, log n_HI Gaussian random field P(k) ~ k^-2.5, "
+                               "sigma_ln 2, mean 1e-5 cm^-3, T = 1e4 K (n/mean)^0.5, velocity fields 100 km/s), "
+                               "%d packets per step emitted ~ n_HI^2, thermal spectrum, x_crit 3, dipole, three "
+                               "axis observers 512x512x200, face exits handed off" % (a.grid, a.packets),
+                   "packets_per_step": a.packets, "warmup_packets": a.warmup_packets, "fields": a.fields,
+                   "precision": a.precision, "path": "persistent", "waves_per_cu": a.waves_per_cu,
+                   "block": a.block or 256, "visits_per_turn": a.turn_visits or 256,
+                   "wide_lanes": a.wide_lanes or 8},
         "packets_per_s": tot["emitted"] / dt,
         "scatterings_per_packet": scat / max(tot["emitted"], 1),
-        "cell_visits_per_s": visits / dt,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ({"transport": "k_persistent<float,true,true>", "tail": "k_tail<float,true,true>",
-                                 "peel_pass": "k_peel_pass_f32"}[dom] if a.path == "persistent" else "k_plain"),
-                     "launches": split[dom]["launches"], "batches_per_launch": a.steps / max(split[dom]["launches"], 1),
-                     "kernel_ms": split[dom]["ms"], "visits": split[dom]["visits"],
-                     "bytes_per_visit": BYTES_PER_VISIT,
-                     "upar_trials_per_scattering": tot["upar_trials"] / max(tot["n_res"], 1)},
+        "cell_visits_per_s": visits / ks,
+        "path_hbm": {"achieved": path_gbs, "frac": path_gbs / HBM_PEAK_GBS, "kernel_ms": tot["kernel_ms"],
+                     "main_visits": tot["main_visits"], "peel_visits": tot["peel_visits"]},
+        "roofline": roof,
         "kernels": split,
-        # the step ends when its longest packet history does: a few packets per
-        # million scatter 1e4-1e6 times near line centre, and the last of them
-        # run alone, one lane's serial chain of interactions each
-        "longest_history": {"events": tot["max_events"],
-                            "us_per_event_if_alone_for_the_step": dt * 1e6 / max(tot["max_events"], 1),
-                            "tail_kernel_ms": tot.get("tail_ms", 0.0), "tail_events": tot.get("tail_events", 0)},
+        "passes": tot["passes"],
+        "longest_history": tot["max_events"],
     }
-    rec = counter_record("shell%d" % a.grid) if (a.path == "persistent" and a.precision == "mixed") else None
-    if rec is not None:
-        attach_counters(out["roofline"], split, dom, rec, a.steps)
-    if a.plain_steps:
-        pdt, ptot = run_steps(T, wl, a.packets, a.plain_steps, 2 * 10**12, precision="fp64", path="plain")
-        pval = (ptot["n_res"] + ptot["n_dust"]) / pdt
-        out["plain_fp64"] = {"value": pval, "unit": "scatterings/s", "ms_per_step": pdt / a.plain_steps * 1e3,
-                             "packets_per_s": ptot["emitted"] / pdt}
-        out["speedup_vs_plain_fp64"] = value / pval
-    T.close()
+    if plain:
+        out["plain_fp64"] = plain
+        out["speedup_vs_plain_fp64"] = value / plain["value"]
+    del wl["geom"]
+    if a.shell:
+        out["shell"] = shell_box(a)
     if a.serving:
-        out["serving"] = serving(a, kw)
-    if a.web_grid:
-        out["web"] = web_box(a, kw)
+        out["serving"] = serving(a)
     if a.rays:
         r = rays_box(a, device_fields=True)
         out["rays"] = {"workload": r["workload"] + " (device-built fields)",
@@ -404,8 +482,9 @@ def main():
                        "forest_ms": {k: v["ms"] for k, v in r["forest"].items()},
                        "forest_voigt_evals_per_s": {k: v["voigt_evals_per_s"] for k, v in r["forest"].items()},
                        "forest_rays": r["forest"]["fp64"]["rays"]}
-    if cpu:
-        out["cpu_baseline"] = cpu
+    if a.cpu_baseline and host is not None:
+        import workloads as W
+        out["cpu_baseline"] = cpu_baseline(a, W.web(n_grid=a.grid, fields=host, n_packets=a.packets), host)
     print(json.dumps(out), flush=True)
 
 

@@ -312,11 +312,15 @@ def scatter_resonant(x: float, a: float, k, n: int, x_crit: float = 0.0, phase: 
 
 
 def run_threaded(geom: dict, src: dict, opts: dict, first_id: int, n: int, threads: int,
-                 records: bool = False):
+                 records: bool = False, reduce: bool = True):
     """Same result as ``run`` (up to summation order of the FP64 accumulators)
     with the id range split over `threads` host threads that share one prepared
     medium (one emission CDF, the caller's field arrays); each thread has its
-    own outputs.  ctypes releases the GIL for the duration of each call."""
+    own outputs.  ctypes releases the GIL for the duration of each call.
+    'transport_seconds' is the wall time of the threads' transport calls
+    alone (no preparation, no reduction); with reduce=False only the summed
+    counters and that time are returned."""
+    import time
     from concurrent.futures import ThreadPoolExecutor
     g, s, o, keep = make_structs(geom, src, opts)
     L = lib()
@@ -341,13 +345,17 @@ def run_threaded(geom: dict, src: dict, opts: dict, first_id: int, n: int, threa
 
     try:
         with ThreadPoolExecutor(threads) as ex:
+            t0 = time.perf_counter()
             parts = list(ex.map(part, range(threads)))
+            seconds = time.perf_counter() - t0
     finally:
         L.or_release(prep)
     del keep
-    out = {"spectrum": sum(p[0] for p in parts),
-           "cube": None if parts[0][1] is None else sum(p[1] for p in parts),
-           "stats": {k: sum(p[2][k] for p in parts) for k in parts[0][2]}}
+    stats = {k: sum(p[2][k] for p in parts) for k in parts[0][2]}
+    if not reduce:
+        return {"stats": stats, "transport_seconds": seconds}
+    out = {"spectrum": sum(p[0] for p in parts), "transport_seconds": seconds,
+           "cube": None if parts[0][1] is None else sum(p[1] for p in parts), "stats": stats}
     if records:
         out["records"] = np.concatenate([p[3] for p in parts])
     return out

@@ -38,3 +38,22 @@ def test_split_without_tail_or_seeds():
     s = b.kernel_split(st)
     assert "tail" not in s
     assert s["transport"]["visits"] == 40 and s["peel_pass"]["visits"] == 0
+
+
+def test_totals_over_calls_and_headline_roofline():
+    """Per-call stats add up over the timed calls (the longest history is a
+    maximum); the roofline takes the kernel with the most device time, its
+    average launch time and algorithmic bytes per launch."""
+    b = _bench()
+    st = {"transport_ms": 40.0, "tail_ms": 1.0, "peel_ms": 60.0, "passes": 2, "kernel_ms": 101.0,
+          "main_visits": 100, "peel_visits": 1000, "peel_contrib": 50, "tail_main_visits": 1,
+          "tail_peel_visits": 1, "tail_events": 3, "max_events": 7}
+    tot = b.add_stats(None, st)
+    tot = b.add_stats(tot, dict(st, max_events=5))
+    assert tot["passes"] == 4 and tot["peel_visits"] == 2000 and tot["max_events"] == 7
+    roof, split, dom = b.roofline_web(tot)
+    assert dom == "peel_pass" and roof["kernel"] == "k_peel_pass_f32" and roof["bound"] == "hbm"
+    assert roof["launches"] == 4 and abs(roof["avg_launch_ms"] - 30.0) < 1e-12
+    assert abs(roof["algorithmic_bytes_per_launch"] - 20 * (2000 - 100) / 4) < 1e-9
+    assert abs(roof["achieved"] - roof["algorithmic_bytes_per_launch"] / 0.030 / 1e9) < 1e-6
+    assert abs(roof["frac"] - roof["achieved"] / 8000.0) < 1e-12
