@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--turn-visits", type=int, default=0)
     ap.add_argument("--wide-lanes", type=int, default=0)
+    ap.add_argument("--park-lanes", type=int, default=0)
     ap.add_argument("--plain-packets", type=int, default=20_000,
                     help="packets of the plain FP64 path on the same box (0: skip)")
     ap.add_argument("--shell", type=int, default=20, help="batches of 1e6 packets of the 128^3 shell (0: skip)")
@@ -423,7 +424,7 @@ def main():
         print(json.dumps({"serving": serving(a)}), flush=True)
         return
     kw = dict(precision=a.precision, path="persistent", waves_per_cu=a.waves_per_cu, block=a.block,
-              visits_per_turn=a.turn_visits, wide_lanes=a.wide_lanes)
+              visits_per_turn=a.turn_visits, wide_lanes=a.wide_lanes, park_lanes=a.park_lanes)
     wl, tot, dt, plain, host = web_headline(a, kw)
     print("[bench] web %d^3: %d packets in %.2f s" % (a.grid, tot["emitted"], dt), file=sys.stderr, flush=True)
     scat = tot["n_res"] + tot["n_dust"]
@@ -455,7 +456,7 @@ def main():
                    "packets_per_step": a.packets, "warmup_packets": a.warmup_packets, "fields": a.fields,
                    "precision": a.precision, "path": "persistent", "waves_per_cu": a.waves_per_cu,
                    "block": a.block or 256, "visits_per_turn": a.turn_visits or 256,
-                   "wide_lanes": a.wide_lanes or 8},
+                   "wide_lanes": a.wide_lanes or 8, "park_lanes": a.park_lanes or 32},
         "packets_per_s": tot["emitted"] / dt,
         "scatterings_per_packet": scat / max(tot["emitted"], 1),
         "cell_visits_per_s": visits / ks,

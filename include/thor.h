@@ -185,6 +185,12 @@ typedef struct {
                                    packet's next events ahead (same results; a shorter
                                    serial chain for the packets that end a launch);
                                    0 = 8, negative = never, at most 16 */
+    int32_t park_lanes;         /* PERSISTENT: a lane that reaches its interaction site waits
+                                   there while its wave mates march on; the waiting lanes
+                                   interact together once this many wait, no lane marches,
+                                   or the turn ends (same histories; more lanes share the
+                                   long interaction code); 0 = the library default,
+                                   negative = never, at most 64 */
 } thor_transport_opts;
 
 /* Counters of one thor_transport call (device counters read back at the end

@@ -217,6 +217,37 @@ __device__ __forceinline__ double voigt64(double a, double x) {
     return h;
 }
 
+// Far from the line centre H(a, x) follows the asymptotic series of
+// w(z) = (i/pi) int exp(-t^2) / (z - t) dt at z = x + i a:
+//   w(z) ~ (i / sqrt(pi)) sum_n (2n - 1)!! / 2^n  z^-(2n+1),
+// so H = Re w = -Im(S) / sqrt(pi) with S that sum (the Gaussian part,
+// exp(-x^2), is below 1e-18 of H there).  Dropping the terms after n = N
+// changes H by about (2N + 3) c_(N+1) / x^(2N+2) relative.  FP64: N = 4 from
+// |x| = 40 (3e-14), N = 6 from |x| = 20 (1e-14) and N = 9 from |x| = 12
+// (4e-15); nearer the line the FP64 Voigt function.  1 / |z|^2 comes from the
+// hardware reciprocal refined by two Newton steps (FP64) or alone (FP32).
+// FP32 (voigt32): N = 4 beyond |x| = 6.5 (3e-6), where its Taylor branch ends.
+template <class R, int N>
+__device__ __forceinline__ R voigt_wing(R a, R x) {
+    // c_n = (2n - 1)!! / 2^n
+    constexpr R c[10] = {R(1.0), R(0.5), R(0.75), R(1.875), R(6.5625), R(29.53125), R(162.421875),
+                         R(1055.7421875), R(7918.06640625), R(67303.564453125)};
+    static_assert(N >= 1 && N <= 9, "series length");
+    R r;
+    if constexpr (sizeof(R) == 8) r = rcp64(x * x + a * a);
+    else r = __builtin_amdgcn_rcpf(x * x + a * a);
+    const R zr = x * r, zi = -a * r;                        // zeta = 1 / z
+    const R qr = zr * zr - zi * zi, qi = R(2) * zr * zi;    // zeta^2
+    R pr = c[N], pi = R(0);
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        const R nr = pr * qr - pi * qi + c[k];
+        pi = pr * qi + pi * qr;
+        pr = nr;
+    }
+    return -(zr * pi + zi * pr) * R(1.0 / kSqrtPi);         // -Im(zeta P) / sqrt(pi)
+}
+
 __device__ __forceinline__ float voigt32(float a, float x, const float* tab = c_dawson32) {
     const float ax = fabsf(x);
     constexpr float two_rsqpi = float(2.0 / kSqrtPi);
@@ -240,17 +271,7 @@ __device__ __forceinline__ float voigt32(float a, float x, const float* tab = c_
         }
         return sum;
     }
-    float tr = ax, ti = a;
-#pragma unroll
-    for (int k = 6; k >= 1; --k) {
-        const float inv = __builtin_amdgcn_rcpf(tr * tr + ti * ti);
-        const float h = 0.5f * float(k);
-        tr = ax - h * tr * inv;
-        ti = a + h * ti * inv;
-    }
-    float h = __fdividef(ti, (tr * tr + ti * ti) * float(kSqrtPi));
-    if (ax < 9.0f) h += __expf(-ax * ax);
-    return h;
+    return voigt_wing<float, 4>(a, ax);
 }
 
 // A lower bound of H(a, x) that decides sure peel cuts without the profile.
@@ -617,6 +638,7 @@ struct StepDesc {
     uint32_t step_events;  // 0 = run to completion
     uint32_t turn_visits;
     uint32_t wide;         // wide turns at or below this many live lanes (0 = never)
+    uint32_t park;         // lanes at their interaction sites that interact together (0 = no parking)
 };
 
 struct OutDev {

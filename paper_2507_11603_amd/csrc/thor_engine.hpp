@@ -850,16 +850,24 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
 // (kFateNone while it lives on); the packet state is complete on return, so
 // a later call resumes it exactly.  PRE: `pre` holds the draws of events
 // pre_event, pre_event + 1, ... evaluated ahead; max_events must not run
-// past them; `dtab` is the FP32 Dawson table to read (an LDS copy).
+// past them; `dtab` is the FP32 Dawson table the march reads (an LDS copy
+// in the persistent and tail kernels).
 // early_end (persistent waves): the call also ends once a quarter of the
 // lanes that entered it have left, so that the wave refills them without
 // waiting for its longest flight.
+// park (persistent waves, > 0): a lane that reaches its interaction site
+// waits there, its position, opacity and cell fields kept, while the other
+// lanes march on; the waiting lanes interact together once `park` of them
+// wait, once no lane is marching, or when the call ends.  Each packet's
+// arithmetic and its order are unchanged (the same histories); the wave runs
+// the long interaction code for many lanes at once instead of for the few
+// that happen to interact at the same march step.
 template <class R, bool GRID, bool Q = false, bool PRE = false>
 __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt<R>& pk, Counters& cnt,
                        uint32_t max_visits, uint32_t max_events, uint32_t* events_done,
                        const SeedBuf* sb = nullptr, SeedLane* sl = nullptr, CellCache<R>* ccp = nullptr,
                        const EventDraws<R>* pre = nullptr, uint32_t pre_event = 0, JobSink<R>* js = nullptr,
-                       const float* dtab = nullptr, bool early_end = false) {
+                       const float* dtab = c_dawson32, bool early_end = false, uint32_t park = 0) {
     const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
     Loc L;
 #pragma unroll
@@ -882,59 +890,85 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
     int fate = kFateNone;
     uint32_t ev = 0;
     const int n_in = early_end ? __popcll(__ballot(1)) : 0;
-    for (uint32_t vis = 0; vis < max_visits && ev < max_events; ++vis) {
-        // a quarter of the lanes that entered have left (finished packets
-        // wait for a refill): end the turn for all
-        if (early_end && 4 * __popcll(__ballot(1)) <= 3 * n_in) break;
-        int nr, cm;
-        double t;
-        Fields<R> fl;
-        if constexpr (GRID) {
-            t = grid_step<R>(g, L.p, L.c, pk.k, ik, &cm);
-            cached_fields<R>(g, L.c, cc);
-            nr = kRegGas;
-        } else {
-            t = meshless_query<R>(m, L.p, L.region, pk.k, fl, &nr, &cm);
-        }
-        const Fields<R>& f = GRID ? cc.f : fl;
-        cnt.main_visits++;
-        double kt = 0.0;
-        if (f.k0 > 0.0 || f.kd > 0.0) {
-            const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
-            if constexpr (PRE && sizeof(R) == 4) kt = f.k0 * double(voigt32(f.a, x, dtab)) + f.kd;
-            else kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
-        }
-        if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) {
-            if constexpr (Q && !PRE) {
-                // no room for this event's rays: end the turn before it (state
-                // unchanged); the wave claims a new run of slots
-                if (sl->left < uint32_t(o.n_obs)) break;
+    // a lane at its interaction site: the opacity there and (meshless media)
+    // the fields there; on a grid the cell cache keeps the site's fields
+    bool parked = false;
+    double kt_site = 0.0;
+    Fields<R> f_site;
+    if constexpr (!GRID) f_site = Fields<R>{R(1), R(0), 0.0, 0.0, {R(0), R(0), R(0)}};
+    uint32_t vis = 0;
+    for (;;) {
+        // the call ends at the visit or event bound, or once a quarter of the
+        // lanes that entered have left (finished packets wait for a refill)
+        bool stop = !(vis < max_visits && ev < max_events);
+        if (early_end && 4 * __popcll(__ballot(1)) <= 3 * n_in) stop = true;
+        if (!stop && !parked) {
+            ++vis;
+            int nr, cm;
+            double t;
+            Fields<R> fl;
+            if constexpr (GRID) {
+                t = grid_step<R>(g, L.p, L.c, pk.k, ik, &cm);
+                cached_fields<R>(g, L.c, cc);
+                nr = kRegGas;
+            } else {
+                t = meshless_query<R>(m, L.p, L.region, pk.k, fl, &nr, &cm);
             }
-            // interaction site where tau_current = tau_target along the step
-            const double s = div_tau<R>(pk.tau_t - pk.tau_a, kt);
+            const Fields<R>& f = GRID ? cc.f : fl;
+            cnt.main_visits++;
+            double kt = 0.0;
+            if (f.k0 > 0.0 || f.kd > 0.0) {
+                const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
+                if constexpr (sizeof(R) == 4) kt = f.k0 * double(voigt32(f.a, x, dtab)) + f.kd;
+                else kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+            }
+            if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) {
+                if constexpr (Q && !PRE) {
+                    // no room for this event's rays: end the turn before it (state
+                    // unchanged); the wave claims a new run of slots
+                    if (sl->left < uint32_t(o.n_obs)) break;
+                }
+                // interaction site where tau_current = tau_target along the step
+                const double s = div_tau<R>(pk.tau_t - pk.tau_a, kt);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) L.p[i] += s * double(pk.k[i]);
-            pk.event++;
-            ++ev;
-            if (uint64_t(pk.event) > emax) { fate = kFateCapped; break; }
-            fate = interact<R, GRID, Q, PRE>(g, m, o, pk, L, f, kt, key, cnt, sb, sl,
+                for (int i = 0; i < 3; ++i) L.p[i] += s * double(pk.k[i]);
+                pk.event++;
+                ++ev;
+                if (uint64_t(pk.event) > emax) { fate = kFateCapped; break; }
+                parked = true;
+                kt_site = kt;
+                if constexpr (!GRID) f_site = fl;
+            } else {
+                if (isinf(t)) { fate = kFateEscaped; break; }
+                pk.tau_a += kt * t;
+                bool out;
+                if constexpr (GRID) {
+                    out = grid_advance<R>(g, L.p, L.c, pk.k, t, cm);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) L.p[i] += t * double(pk.k[i]);
+                    if (cm) L.region = nr;
+                    out = L.region == kRegOut;
+                }
+                if (out) { fate = kFateEscaped; break; }
+            }
+        }
+        // when the parked lanes interact: at once without parking; with
+        // parking, once `park` lanes wait, no lane marches, or the call ends
+        bool go = parked;
+        if (park) {
+            const uint64_t pm = __ballot(parked);
+            const bool marching = __ballot(!parked && !stop) != 0;
+            go = parked && (stop || uint32_t(__popcll(pm)) >= park || !marching);
+        }
+        if (go) {
+            parked = false;
+            fate = interact<R, GRID, Q, PRE>(g, m, o, pk, L, GRID ? cc.f : f_site, kt_site, key, cnt, sb, sl,
                                              PRE ? pre + (pk.event - pre_event) : nullptr, js);
             if (fate != kFateNone) break;
             set_inverse();
-            continue;
         }
-        if (isinf(t)) { fate = kFateEscaped; break; }
-        pk.tau_a += kt * t;
-        bool out;
-        if constexpr (GRID) {
-            out = grid_advance<R>(g, L.p, L.c, pk.k, t, cm);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 3; ++i) L.p[i] += t * double(pk.k[i]);
-            if (cm) L.region = nr;
-            out = L.region == kRegOut;
-        }
-        if (out) { fate = kFateEscaped; break; }
+        if (stop) break;
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) { pk.p[i] = L.p[i]; pk.c[i] = L.c[i]; }

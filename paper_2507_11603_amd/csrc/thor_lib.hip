@@ -95,11 +95,17 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
     const int nbatch = desc->nbatch;
     const uint32_t step_events = desc->step_events;
     const uint32_t turn_visits = desc->turn_visits;
+    const uint32_t park = desc->park;
     const int hand_off = tail.pk ? int(desc->wide) : 0;
     const uint64_t waves_total = uint64_t(gridDim.x) * (blockDim.x >> 6);
     // peel rays of grid media: first segment at the event, the rest written to
     // the seed buffer for the peel pass (SEEDS: 1..kMaxSeedObs observers)
     constexpr bool useq = GRID && SEEDS;
+    // the FP32 Dawson table in LDS for the march's Voigt evaluations
+    constexpr int kDaw = kDawsonIntervals * (kDawsonDeg32 + 1);
+    __shared__ float daw[kDaw];
+    for (int k = threadIdx.x; k < kDaw; k += blockDim.x) daw[k] = c_dawson32[k];
+    __syncthreads();
     SeedLane sl{0, 0};
     bool stalled = false;          // the seed buffer is full: park and stop
     Counters cnt = {};
@@ -193,7 +199,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
         if (work) {
             const ModelDev& m = models[pk.model];
             const int fate = advance<R, GRID, useq>(g, m, o, pk, cnt, turn_visits, budget - used, &used, &sb, &sl,
-                                                    &cc, nullptr, 0u, nullptr, nullptr, true);
+                                                    &cc, nullptr, 0u, nullptr, daw, true, park);
             if (fate != kFateNone) {
                 finish<R, GRID>(g, m, o, pk, fate, cnt);
                 active = false;
@@ -379,10 +385,15 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
     const uint32_t xcd = blockIdx.x % kXcds; // workgroups are dealt round-robin over the XCDs
     __shared__ uint32_t agg_key[kAggSlots];
     __shared__ float agg_val[kAggSlots];
+    // the FP32 Dawson table in LDS: its lookups are per-lane gathers
+    constexpr int kDaw = kDawsonIntervals * (kDawsonDeg32 + 1);
+    __shared__ float daw[kAxis ? kDaw : 1];
     for (uint32_t i = threadIdx.x; i < kAggSlots; i += blockDim.x) {
         agg_key[i] = 0u;
         agg_val[i] = 0.0f;
     }
+    if constexpr (kAxis)
+        for (uint32_t i = threadIdx.x; i < uint32_t(kDaw); i += blockDim.x) daw[i] = c_dawson32[i];
     __syncthreads();
     uint32_t part = 0;
     for (;;) {
@@ -463,18 +474,14 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
 #pragma unroll
                 for (int j = 0; j < kLook; ++j) {
                     if (j >= mm || cut) break;
-                    const int cj = ca + (pos ? j : -j);
-                    const double face = pos ? lo + double(cj + 1) * dx : lo + double(cj) * dx;
-                    double t = pos ? face - pa : pa - face;
-                    t = t < 0.0 ? 0.0 : t;
+                    // every cell after the event's is crossed whole: segment = cell width
                     cnt.peel_visits++;
                     if (rc[j].k0 > 0.0f || rc[j].kd > 0.0f) {
                         const float x = (dvp - (pos ? rc[j].v : -rc[j].v)) * rc[j].ivth;
                         const float av = float(kDampTimesVth) * rc[j].ivth;
-                        tau += (double(rc[j].k0) * double(voigt32(av, x)) + double(rc[j].kd)) * t;
+                        tau += (double(rc[j].k0) * double(voigt32(av, x, daw)) + double(rc[j].kd)) * dx;
                         cut = tau > o.tau_cut;
                     }
-                    pa = face;
                 }
             } else {
                 CellRec rc[kLook];
@@ -750,6 +757,7 @@ struct ServingReq {
     bool finished;
 };
 
+constexpr uint32_t kDefaultParkLanes = 32;  // lanes that wait before interacting together
 constexpr int kServingMaxModels = 1 << 16;
 constexpr int kServingMaxBatches = 1 << 14;
 
@@ -1038,6 +1046,14 @@ OutDev make_out(thor_ctx* ctx, const thor_transport_opts* o) {
     out.tau_cut = o->tau_cut > 0.0 ? o->tau_cut : 40.0;
     out.max_events = o->max_events;
     return out;
+}
+
+// Lanes of a persistent wave that wait at their interaction sites before
+// they interact together (0: each interacts when it gets there).
+uint32_t park_lanes(const thor_transport_opts* o) {
+    if (o->park_lanes < 0) return 0u;
+    if (o->park_lanes == 0) return kDefaultParkLanes;
+    return o->park_lanes > 64 ? 64u : uint32_t(o->park_lanes);
 }
 
 // Live lanes at or below which a persistent wave takes wide turns.
@@ -1533,7 +1549,8 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         if (opt->step_events > 0xFFFFFFFFull) return fail(THOR_E_INVAL, "step_events must fit 32 bits");
         // unbounded calls hand the last packets of drained waves to k_tail
         const bool hand_off = !bounded && wide_lanes(opt) > 0;
-        *ctx->h_desc = StepDesc{q_end, int(nb), uint32_t(opt->step_events), turn, hand_off ? wide_lanes(opt) : 0u};
+        *ctx->h_desc = StepDesc{q_end, int(nb), uint32_t(opt->step_events), turn, hand_off ? wide_lanes(opt) : 0u,
+                                park_lanes(opt)};
         HIPCHK(ctx, hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(StepDesc), hipMemcpyHostToDevice, ctx->stream));
         if (bounded) {
             s = ensure_pool(ctx, uint64_t(gsize) * block, opt->precision);
@@ -1719,7 +1736,7 @@ thor_status thor_transport_noalloc(thor_ctx* ctx, const thor_transport_opts* opt
     const int block = opt->block > 0 ? opt->block : 256;
     const int gsize = launch_grid_size(ctx, opt, block);
     const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
-    const StepDesc desc{q, int(nb), 0u, turn, 0u};
+    const StepDesc desc{q, int(nb), 0u, turn, 0u, park_lanes(opt)};
     if (out_stats) HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     const uint64_t spec_words = uint64_t(kSpecCopies) * uint64_t(opt->spec_nb);
     hipLaunchKernelGGL(k_na_setup, dim3(std::max<uint64_t>(1, std::min<uint64_t>(1024, (spec_words + 255) / 256))),
@@ -2032,7 +2049,7 @@ thor_status thor_step(thor_ctx* ctx, uint32_t max_events_per_packet, const thor_
     if (nb) std::memcpy(ctx->h_s_batches, ctx->s_batches.data(), nb * sizeof(BatchDev));
     const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
     // nb == 0: only parked packets are left; no lane can take a new index
-    *ctx->h_s_desc = StepDesc{ctx->s_q_total, int(nb), max_events_per_packet, turn, 0u};
+    *ctx->h_s_desc = StepDesc{ctx->s_q_total, int(nb), max_events_per_packet, turn, 0u, park_lanes(opt)};
     if (ctx->s_dirty) {
         const int hi = ctx->s_next_slot;
         HIPCHK(ctx, hipMemcpyAsync(ctx->d_s_models, ctx->s_models.data(), sizeof(ModelDev) * hi,

@@ -70,7 +70,7 @@ class thor_transport_opts(C.Structure):
                 ("waves_per_cu", C.c_int32), ("block", C.c_int32), ("visits_per_turn", C.c_int32),
                 ("use_graph", C.c_int32), ("inline_peel", C.c_int32), ("records", C.c_int32),
                 ("seed_slots", C.c_uint64),
-                ("wide_lanes", C.c_int32)]
+                ("wide_lanes", C.c_int32), ("park_lanes", C.c_int32)]
 
 
 STAT_U64 = ("emitted", "escaped", "absorbed", "capped", "handed_off", "n_res", "n_dust",
@@ -291,7 +291,7 @@ def make_source(src: dict) -> thor_source:
 
 def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_events=0,
               waves_per_cu=0, block=0, visits_per_turn=0, use_graph=False,
-              inline_peel=False, seed_slots=0, wide_lanes=0) -> thor_transport_opts:
+              inline_peel=False, seed_slots=0, wide_lanes=0, park_lanes=0) -> thor_transport_opts:
     o = thor_transport_opts()
     o.precision = PREC[precision]
     o.path = PATH[path]
@@ -322,6 +322,7 @@ def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_ev
     o.records = int(records)
     o.seed_slots = int(seed_slots)
     o.wide_lanes = int(wide_lanes)
+    o.park_lanes = int(park_lanes)
     return o
 
 
