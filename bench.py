@@ -29,6 +29,9 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 VALU_PEAK_IPS = 256 * 4 * 2.4e9 / 4    # wave64 VALU instructions/s: 256 CUs x 4 SIMDs, 1 per 4 cycles each
 BYTES_PER_VISIT = 20.0         # (vx, vy, vz, n_HI, T) float32 per cell visit
 METRIC = "photon scatterings/s on 1 MI355X (vs FP64 plain path); p50/p99 shell-request latency"
+# knobs the autotuner searches on the web box (the others keep the library
+# defaults; every candidate costs three runs of the steady-state sample)
+WEB_SPACE = dict(park_lanes=[16, 32, 48], refill_64ths=[8, 16, 32], wide_lanes=[8, 16])
 KERNEL_NAMES = {"transport": "k_persistent<float, true, true>", "tail": "k_tail<float, true, true>",
                 "peel_pass": "k_peel_pass_f32"}
 
@@ -49,6 +52,12 @@ def parse():
     ap.add_argument("--turn-visits", type=int, default=0)
     ap.add_argument("--wide-lanes", type=int, default=0)
     ap.add_argument("--park-lanes", type=int, default=0)
+    ap.add_argument("--refill-64ths", type=int, default=0)
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="pick the launch knobs with the autotuner on a sample of the box first")
+    ap.add_argument("--autotune-sample", type=int, default=4_000_000,
+                    help="packets per autotuner run: enough for the steady state (a few dozen per lane), "
+                         "so that the drain at the end of a launch does not decide")
     ap.add_argument("--plain-packets", type=int, default=20_000,
                     help="packets of the plain FP64 path on the same box (0: skip)")
     ap.add_argument("--shell", type=int, default=20, help="batches of 1e6 packets of the 128^3 shell (0: skip)")
@@ -194,14 +203,21 @@ def web_headline(a, kw):
             wl["geom"][k] = None
         del f
         torch.cuda.empty_cache()
+        if a.autotune:
+            from paper_2507_11603_amd import autotune
+            tuned, table = autotune.tune(T, wl, "web%d" % a.grid, a.precision, sample=a.autotune_sample,
+                                         space=WEB_SPACE, log=lambda m: print(m, file=sys.stderr, flush=True))
+            kw.update(tuned)
+            kw["autotuned"] = {"sample": a.autotune_sample, "candidates": len(table)}
+        knobs = {k: v for k, v in kw.items() if k != "autotuned"}
         for s in range(a.warmup):      # code loading, seed buffer, packet pool, pencil records
-            run_call(T, wl, a.warmup_packets, 10**13 + s * a.warmup_packets, **kw)
+            run_call(T, wl, a.warmup_packets, 10**13 + s * a.warmup_packets, **knobs)
         T.reset()
         tot = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(a.steps):
-            st = run_call(T, wl, a.packets, s * a.packets, **kw)
+            st = run_call(T, wl, a.packets, s * a.packets, **knobs)
             tot = add_stats(tot, st)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -423,8 +439,9 @@ def main():
     if a.serving_only:
         print(json.dumps({"serving": serving(a)}), flush=True)
         return
-    kw = dict(precision=a.precision, path="persistent", waves_per_cu=a.waves_per_cu, block=a.block,
-              visits_per_turn=a.turn_visits, wide_lanes=a.wide_lanes, park_lanes=a.park_lanes)
+    kw = dict(precision=a.precision, path="persistent", waves_per_cu=a.waves_per_cu, block=a.block or 256,
+              visits_per_turn=a.turn_visits or 256, wide_lanes=a.wide_lanes or 8, park_lanes=a.park_lanes or 32,
+              refill_64ths=a.refill_64ths or 16)
     wl, tot, dt, plain, host = web_headline(a, kw)
     print("[bench] web %d^3: %d packets in %.2f s" % (a.grid, tot["emitted"], dt), file=sys.stderr, flush=True)
     scat = tot["n_res"] + tot["n_dust"]
@@ -454,9 +471,10 @@ def main():
                                "%d packets per step emitted ~ n_HI^2, thermal spectrum, x_crit 3, dipole, three "
                                "axis observers 512x512x200, face exits handed off" % (a.grid, a.packets),
                    "packets_per_step": a.packets, "warmup_packets": a.warmup_packets, "fields": a.fields,
-                   "precision": a.precision, "path": "persistent", "waves_per_cu": a.waves_per_cu,
-                   "block": a.block or 256, "visits_per_turn": a.turn_visits or 256,
-                   "wide_lanes": a.wide_lanes or 8, "park_lanes": a.park_lanes or 32},
+                   "precision": a.precision, "path": "persistent",
+                   "knobs": {k: kw[k] for k in ("waves_per_cu", "block", "visits_per_turn", "wide_lanes",
+                                                "park_lanes", "refill_64ths")},
+                   "autotuned": kw.get("autotuned")},
         "packets_per_s": tot["emitted"] / dt,
         "scatterings_per_packet": scat / max(tot["emitted"], 1),
         "cell_visits_per_s": visits / ks,

@@ -191,7 +191,20 @@ typedef struct {
                                    or the turn ends (same histories; more lanes share the
                                    long interaction code); 0 = the library default,
                                    negative = never, at most 64 */
+    int32_t refill_64ths;       /* PERSISTENT: a turn ends early once this many 64ths of the
+                                   lanes that entered it have finished, so that the wave
+                                   refills them; 0 = 16 (a quarter), 64 = only at the
+                                   visits_per_turn bound */
+    int32_t accum;              /* cube accumulation: THOR_ACCUM_F32_ATOMIC (float32 atomic
+                                   adds; sums depend on their order in the last bits) or
+                                   THOR_ACCUM_FIXED64 (each contribution rounded to an
+                                   integer number of 2^-fixed_bits units and added as a
+                                   uint64: bit-reproducible in any order and launch
+                                   shape; a voxel holds at most 2^(64 - fixed_bits)) */
+    int32_t fixed_bits;         /* FIXED64: 0 = 40 (units of 9.1e-13, voxel sums up to 1.7e7) */
 } thor_transport_opts;
+
+typedef enum { THOR_ACCUM_F32_ATOMIC = 0, THOR_ACCUM_FIXED64 = 1 } thor_accum;
 
 /* Counters of one thor_transport call (device counters read back at the end
  * of the call). */
@@ -228,7 +241,7 @@ typedef struct {
 } thor_record;
 
 typedef enum { THOR_OUT_SPECTRUM = 0, THOR_OUT_CUBE = 1, THOR_OUT_RECORDS = 2,
-               THOR_OUT_STATS = 3 } thor_output;
+               THOR_OUT_STATS = 3, THOR_OUT_CUBE_FIXED = 4 } thor_output;
 
 /* ---------------------------------------------------------------- calls */
 
@@ -264,9 +277,12 @@ thor_status thor_reset_outputs(thor_ctx *ctx);
 
 /* Copy an output to dst (host memory, or device memory when dst_on_device):
  *   SPECTRUM: float64[spec_nb]; CUBE: float32[n_obs][ny][nx][nb] (index
- *   selects nothing and must be 0); RECORDS: thor_record[packets of the last
- *   call]; STATS: thor_stats of the last call.  dst_bytes must be at least
- *   the size of the output (THOR_E_INVAL otherwise). */
+ *   selects nothing and must be 0; a FIXED64 cube is converted, each voxel
+ *   rounded once); CUBE_FIXED: uint64[n_obs][ny][nx][nb], the FIXED64 cube's
+ *   integer sums (units of 2^-fixed_bits; THOR_E_STATE for a float cube);
+ *   RECORDS: thor_record[packets of the last call]; STATS: thor_stats of the
+ *   last call.  dst_bytes must be at least the size of the output
+ *   (THOR_E_INVAL otherwise). */
 thor_status thor_read_spectra(thor_ctx *ctx, thor_output which, uint32_t index, void *dst,
                               uint64_t dst_bytes, int dst_on_device);
 
@@ -340,7 +356,7 @@ thor_status thor_poll(thor_ctx *ctx, uint64_t req_id, double *spectrum, thor_sta
  * Limits (THOR_E_INVAL beyond them, context unchanged): at most
  * THOR_NOALLOC_MAX_BATCHES queued batches and THOR_NOALLOC_MAX_BINS spectrum
  * bins.  Not supported (THOR_E_UNSUPPORTED): path PLAIN, step_events > 0,
- * records.  The last packets of a launch are not handed to a tail kernel,
+ * records, accum FIXED64.  The last packets of a launch are not handed to a tail kernel,
  * and on a grid with observers every peel ray is marched by the scattering
  * lane (inline_peel), since the tail list and the peel-seed buffer are not
  * of a modest size.  Packet histories, spectrum and counters equal those of

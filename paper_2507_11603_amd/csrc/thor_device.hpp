@@ -639,6 +639,8 @@ struct StepDesc {
     uint32_t turn_visits;
     uint32_t wide;         // wide turns at or below this many live lanes (0 = never)
     uint32_t park;         // lanes at their interaction sites that interact together (0 = no parking)
+    uint32_t refill;       // a turn ends once refill/64 of the lanes that entered it have left (64: never early)
+    uint32_t pad;
 };
 
 struct OutDev {
@@ -649,6 +651,8 @@ struct OutDev {
     double img_lo[2], img_w[2];
     double v_lo, v_w;
     float* cube;
+    unsigned long long* cube_fx;   // fixed-point cube (units of 1/fx_scale), used instead of `cube` when set
+    double fx_scale;
     double tau_cut;
     uint64_t max_events;
     double* rec_dv;       // optional per-packet records (SoA), indexed by queue index - q_rec0

@@ -330,6 +330,17 @@ __device__ __forceinline__ int bin_of(double v, double lo, double w, int nb) {
     return (b >= 0.0 && b < double(nb)) ? int(b) : -1;
 }
 
+// A peel contribution c >= 0 into cube element idx: a float32 atomic add, or
+// in the fixed-point mode an integer add of c rounded to units of
+// 1/fx_scale (integer sums do not depend on the order of the additions).
+__device__ __forceinline__ unsigned long long to_fixed(const OutDev& o, double c) {
+    return (unsigned long long)(c * o.fx_scale + 0.5);
+}
+__device__ __forceinline__ void cube_add(const OutDev& o, uint64_t idx, double c) {
+    if (o.cube_fx) atomicAdd(o.cube_fx + idx, to_fixed(o, c));
+    else unsafeAtomicAdd(o.cube + idx, float(c));
+}
+
 // Contribution weight * exp(-tau) of a finished ray into its observer cube
 // at the pixel of the event position and the bin of the peeled frequency.
 __device__ __forceinline__ void peel_deposit(const OutDev& o, int obs, int axis, const double p[3], double dv_peel,
@@ -341,7 +352,7 @@ __device__ __forceinline__ void peel_deposit(const OutDev& o, int obs, int axis,
     const int ib = bin_of(dv_peel, o.v_lo, o.v_w, o.cube_nb);
     if (ix < 0 || iy < 0 || ib < 0) { cnt.peel_dropped++; return; }
     const uint64_t idx = ((uint64_t(obs) * o.cube_ny + iy) * o.cube_nx + ix) * o.cube_nb + ib;
-    unsafeAtomicAdd(o.cube + idx, float(weight * exp(-tau)));
+    cube_add(o, idx, weight * exp(-tau));
 }
 
 // Peel-off ray (Section 3.4.1): tau along the observer axis from the event,
@@ -852,9 +863,9 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
 // pre_event, pre_event + 1, ... evaluated ahead; max_events must not run
 // past them; `dtab` is the FP32 Dawson table the march reads (an LDS copy
 // in the persistent and tail kernels).
-// early_end (persistent waves): the call also ends once a quarter of the
+// refill (persistent waves, 1..63): the call also ends once refill/64 of the
 // lanes that entered it have left, so that the wave refills them without
-// waiting for its longest flight.
+// waiting for its longest flight (0 or 64: only at the visit bound).
 // park (persistent waves, > 0): a lane that reaches its interaction site
 // waits there, its position, opacity and cell fields kept, while the other
 // lanes march on; the waiting lanes interact together once `park` of them
@@ -867,7 +878,7 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
                        uint32_t max_visits, uint32_t max_events, uint32_t* events_done,
                        const SeedBuf* sb = nullptr, SeedLane* sl = nullptr, CellCache<R>* ccp = nullptr,
                        const EventDraws<R>* pre = nullptr, uint32_t pre_event = 0, JobSink<R>* js = nullptr,
-                       const float* dtab = c_dawson32, bool early_end = false, uint32_t park = 0) {
+                       const float* dtab = c_dawson32, uint32_t refill = 0, uint32_t park = 0) {
     const Key key{m.seed, m.req, uint32_t(pk.id), uint32_t(pk.id >> 32)};
     Loc L;
 #pragma unroll
@@ -889,7 +900,10 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
     const uint64_t emax = o.max_events ? o.max_events : 100000000ull;
     int fate = kFateNone;
     uint32_t ev = 0;
+    const bool early_end = refill > 0 && refill < 64;
+    // lanes that must have left before the turn ends early (at least one)
     const int n_in = early_end ? __popcll(__ballot(1)) : 0;
+    const int n_leave = early_end ? max(1, int((uint32_t(n_in) * refill + 63u) >> 6)) : 0;
     // a lane at its interaction site: the opacity there and (meshless media)
     // the fields there; on a grid the cell cache keeps the site's fields
     bool parked = false;
@@ -898,10 +912,10 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
     if constexpr (!GRID) f_site = Fields<R>{R(1), R(0), 0.0, 0.0, {R(0), R(0), R(0)}};
     uint32_t vis = 0;
     for (;;) {
-        // the call ends at the visit or event bound, or once a quarter of the
-        // lanes that entered have left (finished packets wait for a refill)
+        // the call ends at the visit or event bound, or once the refill share
+        // of the lanes that entered have left (finished packets wait for a refill)
         bool stop = !(vis < max_visits && ev < max_events);
-        if (early_end && 4 * __popcll(__ballot(1)) <= 3 * n_in) stop = true;
+        if (early_end && n_in - __popcll(__ballot(1)) >= n_leave) stop = true;
         if (!stop && !parked) {
             ++vis;
             int nr, cm;

@@ -96,6 +96,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
     const uint32_t step_events = desc->step_events;
     const uint32_t turn_visits = desc->turn_visits;
     const uint32_t park = desc->park;
+    const uint32_t refill = desc->refill;
     const int hand_off = tail.pk ? int(desc->wide) : 0;
     const uint64_t waves_total = uint64_t(gridDim.x) * (blockDim.x >> 6);
     // peel rays of grid media: first segment at the event, the rest written to
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
         if (work) {
             const ModelDev& m = models[pk.model];
             const int fate = advance<R, GRID, useq>(g, m, o, pk, cnt, turn_visits, budget - used, &used, &sb, &sl,
-                                                    &cc, nullptr, 0u, nullptr, daw, true, park);
+                                                    &cc, nullptr, 0u, nullptr, daw, refill, park);
             if (fate != kFateNone) {
                 finish<R, GRID>(g, m, o, pk, fate, cnt);
                 active = false;
@@ -343,10 +344,27 @@ constexpr uint32_t kXcds = 8;           // accelerator complex dies of an MI355X
 constexpr uint32_t kAggSlots = 512;     // LDS sums per workgroup (power of two)
 constexpr int kAggProbes = 4;
 
-// Adds v to cube element ci through the workgroup's LDS table (keys: element
-// + 1, 0 = free; short linear probing); a crowded table passes v straight to
-// the cube.
-__device__ __forceinline__ void deposit_lds(uint32_t* keys, float* vals, float* cube, uint64_t ci, float v) {
+// Adds contribution c to cube element ci through the workgroup's LDS table
+// (keys: element + 1, 0 = free; short linear probing); a crowded table
+// passes c straight to the cube.  The table holds float32 sums, or integer
+// sums in the fixed-point mode (V = unsigned long long).
+template <class V> __device__ __forceinline__ V agg_value(const OutDev& o, double c);
+template <> __device__ __forceinline__ float agg_value<float>(const OutDev&, double c) { return float(c); }
+template <> __device__ __forceinline__ unsigned long long agg_value<unsigned long long>(const OutDev& o, double c) {
+    return to_fixed(o, c);
+}
+template <class V> __device__ __forceinline__ void agg_flush(const OutDev& o, uint64_t ci, V v);
+template <> __device__ __forceinline__ void agg_flush<float>(const OutDev& o, uint64_t ci, float v) {
+    unsafeAtomicAdd(o.cube + ci, v);
+}
+template <> __device__ __forceinline__ void agg_flush<unsigned long long>(const OutDev& o, uint64_t ci,
+                                                                         unsigned long long v) {
+    atomicAdd(o.cube_fx + ci, v);
+}
+
+template <class V>
+__device__ __forceinline__ void deposit_lds(uint32_t* keys, V* vals, const OutDev& o, uint64_t ci, double c) {
+    const V v = agg_value<V>(o, c);
     if (ci < 0xFFFFFFFFull) {
         const uint32_t k = uint32_t(ci) + 1u;
         uint32_t h = (k * 2654435761u) & (kAggSlots - 1u);
@@ -360,10 +378,10 @@ __device__ __forceinline__ void deposit_lds(uint32_t* keys, float* vals, float* 
             h = (h + 1u) & (kAggSlots - 1u);
         }
     }
-    unsafeAtomicAdd(cube + ci, v);
+    agg_flush<V>(o, ci, v);
 }
 
-template <class R>
+template <class R, class V>
 __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, const SeedBuf& sb,
                                           unsigned long long* work, unsigned long long* gstats) {
     // FP32 (mixed) rays read the pencil records of their axis: consecutive
@@ -384,13 +402,13 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
     uint64_t cur = 0, end = 0;             // the wave's chunk, [cur, end)
     const uint32_t xcd = blockIdx.x % kXcds; // workgroups are dealt round-robin over the XCDs
     __shared__ uint32_t agg_key[kAggSlots];
-    __shared__ float agg_val[kAggSlots];
+    __shared__ V agg_val[kAggSlots];
     // the FP32 Dawson table in LDS: its lookups are per-lane gathers
     constexpr int kDaw = kDawsonIntervals * (kDawsonDeg32 + 1);
     __shared__ float daw[kAxis ? kDaw : 1];
     for (uint32_t i = threadIdx.x; i < kAggSlots; i += blockDim.x) {
         agg_key[i] = 0u;
-        agg_val[i] = 0.0f;
+        agg_val[i] = V(0);
     }
     if constexpr (kAxis)
         for (uint32_t i = threadIdx.x; i < uint32_t(kDaw); i += blockDim.x) daw[i] = c_dawson32[i];
@@ -513,26 +531,36 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
                 cnt.peel_cut++;
                 have = false;
             } else if (mm == left) {
-                deposit_lds(agg_key, agg_val, o.cube, ci, float(w * exp(-tau)));
+                deposit_lds<V>(agg_key, agg_val, o, ci, w * exp(-tau));
                 have = false;
             }
         }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < kAggSlots; i += blockDim.x)
-        if (agg_key[i]) unsafeAtomicAdd(o.cube + (agg_key[i] - 1u), agg_val[i]);
+        if (agg_key[i]) agg_flush<V>(o, agg_key[i] - 1u, agg_val[i]);
     flush_counters(cnt, gstats);
 }
 
 // FP32 pass: at most 80 VGPRs, six waves per SIMD to hide the gather latency.
+// V: float32 cube, or unsigned long long for the fixed-point cube.
+template <class V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
 void k_peel_pass_f32(GridDev g, OutDev o, SeedBuf sb, unsigned long long* work, unsigned long long* gstats) {
-    peel_pass<float>(g, o, sb, work, gstats);
+    peel_pass<float, V>(g, o, sb, work, gstats);
 }
 
+template <class V>
 __global__ __launch_bounds__(256) void k_peel_pass_f64(GridDev g, OutDev o, SeedBuf sb, unsigned long long* work,
                                                        unsigned long long* gstats) {
-    peel_pass<double>(g, o, sb, work, gstats);
+    peel_pass<double, V>(g, o, sb, work, gstats);
+}
+
+// The fixed-point cube as float32 (units of 1/scale).
+__global__ void k_fx_to_f32(const unsigned long long* __restrict__ src, float* __restrict__ dst, uint64_t n,
+                            double inv_scale) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        dst[i] = float(double(src[i]) * inv_scale);
 }
 
 // Marks every slot of a fresh seed buffer empty.
@@ -791,8 +819,10 @@ struct thor_ctx {
     double* d_spec = nullptr;
     int spec_nb = 0;
     float* d_cube = nullptr;
+    unsigned long long* d_cube_fx = nullptr;   // the cube in the fixed-point mode (instead of d_cube)
     uint64_t cube_elems = 0;
-    int cube_shape[4] = {0, 0, 0, 0};
+    int cube_shape[5] = {0, 0, 0, 0, 0};       // observers, ny, nx, bins, accumulation mode
+    double cube_fx_scale = 0.0;
     unsigned long long* d_stats = nullptr;   // kNumU64Counters counters, then cursor
     unsigned long long* d_xstats = nullptr;  // longest history, then the tail kernel's counters
     ModelDev* d_models = nullptr;
@@ -983,7 +1013,13 @@ thor_status check_opts(const thor_transport_opts* o) {
     if (o->step_events && o->path != THOR_PATH_PERSISTENT)
         return fail(THOR_E_INVAL, "bounded steps need the persistent path");
     if (o->block && (o->block % 64 || o->block > 256)) return fail(THOR_E_INVAL, "block must be 64..256, multiple of 64");
+    if (o->accum != THOR_ACCUM_F32_ATOMIC && o->accum != THOR_ACCUM_FIXED64) return fail(THOR_E_INVAL, "bad accum mode");
+    if (o->fixed_bits < 0 || o->fixed_bits > 60) return fail(THOR_E_INVAL, "fixed_bits must be 0..60");
     return THOR_OK;
+}
+
+double fixed_scale(const thor_transport_opts* o) {
+    return std::ldexp(1.0, o->fixed_bits > 0 ? o->fixed_bits : 40);
 }
 
 thor_status ensure_outputs(thor_ctx* ctx, const thor_transport_opts* o) {
@@ -996,18 +1032,30 @@ thor_status ensure_outputs(thor_ctx* ctx, const thor_transport_opts* o) {
         ctx->spec_nb = o->spec_nb;
         HIPCHK(ctx, hipMemsetAsync(ctx->d_spec, 0, uint64_t(o->spec_nb) * 8 * kSpecCopies, ctx->stream));
     }
-    const int shape[4] = {o->n_obs, o->cube_ny, o->cube_nx, o->cube_nb};
-    if (std::memcmp(shape, ctx->cube_shape, sizeof shape) != 0) {
+    const int fx = o->n_obs > 0 && o->accum == THOR_ACCUM_FIXED64;
+    const int shape[5] = {o->n_obs, o->cube_ny, o->cube_nx, o->cube_nb, fx};
+    if (std::memcmp(shape, ctx->cube_shape, sizeof shape) != 0 ||
+        (fx && ctx->cube_fx_scale != fixed_scale(o))) {
         dfree(ctx, ctx->d_cube, ctx->cube_elems * 4);
+        dfree(ctx, ctx->d_cube_fx, ctx->cube_elems * 8);
         ctx->d_cube = nullptr;
+        ctx->d_cube_fx = nullptr;
         ctx->cube_elems = 0;
+        ctx->cube_fx_scale = 0.0;
         std::memset(ctx->cube_shape, 0, sizeof ctx->cube_shape);
         if (o->n_obs > 0) {
             const uint64_t elems = uint64_t(o->n_obs) * o->cube_ny * o->cube_nx * o->cube_nb;
-            thor_status s = dalloc(ctx, (void**)&ctx->d_cube, elems * 4, "cube");
-            if (s) return s;
+            if (fx) {
+                thor_status s = dalloc(ctx, (void**)&ctx->d_cube_fx, elems * 8, "fixed-point cube");
+                if (s) return s;
+                HIPCHK(ctx, hipMemsetAsync(ctx->d_cube_fx, 0, elems * 8, ctx->stream));
+                ctx->cube_fx_scale = fixed_scale(o);
+            } else {
+                thor_status s = dalloc(ctx, (void**)&ctx->d_cube, elems * 4, "cube");
+                if (s) return s;
+                HIPCHK(ctx, hipMemsetAsync(ctx->d_cube, 0, elems * 4, ctx->stream));
+            }
             ctx->cube_elems = elems;
-            HIPCHK(ctx, hipMemsetAsync(ctx->d_cube, 0, elems * 4, ctx->stream));
         }
         std::memcpy(ctx->cube_shape, shape, sizeof shape);
     }
@@ -1043,6 +1091,8 @@ OutDev make_out(thor_ctx* ctx, const thor_transport_opts* o) {
     out.v_lo = o->cube_v_lo;
     out.v_w = o->n_obs ? (o->cube_v_hi - o->cube_v_lo) / o->cube_nb : 1.0;
     out.cube = ctx->d_cube;
+    out.cube_fx = ctx->d_cube_fx;
+    out.fx_scale = ctx->d_cube_fx ? ctx->cube_fx_scale : 0.0;
     out.tau_cut = o->tau_cut > 0.0 ? o->tau_cut : 40.0;
     out.max_events = o->max_events;
     return out;
@@ -1054,6 +1104,13 @@ uint32_t park_lanes(const thor_transport_opts* o) {
     if (o->park_lanes < 0) return 0u;
     if (o->park_lanes == 0) return kDefaultParkLanes;
     return o->park_lanes > 64 ? 64u : uint32_t(o->park_lanes);
+}
+
+// Share (in 64ths) of a turn's lanes that must have finished before the turn
+// ends early so that the wave refills them (64: only at the visit bound).
+uint32_t refill_64ths(const thor_transport_opts* o) {
+    if (o->refill_64ths <= 0) return 16u;
+    return o->refill_64ths > 64 ? 64u : uint32_t(o->refill_64ths);
 }
 
 // Live lanes at or below which a persistent wave takes wide turns.
@@ -1162,14 +1219,20 @@ thor_status ensure_seeds(thor_ctx* ctx, uint64_t slots, SeedBuf* sb) {
     return THOR_OK;
 }
 
-template <class R>
-void launch_peel_pass(thor_ctx* ctx, const OutDev& out, const SeedBuf& sb) {
+template <class R, class V>
+void launch_peel_pass_v(thor_ctx* ctx, const OutDev& out, const SeedBuf& sb) {
     if constexpr (sizeof(R) == 4)
-        hipLaunchKernelGGL(k_peel_pass_f32, dim3(ctx->num_cu * 6), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
+        hipLaunchKernelGGL(k_peel_pass_f32<V>, dim3(ctx->num_cu * 6), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
                            ctx->d_seedctl + 2, ctx->d_stats);
     else
-        hipLaunchKernelGGL(k_peel_pass_f64, dim3(ctx->num_cu * 4), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
+        hipLaunchKernelGGL(k_peel_pass_f64<V>, dim3(ctx->num_cu * 4), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
                            ctx->d_seedctl + 2, ctx->d_stats);
+}
+
+template <class R>
+void launch_peel_pass(thor_ctx* ctx, const OutDev& out, const SeedBuf& sb) {
+    if (out.cube_fx) launch_peel_pass_v<R, unsigned long long>(ctx, out, sb);
+    else launch_peel_pass_v<R, float>(ctx, out, sb);
 }
 
 thor_status ensure_pool(thor_ctx* ctx, uint64_t slots, int prec) {
@@ -1266,7 +1329,7 @@ void thor_destroy(thor_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    void* ptrs[] = {ctx->d_rec, ctx->d_cdf, ctx->d_spec, ctx->d_cube, ctx->d_stats,
+    void* ptrs[] = {ctx->d_rec, ctx->d_cdf, ctx->d_spec, ctx->d_cube, ctx->d_cube_fx, ctx->d_stats,
                     ctx->d_models, ctx->d_batches, ctx->d_rec_dv, ctx->d_rec_nres, ctx->d_rec_ndust,
                     ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done,
                     ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
@@ -1454,6 +1517,7 @@ thor_status thor_reset_outputs(thor_ctx* ctx) {
     if (ctx->d_spec)
         HIPCHK(ctx, hipMemsetAsync(ctx->d_spec, 0, uint64_t(ctx->spec_nb) * 8 * kSpecCopies, ctx->stream));
     if (ctx->d_cube) HIPCHK(ctx, hipMemsetAsync(ctx->d_cube, 0, ctx->cube_elems * 4, ctx->stream));
+    if (ctx->d_cube_fx) HIPCHK(ctx, hipMemsetAsync(ctx->d_cube_fx, 0, ctx->cube_elems * 8, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return THOR_OK;
 }
@@ -1550,7 +1614,7 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         // unbounded calls hand the last packets of drained waves to k_tail
         const bool hand_off = !bounded && wide_lanes(opt) > 0;
         *ctx->h_desc = StepDesc{q_end, int(nb), uint32_t(opt->step_events), turn, hand_off ? wide_lanes(opt) : 0u,
-                                park_lanes(opt)};
+                                park_lanes(opt), refill_64ths(opt), 0u};
         HIPCHK(ctx, hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(StepDesc), hipMemcpyHostToDevice, ctx->stream));
         if (bounded) {
             s = ensure_pool(ctx, uint64_t(gsize) * block, opt->precision);
@@ -1705,6 +1769,8 @@ thor_status thor_transport_noalloc(thor_ctx* ctx, const thor_transport_opts* opt
     if (opt->path != THOR_PATH_PERSISTENT) return fail(THOR_E_UNSUPPORTED, "no-allocation transport: PERSISTENT path only");
     if (opt->step_events) return fail(THOR_E_UNSUPPORTED, "no-allocation transport: no bounded steps");
     if (opt->records) return fail(THOR_E_UNSUPPORTED, "no-allocation transport: no per-packet records");
+    if (opt->accum != THOR_ACCUM_F32_ATOMIC)
+        return fail(THOR_E_UNSUPPORTED, "no-allocation transport: float32 cube accumulation only");
     if (uint64_t(opt->spec_nb) > kNaMaxBins)
         return fail(THOR_E_INVAL, "no-allocation transport: %d spectrum bins exceed the maximum of %d", opt->spec_nb,
                     int(kNaMaxBins));
@@ -1733,10 +1799,12 @@ thor_status thor_transport_noalloc(thor_ctx* ctx, const thor_transport_opts* opt
     }
     OutDev out = make_out(ctx, opt);
     out.cube = d_cube;
+    out.cube_fx = nullptr;
+    out.fx_scale = 0.0;
     const int block = opt->block > 0 ? opt->block : 256;
     const int gsize = launch_grid_size(ctx, opt, block);
     const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
-    const StepDesc desc{q, int(nb), 0u, turn, 0u, park_lanes(opt)};
+    const StepDesc desc{q, int(nb), 0u, turn, 0u, park_lanes(opt), refill_64ths(opt), 0u};
     if (out_stats) HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     const uint64_t spec_words = uint64_t(kSpecCopies) * uint64_t(opt->spec_nb);
     hipLaunchKernelGGL(k_na_setup, dim3(std::max<uint64_t>(1, std::min<uint64_t>(1024, (spec_words + 255) / 256))),
@@ -1779,6 +1847,7 @@ uint64_t thor_output_bytes(thor_ctx* ctx, thor_output which) {
     switch (which) {
     case THOR_OUT_SPECTRUM: return uint64_t(ctx->spec_nb) * 8;
     case THOR_OUT_CUBE: return ctx->cube_elems * 4;
+    case THOR_OUT_CUBE_FIXED: return ctx->d_cube_fx ? ctx->cube_elems * 8 : 0;
     case THOR_OUT_RECORDS: return ctx->rec_n * sizeof(thor_record);
     case THOR_OUT_STATS: return sizeof(thor_stats);
     }
@@ -1801,7 +1870,28 @@ thor_status thor_read_spectra(thor_ctx* ctx, thor_output which, uint32_t index, 
         break;
     case THOR_OUT_CUBE:
         if (!need) return fail(THOR_E_STATE, "no cube (no observers)");
-        HIPCHK(ctx, hipMemcpyAsync(dst, ctx->d_cube, need, kind, ctx->stream));
+        if (ctx->d_cube_fx) {
+            const double inv = 1.0 / ctx->cube_fx_scale;
+            if (dst_on_device) {
+                hipLaunchKernelGGL(k_fx_to_f32, dim3(ctx->num_cu * 4), dim3(256), 0, ctx->stream, ctx->d_cube_fx,
+                                   static_cast<float*>(dst), ctx->cube_elems, inv);
+                HIPCHK(ctx, hipGetLastError());
+            } else {
+                std::vector<unsigned long long> raw(ctx->cube_elems);
+                HIPCHK(ctx, hipMemcpyAsync(raw.data(), ctx->d_cube_fx, ctx->cube_elems * 8, hipMemcpyDeviceToHost,
+                                           ctx->stream));
+                HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+                float* d = static_cast<float*>(dst);
+                for (uint64_t i = 0; i < ctx->cube_elems; ++i) d[i] = float(double(raw[i]) * inv);
+                return THOR_OK;
+            }
+        } else {
+            HIPCHK(ctx, hipMemcpyAsync(dst, ctx->d_cube, need, kind, ctx->stream));
+        }
+        break;
+    case THOR_OUT_CUBE_FIXED:
+        if (!need) return fail(THOR_E_STATE, "no fixed-point cube (accum FIXED64 with observers)");
+        HIPCHK(ctx, hipMemcpyAsync(dst, ctx->d_cube_fx, need, kind, ctx->stream));
         break;
     case THOR_OUT_RECORDS: {
         if (!need) return fail(THOR_E_STATE, "no records (set opts.records)");
@@ -2049,7 +2139,8 @@ thor_status thor_step(thor_ctx* ctx, uint32_t max_events_per_packet, const thor_
     if (nb) std::memcpy(ctx->h_s_batches, ctx->s_batches.data(), nb * sizeof(BatchDev));
     const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
     // nb == 0: only parked packets are left; no lane can take a new index
-    *ctx->h_s_desc = StepDesc{ctx->s_q_total, int(nb), max_events_per_packet, turn, 0u, park_lanes(opt)};
+    *ctx->h_s_desc = StepDesc{ctx->s_q_total, int(nb), max_events_per_packet, turn, 0u, park_lanes(opt),
+                              refill_64ths(opt), 0u};
     if (ctx->s_dirty) {
         const int hi = ctx->s_next_slot;
         HIPCHK(ctx, hipMemcpyAsync(ctx->d_s_models, ctx->s_models.data(), sizeof(ModelDev) * hi,

@@ -28,7 +28,8 @@ PATH = {"plain": 0, "persistent": 1}
 PHASE = {"iso": 0, "dipole": 1, "core_wing": 2}
 CORE_SKIP = {"off": 0, "fixed": 1, "adaptive": 2}
 OBS = {"+x": 0, "+y": 1, "+z": 2, "-x": 3, "-y": 4, "-z": 5}
-OUT = {"spectrum": 0, "cube": 1, "records": 2, "stats": 3}
+OUT = {"spectrum": 0, "cube": 1, "records": 2, "stats": 3, "cube_fixed": 4}
+ACCUM = {"f32": 0, "fixed64": 1}
 SYMBOLS = ["thor_create", "thor_destroy", "thor_load_grid", "thor_emit", "thor_transport",
            "thor_reset_outputs", "thor_read_spectra", "thor_output_bytes", "thor_last_error",
            "thor_eval_voigt", "thor_sample_upar", "thor_submit", "thor_step", "thor_poll",
@@ -70,7 +71,8 @@ class thor_transport_opts(C.Structure):
                 ("waves_per_cu", C.c_int32), ("block", C.c_int32), ("visits_per_turn", C.c_int32),
                 ("use_graph", C.c_int32), ("inline_peel", C.c_int32), ("records", C.c_int32),
                 ("seed_slots", C.c_uint64),
-                ("wide_lanes", C.c_int32), ("park_lanes", C.c_int32)]
+                ("wide_lanes", C.c_int32), ("park_lanes", C.c_int32), ("refill_64ths", C.c_int32),
+                ("accum", C.c_int32), ("fixed_bits", C.c_int32)]
 
 
 STAT_U64 = ("emitted", "escaped", "absorbed", "capped", "handed_off", "n_res", "n_dust",
@@ -291,7 +293,8 @@ def make_source(src: dict) -> thor_source:
 
 def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_events=0,
               waves_per_cu=0, block=0, visits_per_turn=0, use_graph=False,
-              inline_peel=False, seed_slots=0, wide_lanes=0, park_lanes=0) -> thor_transport_opts:
+              inline_peel=False, seed_slots=0, wide_lanes=0, park_lanes=0,
+              refill_64ths=0, accum="f32", fixed_bits=0) -> thor_transport_opts:
     o = thor_transport_opts()
     o.precision = PREC[precision]
     o.path = PATH[path]
@@ -323,6 +326,9 @@ def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_ev
     o.seed_slots = int(seed_slots)
     o.wide_lanes = int(wide_lanes)
     o.park_lanes = int(park_lanes)
+    o.refill_64ths = int(refill_64ths)
+    o.accum = ACCUM[accum]
+    o.fixed_bits = int(fixed_bits)
     return o
 
 
@@ -399,6 +405,12 @@ class Transport:
     def cube(self, shape) -> np.ndarray:
         out = np.zeros(shape, dtype=np.float32)
         thor_read_spectra(self.ctx, "cube", out.ctypes.data, out.nbytes, False)
+        return out
+
+    def cube_fixed(self, shape) -> np.ndarray:
+        """The FIXED64 cube's integer sums (units of 2^-fixed_bits)."""
+        out = np.zeros(shape, dtype=np.uint64)
+        thor_read_spectra(self.ctx, "cube_fixed", out.ctypes.data, out.nbytes, False)
         return out
 
     def records(self) -> np.ndarray:

@@ -1,43 +1,49 @@
-"""The autotuner scores launch knobs by the device time without the tail
-kernel (host logic, no GPU: a stand-in transport)."""
-import types
-
+"""The autotuner (host logic, no GPU: a stand-in transport): coordinate-wise
+search over the knobs, scored by the median total device time of repeated
+runs over the same sample."""
 import pytest
 
 from paper_2507_11603_amd import autotune
 
 
 class FakeTransport:
-    """Persistent-kernel time depends on the knobs; the tail kernel's time is
-    large and unrelated to them (it follows the longest history)."""
+    """Total device time depends on the knobs, with one slow outlier run out
+    of every three (the median ignores it)."""
     device = 0
 
     def __init__(self):
         self.calls = 0
+        self.samples = set()
 
     def reset(self):
         pass
 
     def emit(self, src, n, first):
-        pass
+        self.samples.add((n, first))
 
-    def transport(self, opts, precision, path, waves_per_cu, block, visits_per_turn):
+    def transport(self, opts, precision, path, waves_per_cu, block, park_lanes, refill_64ths, wide_lanes,
+                  visits_per_turn):
         self.calls += 1
-        dense = 10.0 + abs(waves_per_cu - 8) + abs(visits_per_turn - 256) / 64.0
-        tail = 1000.0 * ((self.calls * 7919) % 13)        # noise far above the knob effect
-        return 0, {"kernel_ms": dense + tail, "tail_ms": tail}
+        ms = (10.0 + abs(waves_per_cu - 4) + abs(park_lanes - 24) / 8.0 + (block != 128)
+              + abs(refill_64ths - 32) / 16.0 + abs(wide_lanes - 16) / 4.0 + abs(visits_per_turn - 1024) / 512.0)
+        if self.calls % 3 == 0:
+            ms += 1000.0
+        return 0, {"kernel_ms": ms}
 
 
-def test_tune_ignores_the_tail(monkeypatch, tmp_path):
+def test_tune_coordinate_search_with_median(monkeypatch, tmp_path):
     torch = pytest.importorskip("torch")
     monkeypatch.setattr(torch.cuda, "get_device_name", lambda d=0: "fake")
-    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
     monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "cache.json"))
     T = FakeTransport()
     wl = {"src": {}, "opts": {}}
-    best, table = autotune.tune(T, wl, "fake-shell", sample=10, batches=1)
-    assert best == {"waves_per_cu": 8, "block": 256, "visits_per_turn": 256}
-    assert len(table) == len(autotune.DEFAULT_SPACE["waves_per_cu"]) * len(autotune.DEFAULT_SPACE["visits_per_turn"])
-    # the choice is cached per device, workload and precision
-    again, _ = autotune.tune(T, wl, "fake-shell", sample=10, batches=1)
-    assert again == best and T.calls == len(table)
+    best, table = autotune.tune(T, wl, "fake-web", sample=10, repeats=3)
+    assert best == {"waves_per_cu": 4, "block": 128, "park_lanes": 24, "refill_64ths": 32, "wide_lanes": 16,
+                    "visits_per_turn": 1024}
+    # every candidate ran on the same packets
+    assert T.samples == {(10, 7 * 10**12)}
+    assert len(table) <= sum(len(v) for v in autotune.SPACE.values())
+    # cached per device, workload, precision and sample
+    calls = T.calls
+    again, _ = autotune.tune(T, wl, "fake-web", sample=10, repeats=3)
+    assert again == best and T.calls == calls
