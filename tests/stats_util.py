@@ -38,3 +38,45 @@ def chi2_weighted(w1, s1, w2, s2, min_rel=0.2):
     chi2 = np.sum(num / den)
     dof = len(w1) - 1
     return chi2, dof, stats.chi2.sf(chi2, dof)
+
+
+def chi2_chunks(a, b, na=1, nb=1, min_frac=0.002):
+    """Two-sample test of weighted histograms from independent chunks.
+
+    a, b: arrays (chunks, bins), each row the per-packet histogram (sum over
+    the chunk / packets in it) of one chunk of na (resp. nb) packets over
+    disjoint photon-id ranges, so rows are independent.  Under the null
+    hypothesis both samples draw packets from one distribution, so per bin
+    one per-packet variance serves both: it is pooled from the chunks of both
+    sides, each squared deviation weighted by its chunk's packet count (a
+    chunk mean has variance sigma^2 / n).  The many-packet side then sets the
+    estimate, which keeps it from following the few large contributions of
+    a small, skewed chunk.  Per bin t = (m_a - m_b) / sqrt(sigma^2 (1/N_a +
+    1/N_b)) with K_a + K_b - 2 degrees of freedom is mapped to a standard
+    normal quantile through its t distribution, and the squares are summed
+    over bins whose pooled mean holds at least `min_frac` of the pooled
+    total.  Returns (chi2, dof, p)."""
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    ka, kb = len(a), len(b)
+    ma, mb = a.mean(axis=0), b.mean(axis=0)
+    s2 = (na * ((a - ma) ** 2).sum(axis=0) + nb * ((b - mb) ** 2).sum(axis=0)) / (ka + kb - 2)
+    var = s2 * (1.0 / (ka * na) + 1.0 / (kb * nb))
+    tot = ma.sum() + mb.sum()
+    sel = ((ma + mb) >= min_frac * tot) & (var > 0)
+    t = (ma - mb)[sel] / np.sqrt(var[sel])
+    z = stats.norm.isf(stats.t.sf(t, ka + kb - 2))
+    chi2 = float(np.sum(z ** 2))
+    dof = int(sel.sum())
+    return chi2, dof, stats.chi2.sf(chi2, dof)
+
+
+def rebin(a, factors):
+    """Sum blocks of `factors` along each axis (sizes must divide)."""
+    a = np.asarray(a)
+    shape = []
+    for n, f in zip(a.shape, factors):
+        assert n % f == 0, (n, f)
+        shape += [n // f, f]
+    a = a.reshape(shape)
+    return a.sum(axis=tuple(range(1, 2 * len(factors), 2)))

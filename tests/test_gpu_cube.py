@@ -1,0 +1,336 @@
+"""GPU parity of the peel-off cubes (Section 3.4.1) and of the larger boxes
+against the oracle, through the C ABI:
+
+* same seed, FP64: cube voxels, surface-brightness pixels and peel-spectrum
+  bins that hold a stated share of the flux agree with the oracle's;
+* independent seeds: the surface-brightness maps (cube summed over
+  frequency, rebinned) and the image-summed peel spectra of the GPU and of
+  the oracle pass a two-sample test built from independent chunks of packets
+  (the cube is a weighted histogram, so its variance comes from the chunks);
+* the 512^3 and 1024^3 web boxes (the 1024^3 one in the benchmark's launch
+  configuration) against the oracle on sampled packets;
+* the core/wing phase-function mix, and the tau0 = 1e5 sphere against a
+  stored 1e4-packet oracle spectrum.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from stats_util import chi2_chunks, chi2_two_sample, rebin
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _say(msg):
+    print("[gpu-test] " + msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2507_11603_amd import thor
+    thor.lib()
+    return thor
+
+
+def _threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return np.array([float(l) for l in f if not l.startswith("#")])
+
+
+def _share_check(a, b, share, tol, label):
+    """Entries of b (GPU) against a (oracle) where a holds >= share of a's
+    total: relative difference <= tol.  Returns the largest one."""
+    a = np.asarray(a, float)
+    b = np.asarray(b, float)
+    sel = a >= share * a.sum()
+    assert sel.sum() >= 1, label
+    rel = np.abs(b[sel] - a[sel]) / a[sel]
+    _say("%s: %d entries hold >= %g of the flux; max relative difference %.4f" % (label, sel.sum(), share, rel.max()))
+    assert rel.max() <= tol, (label, rel.max())
+    return rel.max()
+
+
+# ------------------------------------------------------------ same seed, per voxel
+def test_shell_cube_same_seed_per_voxel(gpu):
+    """Expanding shell on 64^3, 20000 packets, FP64 plain path, seed of the
+    oracle: more than 98 % of the histories are identical, so every voxel of
+    the (8 x 8 pixels x 16 bins) rebinned cube that holds >= 1 % of the flux,
+    every SB pixel (16^2) and every peel-spectrum bin (16) holding >= 1 %
+    agree within 5 %.  A transposed image, a mirrored axis or a shifted
+    frequency bin moves such entries by factors, not percent."""
+    wl = W.shell(n_grid=64, n_packets=20000, cube_nb=64)
+    ref = oracle.run_threaded(wl["geom"], wl["src"], wl["opts"], 0, 20000, _threads())
+    g = gpu.run(wl, precision="fp64", path="plain")
+    co, cg = ref["cube"][0], g["cube"][0].astype(np.float64)
+    _share_check(rebin(co, (8, 8, 4)).ravel(), rebin(cg, (8, 8, 4)).ravel(), 0.01, 0.05, "shell voxels")
+    _share_check(rebin(co.sum(axis=2), (4, 4)).ravel(), rebin(cg.sum(axis=2), (4, 4)).ravel(), 0.01, 0.05,
+                 "shell SB pixels")
+    _share_check(rebin(co.sum(axis=(0, 1)), (4,)), rebin(cg.sum(axis=(0, 1)), (4,)), 0.01, 0.05,
+                 "shell peel-spectrum bins")
+
+
+# ------------------------------------------------------------ independent seeds, chunks
+def _oracle_chunks(wl, n_chunks, per, seed, marg):
+    src = dict(wl["src"], seed=seed)
+    out = []
+    for i in range(n_chunks):
+        r = oracle.run_threaded(wl["geom"], src, wl["opts"], i * per, per, _threads())
+        out.append(marg(r["cube"]))
+    return out
+
+
+def _gpu_chunks(thor, wl, n_chunks, per, seed, marg, **kw):
+    T = thor.Transport(0)
+    out = []
+    try:
+        T.load(wl["geom"])
+        o = wl["opts"]
+        c = o["cube"]
+        shape = (len(o["observers"]), c["ny"], c["nx"], c["nb"])
+        src = dict(wl["src"], seed=seed)
+        for i in range(n_chunks):
+            T.reset()
+            T.emit(src, per, 10**11 + i * per)
+            T.transport(o, path="persistent", **kw)
+            out.append(marg(T.cube(shape).astype(np.float64)))
+    finally:
+        T.close()
+    return out
+
+
+def _marginals_shell(cube):
+    c = cube[0]
+    return rebin(c.sum(axis=2), (4, 4)).ravel(), rebin(c.sum(axis=(0, 1)), (4,))
+
+
+@pytest.fixture(scope="module")
+def shell128_oracle():
+    wl = W.shell(n_grid=128, n_packets=1)
+    return wl, _oracle_chunks(wl, 40, 5000, 2002, _marginals_shell)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_shell128_cube_chi2(gpu, shell128_oracle, precision):
+    """The 128^3 shell (128 x 128 x 256 cube): SB map rebinned to 32^2 and
+    the peel spectrum rebinned to 64 bins, 20 GPU chunks of 1e5 packets
+    against 40 oracle chunks of 5000 (independent seeds), over the bins that
+    hold >= 2e-4 of the flux (the central pixel, where every emission ray
+    lands, holds about half of it): p > 0.001 each; the total peeled flux per
+    packet within 4 sigma."""
+    wl, och = shell128_oracle
+    _say("shell128 cube chi2 %s" % precision)
+    gch = _gpu_chunks(gpu, wl, 20, 100000, 3003, _marginals_shell, precision=precision)
+    for k, name in enumerate(("SB map", "peel spectrum")):
+        a = np.array([c[k] for c in och]) / 5000.0
+        b = np.array([c[k] for c in gch]) / 100000.0
+        chi2, dof, p = chi2_chunks(b, a, 100000, 5000, min_frac=2e-4)
+        _say("%s: chi2 %.1f dof %d p %.3g" % (name, chi2, dof, p))
+        assert dof >= 10 and p > 0.001
+    ta = np.array([c[0].sum() for c in och]) / 5000.0
+    tb = np.array([c[0].sum() for c in gch]) / 100000.0
+    err = np.sqrt(ta.var(ddof=1) / len(ta) + tb.var(ddof=1) / len(tb))
+    _say("peel flux per packet gpu %.5g oracle %.5g +- %.2g" % (tb.mean(), ta.mean(), err))
+    assert abs(tb.mean() - ta.mean()) < 4 * err
+
+
+def _marginals_web(cube):
+    sb = rebin(cube.sum(axis=3), (1, 4, 4)).ravel()
+    sp = rebin(cube.sum(axis=(1, 2)), (1, 5)).ravel()
+    return sb, sp
+
+
+@pytest.fixture(scope="module")
+def web64_oracle():
+    wl = W.web(n_grid=64, fields=W.web_fields(64), cube_npix=32, cube_nb=50)
+    return wl, _oracle_chunks(wl, 30, 500, wl["src"]["seed"], lambda c: (c, *_marginals_web(c)))
+
+
+def test_web64_cube_same_seed_per_pixel(gpu, web64_oracle):
+    """Three observers on the 64^3 web box, packets 0..2999, FP64 plain path,
+    the oracle's seed: about 80 % of the (long) histories are identical, so
+    per observer the SB pixels (8^2) and the peel-spectrum bins (10) holding
+    >= 2 % of that observer's flux agree within 25 %."""
+    wl, och = web64_oracle
+    ref = sum(c[0] for c in och[:6])
+    g = gpu.run(wl, n=3000, precision="fp64", path="plain")["cube"].astype(np.float64)
+    for o in range(3):
+        _share_check(rebin(ref[o].sum(axis=2), (4, 4)).ravel(), rebin(g[o].sum(axis=2), (4, 4)).ravel(),
+                     0.02, 0.25, "web observer %d SB pixels" % o)
+        _share_check(rebin(ref[o].sum(axis=(0, 1)), (5,)), rebin(g[o].sum(axis=(0, 1)), (5,)), 0.02, 0.25,
+                     "web observer %d peel-spectrum bins" % o)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_web64_cube_chi2(gpu, web64_oracle, precision):
+    """Web 64^3, three observers: SB maps (3 x 8^2) and peel spectra (3 x 10)
+    from 20 GPU chunks of 5000 packets against 30 oracle chunks of 500
+    (independent seeds): p > 0.001 each."""
+    wl, och = web64_oracle
+    _say("web64 cube chi2 %s" % precision)
+    gch = _gpu_chunks(gpu, wl, 20, 5000, 1003, _marginals_web, precision=precision)
+    for k, name in enumerate(("SB maps", "peel spectra")):
+        a = np.array([c[k + 1] for c in och]) / 500.0
+        b = np.array([c[k] for c in gch]) / 5000.0
+        chi2, dof, p = chi2_chunks(b, a, 5000, 500)
+        _say("%s: chi2 %.1f dof %d p %.3g" % (name, chi2, dof, p))
+        assert dof >= 10 and p > 0.001
+
+
+# ------------------------------------------------------------ larger boxes, sampled packets
+def test_web512_against_oracle(gpu):
+    """The 512^3 web box (numpy fields, 64^2 x 200 cubes): packets 0..9999
+    through the FP64 persistent path follow the oracle's histories (mostly)
+    with the mean scattering count within 1 %; 1e6 mixed-precision packets
+    of another seed pass a spectrum chi^2 against the oracle's 1e4 and their
+    peeled flux per observer lies within 4 sigma of the oracle's."""
+    wl = W.web(n_grid=512, fields=W.web_fields(512), cube_npix=64, cube_nb=200)
+    n = 10000
+    parts = [oracle.run_threaded(wl["geom"], wl["src"], wl["opts"], i * 1000, 1000, _threads(), records=True)
+             for i in range(10)]
+    rec = np.concatenate([p["records"] for p in parts])
+    spec = sum(p["spectrum"] for p in parts)
+    flux = np.array([p["cube"].sum(axis=(1, 2, 3)) / 1000 for p in parts])
+    _say("web512 oracle: %d packets, mean n_res %.1f" % (n, rec["n_res"].mean()))
+    g = gpu.run(wl, n=n, precision="fp64", path="persistent", records=True)
+    same = np.mean(g["records"]["n_res"] == rec["n_res"])
+    ratio = g["records"]["n_res"].mean() / rec["n_res"].mean()
+    _say("fp64 same seed: identical histories %.3f, mean n_res ratio %.4f" % (same, ratio))
+    assert same > 0.6 and abs(ratio - 1) < 0.01
+    m = gpu.run(dict(wl, src=dict(wl["src"], seed=1004)), n=1_000_000, precision="mixed", path="persistent")
+    chi2, dof, p = chi2_two_sample(m["spectrum"], spec)
+    tot = m["cube"].astype(np.float64).sum(axis=(1, 2, 3)) / 1e6
+    mean, err = flux.mean(axis=0), flux.std(axis=0, ddof=1) / np.sqrt(len(flux))
+    _say("mixed 1e6: spectrum chi2 %.1f dof %d p %.3f; peel flux per packet %s vs oracle %s +- %s"
+         % (chi2, dof, p, tot, mean, err))
+    assert p > 0.01
+    assert np.all(np.abs(tot - mean) < 4 * err)
+
+
+def test_web1024_bench_configuration_against_oracle(gpu):
+    """The 1024^3 web box with the benchmark's fields (torch, on the GPU) and
+    launch configuration (mixed precision, persistent path, 8 waves per CU):
+    cell records above 2^32 bytes, 17 GB pencil arrays.  The FP64 persistent
+    path on packets 0..599 follows the oracle's histories (on a host copy of
+    the same fields); 2e6 mixed packets of another seed match the oracle's
+    scattering-count distribution and escape spectrum (chi^2 p > 0.01)."""
+    import torch
+    f = W.web_fields_torch(1024)
+    host = tuple(t.cpu().numpy() for t in f)
+    wl = W.web(n_grid=1024, fields=f)
+    T = gpu.Transport(0)
+    try:
+        T.load(wl["geom"])
+        del f
+        wl["geom"] = dict(wl["geom"], n_HI_field=None, T_field=None, vx=None, vy=None, vz=None)
+        torch.cuda.empty_cache()
+        n = 600
+        T.emit(wl["src"], n, 0)
+        T.transport(wl["opts"], precision="fp64", path="persistent", records=True)
+        g64 = T.records()
+        T.reset()
+        src2 = dict(wl["src"], seed=1005)
+        T.emit(src2, 2_000_000, 0)
+        _, st = T.transport(wl["opts"], precision="mixed", path="persistent", records=True, waves_per_cu=8)
+        gm = T.records()
+        spec_m = T.spectrum()
+    finally:
+        T.close()
+    geom = dict(wl["geom"], n_HI_field=host[0], T_field=host[1], vx=host[2], vy=host[3], vz=host[4])
+    ref = oracle.run_threaded(geom, wl["src"], wl["opts"], 0, n, _threads(), records=True)
+    r = ref["records"]
+    same = np.mean(g64["n_res"] == r["n_res"])
+    _say("web1024 fp64 same seed: identical histories %.3f; mean n_res gpu %.1f oracle %.1f"
+         % (same, g64["n_res"].mean(), r["n_res"].mean()))
+    assert same > 0.5
+    edges = np.array([0, 1, 3, 10, 30, 100, 300, 1000, 3000, 1e9])
+    chi2, dof, p = chi2_two_sample(np.histogram(gm["n_res"], edges)[0], np.histogram(r["n_res"], edges)[0])
+    _say("mixed 2e6 vs oracle: n_res distribution chi2 %.1f dof %d p %.3f" % (chi2, dof, p))
+    assert p > 0.01
+    chi2, dof, p = chi2_two_sample(spec_m, ref["spectrum"])
+    _say("escape spectrum chi2 %.1f dof %d p %.3f" % (chi2, dof, p))
+    assert p > 0.01
+    assert st["capped"] == 0 and st["emitted"] == 2_000_000
+
+
+# ------------------------------------------------------------ phase functions and the sphere
+def test_core_wing_same_seed_and_chi2(gpu):
+    """Core/wing phase mix (p = 11/24 + 3/24 mu^2 in the atom-frame core,
+    dipole in the wing), sphere tau0 = 1e4: the FP64 plain path follows the
+    oracle's histories for the same seed; mixed and FP64 persistent spectra
+    of another seed pass chi^2 against the stored 2e4-packet oracle spectrum."""
+    wl = W.sphere(tau0=1e4, phase="core_wing", n_packets=1000)
+    ref = oracle.run_threaded(wl["geom"], wl["src"], wl["opts"], 0, 1000, _threads(), records=True)
+    g = gpu.run(wl, n=1000, precision="fp64", path="plain", records=True)
+    same = np.mean(g["records"]["n_res"] == ref["records"]["n_res"])
+    _say("core/wing same seed: identical histories %.3f" % same)
+    assert same > 0.9
+    assert abs(g["records"]["n_res"].mean() / ref["records"]["n_res"].mean() - 1) < 0.01
+    gold = _golden("oracle_corewing_tau1e4_n2e4.txt")
+    for precision in ("mixed", "fp64"):
+        m = gpu.run(dict(wl, src=dict(wl["src"], seed=1001)), n=100000, precision=precision, path="persistent")
+        chi2, dof, p = chi2_two_sample(m["spectrum"], gold)
+        _say("core/wing %s 1e5 vs oracle 2e4: chi2 %.1f dof %d p %.3f" % (precision, chi2, dof, p))
+        assert p > 0.01
+
+
+@pytest.mark.parametrize("precision,path", [("fp64", "plain"), ("fp64", "persistent"), ("mixed", "persistent")])
+def test_sphere_spectrum_vs_stored_oracle(gpu, precision, path):
+    """Static sphere tau0 = 1e5 (the Neufeld-test configuration): 5e4 GPU
+    packets (seed 1001) against the stored oracle spectrum of 1e4 packets
+    (seed 1): chi^2 p > 0.01."""
+    wl = W.sphere()
+    gold = _golden("oracle_sphere_tau1e5_n1e4.txt")
+    g = gpu.run(dict(wl, src=dict(wl["src"], seed=1001)), n=50000, precision=precision, path=path)
+    assert g["stats"]["escaped"] == 50000
+    chi2, dof, p = chi2_two_sample(g["spectrum"], gold)
+    _say("sphere %s %s 5e4 vs oracle 1e4: chi2 %.1f dof %d p %.3f" % (precision, path, chi2, dof, p))
+    assert p > 0.01
+
+
+# ------------------------------------------------------------ fixed-point cubes
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fixed64_cube_is_bit_reproducible(gpu, precision):
+    """accum FIXED64: the integer cube is the same bit for bit whatever the
+    launch shape, parking, refill threshold or seed-buffer size (the order of
+    the additions changes, integer sums do not); records are identical; its
+    float32 view matches the float-atomic cube to float rounding."""
+    import torch
+    wl = W.shell(n_grid=64, n_packets=20000, cube_nb=64)
+    o = wl["opts"]
+    shape = (1, o["cube"]["ny"], o["cube"]["nx"], o["cube"]["nb"])
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    variants = [dict(), dict(waves_per_cu=2, park_lanes=-1, refill_64ths=64, seed_slots=256 * n_cu),
+                dict(waves_per_cu=4, block=128, park_lanes=16, refill_64ths=8, wide_lanes=-1)]
+    res = []
+    for kw in variants:
+        T = gpu.Transport(0)
+        try:
+            T.load(wl["geom"])
+            T.emit(wl["src"], 20000, 0)
+            _, st = T.transport(o, precision=precision, path="persistent", records=True, accum="fixed64", **kw)
+            res.append((T.cube_fixed(shape), T.cube(shape), T.records(), st))
+        finally:
+            T.close()
+    for fx, view, rec, st in res[1:]:
+        assert np.array_equal(fx, res[0][0])
+        assert np.array_equal(view, res[0][1])
+        for k in ("n_res", "n_dust", "fate", "dv"):
+            assert np.array_equal(rec[k], res[0][2][k]), k
+    assert res[1][3]["passes"] > 1                      # the small seed buffer refilled
+    f = gpu.run(wl, precision=precision, path="persistent")["cube"].astype(np.float64)
+    v = res[0][1].astype(np.float64)
+    _say("fixed64 %s: %d nonzero voxels; total %.6g vs float %.6g" % (precision, np.count_nonzero(res[0][0]),
+                                                                     v.sum(), f.sum()))
+    assert abs(v.sum() / f.sum() - 1) < 1e-5
+    assert np.allclose(v, f, rtol=2e-3, atol=1e-6 * f.max())
