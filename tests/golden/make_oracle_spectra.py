@@ -12,6 +12,10 @@ escape spectrum's bin counts, one per line):
                                     (200 bins of x over [-40, 40))
   oracle_corewing_tau1e4_n2e4.txt   the same sphere at tau0 = 1e4 with the
                                     core/wing phase-function mix, 20000 packets
+  oracle_slab_dust_tau1e6.txt       dusty slab (T = 20 K, tau0 = 1e6, albedo 0,
+                                    Section 4's dust test): per line
+                                    b = (a tau0)^(1/3) tau_d, tau_d, packets,
+                                    escaped (photon ids 0.., seed 1)
 """
 from __future__ import annotations
 
@@ -47,6 +51,29 @@ def write(name, threads):
     print("%s: %.0f s, mean scatterings %.1f" % (name, time.time() - t0, st["n_res"] / n), flush=True)
 
 
+SLAB_B = (0.5, 1.0)
+SLAB_N = 300
+
+
+def write_slab(threads):
+    name = "oracle_slab_dust_tau1e6.txt"
+    T, tau0 = 20.0, 1e6
+    _, a, _ = oracle.line_params(T)
+    t0 = time.time()
+    rows = []
+    for b in SLAB_B:
+        tau_d = b / (a * tau0) ** (1.0 / 3.0)
+        wl = W.dusty_slab(tau0=tau0, T=T, tau_d=tau_d, n_packets=SLAB_N)
+        r = oracle.run_threaded(wl["geom"], wl["src"], wl["opts"], 0, SLAB_N, threads)
+        rows.append((b, tau_d, SLAB_N, r["stats"]["escaped"]))
+    with open(os.path.join(HERE, name), "w") as f:
+        f.write("# oracle escape from a dusty slab: T=20 K tau0=1e6 albedo 0 isotropic, line-centre source, "
+                "seed 1; columns b tau_d packets escaped; written by tests/golden/make_oracle_spectra.py\n")
+        for row in rows:
+            f.write("%.3f %.10g %d %d\n" % row)
+    print("%s: %.0f s" % (name, time.time() - t0), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
@@ -56,6 +83,8 @@ def main():
     for name in CASES:
         if not a.only or a.only == name:
             write(name, a.threads)
+    if not a.only or a.only == "oracle_slab_dust_tau1e6.txt":
+        write_slab(a.threads)
 
 
 if __name__ == "__main__":

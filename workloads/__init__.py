@@ -227,6 +227,33 @@ def web(n_grid: int = 1024, n_packets: int = 100_000_000, seed: int = 3, box_pmp
 
 
 # --------------------------------------------------------------------------
+# validation media of Section 4: dusty slab, sphere with a linear outflow
+# --------------------------------------------------------------------------
+def dusty_slab(tau0: float = 1e6, T: float = 20.0, tau_d: float = 0.1, n_packets: int = 1000, seed: int = 1,
+               albedo: float = 0.0):
+    """Infinite slab |z| < Z: line-centre optical depth tau0 and dust optical
+    depth tau_d from the mid-plane to a surface, line-centre source at the
+    centre, isotropic phase; albedo 0 makes the dust a pure absorber."""
+    geom = dict(kind="slab", r_inner=0.0, r_outer=KPC, tau0=tau0, T=T, tau_d=tau_d, albedo=albedo, g_hg=0.73)
+    src = dict(kind="point", pos=(0.0, 0.0, 0.0), spectrum="delta", dv0=0.0, seed=seed)
+    opts = dict(phase="iso", spectrum=dict(nb=200, lo=-40.0, hi=40.0, T_ref=T))
+    return dict(name="dusty_slab", geom=geom, src=src, opts=opts, n_packets=n_packets)
+
+
+def outflow_sphere(N_HI: float = 2e18, T: float = 2e4, v_max_kms: float = 200.0, n_packets: int = 1000,
+                   seed: int = 1, nb: int = 200, v_range_kms: float = 1000.0):
+    """Homogeneous sphere of column N_HI (centre to edge) at T with the
+    linear velocity profile v = v_max r / R (outflow for v_max > 0), line-centre
+    source at the centre, dipole phase; spectrum of dv over +-v_range."""
+    R = KPC
+    geom = dict(kind="sphere", r_inner=0.0, r_outer=R, n_HI=N_HI / R, T=T, v_profile="linear",
+                v_max=v_max_kms * KMS, step_f=0.01)
+    src = dict(kind="point", pos=(0.0, 0.0, 0.0), spectrum="delta", dv0=0.0, seed=seed)
+    opts = dict(phase="dipole", spectrum=dict(nb=nb, lo=-v_range_kms * KMS, hi=v_range_kms * KMS))
+    return dict(name="outflow_sphere", geom=geom, src=src, opts=opts, n_packets=n_packets)
+
+
+# --------------------------------------------------------------------------
 # serving: stream of meshless shell-model requests
 # --------------------------------------------------------------------------
 def shell_request(N_HI: float, v_exp_kms: float, tau_d: float, n_packets: int,
