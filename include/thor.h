@@ -94,6 +94,16 @@ typedef struct {
     double sigma_d;
     double tau_d;
     double albedo, g_hg;
+    /* GRID Hubble flow (Section 2.2: the cross-section in the frame of the gas,
+     * which moves with the expansion; Section 3.4 sub-cell stepping): gas
+     * velocity v_cell + hubble (p - hubble_ref), hubble in s^-1 (0 = none).
+     * Every cell crossing of a flight or peel ray is cut into n equal steps, n
+     * the smallest with hubble t / n <= hubble_step v_th (0 = 0.1), each taking
+     * the profile at its midpoint.  stop_dv > 0 (cm/s): a packet whose
+     * gas-frame offset falls more than stop_dv below line centre (checked at
+     * cell faces) escapes (beyond that shift the IGM is taken as transparent),
+     * counted in thor_stats.redshifted and not as a hand-off. */
+    double hubble, hubble_ref[3], hubble_step, stop_dv;
 } thor_geometry;
 
 /* ---------------------------------------------------------------- sources */
@@ -228,6 +238,7 @@ typedef struct {
     uint64_t tail_events;           /* interactions run by the tail kernels (in n_res, n_dust) */
     uint64_t tail_main_visits;      /* main-march cell visits of the tail kernels */
     uint64_t tail_peel_visits;      /* peel cell visits of the tail kernels */
+    uint64_t redshifted;            /* escaped through the redshift stop (part of escaped) */
 } thor_stats;
 
 /* Per-packet record (index = packet id - first id of its batch, batches in
@@ -236,7 +247,7 @@ typedef struct {
     double dv;          /* final lab-frame frequency offset, cm/s */
     uint32_t n_res;
     uint32_t n_dust;
-    int32_t fate;       /* 1 escaped, 2 absorbed, 3 capped */
+    int32_t fate;       /* 1 escaped, 2 absorbed, 3 capped, 4 escaped by the redshift stop */
     uint32_t pad;
 } thor_record;
 

@@ -51,7 +51,9 @@ class Geometry(C.Structure):
                 ("f_vy", C.c_void_p), ("f_vz", C.c_void_p),
                 ("boundary_handoff", C.c_int32),
                 ("sigma_d", C.c_double), ("tau_d", C.c_double),
-                ("albedo", C.c_double), ("g_hg", C.c_double)]
+                ("albedo", C.c_double), ("g_hg", C.c_double),
+                ("hubble", C.c_double), ("hubble_ref", C.c_double * 3), ("hubble_step", C.c_double),
+                ("stop_dv", C.c_double)]
 
 
 class Source(C.Structure):
@@ -75,7 +77,7 @@ class Stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "emitted", "escaped", "absorbed", "capped", "handed_off", "n_res", "n_dust",
         "main_visits", "peel_visits", "peel_contrib", "peel_dropped", "peel_cut",
-        "upar_trials")] + [("w_escaped", C.c_double), ("w_absorbed", C.c_double)]
+        "upar_trials")] + [("w_escaped", C.c_double), ("w_absorbed", C.c_double), ("redshifted", C.c_uint64)]
 
 
 RECORD_DTYPE = np.dtype([("dv", "<f8"), ("n_res", "<u4"), ("n_dust", "<u4"),
@@ -226,6 +228,10 @@ def make_structs(geom: dict, src: dict, opts: dict):
     g.tau_d = geom.get("tau_d", 0.0)
     g.albedo = geom.get("albedo", 0.0)
     g.g_hg = geom.get("g_hg", 0.73)
+    g.hubble = geom.get("hubble", 0.0)
+    g.hubble_ref[:] = list(map(float, geom.get("hubble_ref", (0.0, 0.0, 0.0))))
+    g.hubble_step = geom.get("hubble_step", 0.0)
+    g.stop_dv = geom.get("stop_dv", 0.0)
 
     s = Source()
     s.kind = SOURCE[src.get("kind", "point")]

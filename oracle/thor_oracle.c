@@ -425,6 +425,26 @@ static void grid_fields(const model_t *m, const int c[3], cellf_t *f)
     }
 }
 
+/* Hubble flow of a grid medium.  The cross-section is taken in the frame of
+ * the gas (Section 2.2), whose velocity includes the cosmological expansion:
+ * v(p) = v_cell + H (p - p_ref), so along a flight the gas-frame frequency
+ * drifts by -H per unit length.  Sub-cell stepping (Section 3.4): a cell
+ * crossing of length t is cut into n equal steps, n the smallest integer
+ * with H t / n <= hubble_step v_th, each with the profile at its midpoint. */
+static int hubble_on(const model_t *m) { return m->g->kind == OR_GRID && m->g->hubble > 0.0; }
+
+static void hubble_velocity(const model_t *m, const double p[3], double vh[3])
+{
+    for (int i = 0; i < 3; ++i) vh[i] = m->g->hubble * (p[i] - m->g->hubble_ref[i]);
+}
+
+static int hubble_steps(const model_t *m, double t, double vth)
+{
+    double f = m->g->hubble_step > 0.0 ? m->g->hubble_step : 0.1;
+    double r = m->g->hubble * t / (f * vth);
+    return r > 1.0 ? (int)ceil(r) : 1;
+}
+
 static void meshless_velocity(const model_t *m, const double q[3], double v[3])
 {
     const or_geometry *g = m->g;
@@ -648,10 +668,23 @@ static void peel(const model_t *m, const loc_t *L0, int o, double weight, double
         double t = query(m, &L, k, &f, &nr, &cm);
         st->peel_visits++;
         if (f.k0 > 0.0 || f.kd > 0.0) {
-            double x = (dv_peel - dot3(f.v, k)) / f.vth;
-            double kt = f.k0 * or_voigt(f.a, x) + f.kd;
-            if (isinf(t)) { cut = 1; break; }
-            tau += kt * t;
+            if (hubble_on(m)) {
+                /* gas-frame offset at the segment start, then the sub-steps */
+                double vh[3];
+                hubble_velocity(m, L.p, vh);
+                double u0 = dv_peel - dot3(f.v, k) - dot3(vh, k);
+                int n = hubble_steps(m, t, f.vth);
+                double ds = t / n;
+                for (int j = 0; j < n; ++j) {
+                    double x = (u0 - m->g->hubble * ((j + 0.5) * ds)) / f.vth;
+                    tau += (f.k0 * or_voigt(f.a, x) + f.kd) * ds;
+                }
+            } else {
+                double x = (dv_peel - dot3(f.v, k)) / f.vth;
+                double kt = f.k0 * or_voigt(f.a, x) + f.kd;
+                if (isinf(t)) { cut = 1; break; }
+                tau += kt * t;
+            }
         } else if (isinf(t)) {
             break;
         }
@@ -693,6 +726,7 @@ typedef struct {
     loc_t L;
     double k[3];
     cellf_t f0;        /* fields at the emission point */
+    double v0[3];      /* gas velocity there (with the Hubble flow of a grid) */
     double dv;         /* lab-frame frequency offset */
     double dv_loc;     /* gas-frame offset (THERMAL spectra; 0 otherwise) */
 } emitted_t;
@@ -746,6 +780,12 @@ static void emit_packet(const model_t *m, const or_source *src, uint64_t id, emi
             (void)query(m, &L, k, &f0, &nr, &cm);
         }
     }
+    double v0[3] = { f0.v[0], f0.v[1], f0.v[2] };
+    if (hubble_on(m) && L.region != REG_OUT) {
+        double vh[3];
+        hubble_velocity(m, L.p, vh);
+        for (int i = 0; i < 3; ++i) v0[i] += vh[i];
+    }
     double dv, dv_loc = 0.0;
     double z = 0.0;
     if (src->spectrum != OR_SPEC_DELTA) {
@@ -755,7 +795,7 @@ static void emit_packet(const model_t *m, const or_source *src, uint64_t id, emi
     if (src->spectrum == OR_SPEC_THERMAL) {
         /* gas-frame Doppler profile of the emitting cell, then the lab frame */
         dv_loc = src->dv0 + f0.vth * z / sqrt(2.0);
-        dv = dv_loc + dot3(f0.v, k);
+        dv = dv_loc + dot3(v0, k);
     } else if (src->spectrum == OR_SPEC_GAUSS) {
         dv = src->dv0 + src->sigma_v * z;
     } else {
@@ -763,6 +803,7 @@ static void emit_packet(const model_t *m, const or_source *src, uint64_t id, emi
     }
     e->L = L;
     e->f0 = f0;
+    for (int i = 0; i < 3; ++i) e->v0[i] = v0[i];
     e->dv = dv;
     e->dv_loc = dv_loc;
 }
@@ -839,7 +880,7 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
     for (int o = 0; o < op->n_obs; ++o) {
         double ko[3];
         obs_dir(op->obs_axis[o], ko);
-        double dvp = (src->spectrum == OR_SPEC_THERMAL) ? dv_loc + dot3(f0.v, ko) : dv;
+        double dvp = (src->spectrum == OR_SPEC_THERMAL) ? dv_loc + dot3(em.v0, ko) : dv;
         if (L.region != REG_OUT)
             peel(m, &L, o, 1.0 / (4.0 * PI), dvp, cube, st);
     }
@@ -862,15 +903,46 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
         double t = query(m, &L, k, &f, &nr, &cm);
         st->main_visits++;
         double kh = 0.0, kt = 0.0;
-        if (f.k0 > 0.0 || f.kd > 0.0) {
-            double x = (dv - dot3(f.v, k)) / f.vth;
-            kh = f.k0 * or_voigt(f.a, x);
-            kt = kh + f.kd;
+        double s = -1.0;          /* interaction site along the segment, if any */
+        if (hubble_on(m)) {
+            double vh[3];
+            hubble_velocity(m, L.p, vh);
+            double u0 = dv - dot3(f.v, k) - dot3(vh, k);   /* gas-frame offset at the start */
+            if (g->stop_dv > 0.0 && u0 < -g->stop_dv) {
+                fate = OR_FATE_REDSHIFTED;
+                break;
+            }
+            if (f.k0 > 0.0 || f.kd > 0.0) {
+                int n = hubble_steps(m, t, f.vth);
+                double ds = t / n;
+                for (int j = 0; j < n; ++j) {
+                    double x = (u0 - g->hubble * ((j + 0.5) * ds)) / f.vth;
+                    double ktj = f.k0 * or_voigt(f.a, x) + f.kd;
+                    if (tau_acc + ktj * ds >= tau_target) {
+                        s = j * ds + (tau_target - tau_acc) / ktj;
+                        kt = ktj;
+                        break;
+                    }
+                    tau_acc += ktj * ds;
+                }
+            }
+        } else {
+            if (f.k0 > 0.0 || f.kd > 0.0) {
+                double x = (dv - dot3(f.v, k)) / f.vth;
+                kh = f.k0 * or_voigt(f.a, x);
+                kt = kh + f.kd;
+            }
+            if (kt > 0.0 && tau_acc + kt * t >= tau_target)
+                s = (tau_target - tau_acc) / kt;
         }
-        if (kt > 0.0 && tau_acc + kt * t >= tau_target) {
+        if (s >= 0.0) {
             /* Interaction site: linear step where tau_current = tau_target. */
-            double s = (tau_target - tau_acc) / kt;
             for (int i = 0; i < 3; ++i) L.p[i] += s * k[i];
+            if (hubble_on(m)) {   /* the gas moves with the Hubble flow at the site */
+                double vh[3];
+                hubble_velocity(m, L.p, vh);
+                for (int i = 0; i < 3; ++i) f.v[i] += vh[i];
+            }
             ++event;
             if ((uint64_t)event > max_events) {
                 fate = OR_FATE_CAPPED;
@@ -930,14 +1002,17 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
             fate = OR_FATE_ESCAPED;
             break;
         }
-        tau_acc += kt * t;
+        if (!hubble_on(m))
+            tau_acc += kt * t;
         if (advance(m, &L, k, t, nr, cm))
             fate = OR_FATE_ESCAPED;
     }
-    if (fate == OR_FATE_ESCAPED) {
+    if (fate == OR_FATE_ESCAPED || fate == OR_FATE_REDSHIFTED) {
         st->escaped++;
         st->w_escaped += w;
-        if (g->kind == OR_GRID && g->boundary_handoff)
+        if (fate == OR_FATE_REDSHIFTED)
+            st->redshifted++;
+        else if (g->kind == OR_GRID && g->boundary_handoff)
             st->handed_off++;
         double sv = dv;
         if (op->spec_T_ref > 0.0) {

@@ -29,7 +29,10 @@ enum { OR_SPEC_DELTA = 0, OR_SPEC_GAUSS = 1, OR_SPEC_THERMAL = 2 };
 enum { OR_PHASE_ISO = 0, OR_PHASE_DIPOLE = 1, OR_PHASE_CORE_WING = 2 };
 enum { OR_CS_OFF = 0, OR_CS_FIXED = 1, OR_CS_ADAPTIVE = 2 };
 /* packet fates */
-enum { OR_FATE_NONE = 0, OR_FATE_ESCAPED = 1, OR_FATE_ABSORBED = 2, OR_FATE_CAPPED = 3 };
+/* REDSHIFTED: a grid packet in a Hubble flow whose gas-frame offset fell more
+ * than stop_dv below line centre; it escapes (the IGM is taken as transparent
+ * beyond that shift). */
+enum { OR_FATE_NONE = 0, OR_FATE_ESCAPED = 1, OR_FATE_ABSORBED = 2, OR_FATE_CAPPED = 3, OR_FATE_REDSHIFTED = 4 };
 
 typedef struct {
     int32_t kind;
@@ -47,6 +50,11 @@ typedef struct {
     double sigma_d;            /* dust cross-section per HI atom, cm^2 */
     double tau_d;              /* > 0 (meshless): dust optical depth of the column */
     double albedo, g_hg;
+    /* grid Hubble flow: gas velocity v_cell + hubble (p - hubble_ref) (hubble in
+     * s^-1, 0 = none); every cell crossing is split into equal sub-steps whose
+     * Hubble shift is at most hubble_step v_th (0 = 0.1), each evaluated at its
+     * midpoint; stop_dv > 0: redshift stop (cm/s) */
+    double hubble, hubble_ref[3], hubble_step, stop_dv;
 } or_geometry;
 
 typedef struct {
@@ -77,6 +85,7 @@ typedef struct {
     uint64_t emitted, escaped, absorbed, capped, handed_off;
     uint64_t n_res, n_dust, main_visits, peel_visits, peel_contrib, peel_dropped, peel_cut, upar_trials;
     double w_escaped, w_absorbed;
+    uint64_t redshifted;        /* escaped through the redshift stop (part of escaped) */
 } or_stats;
 
 typedef struct {

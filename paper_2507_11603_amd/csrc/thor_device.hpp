@@ -577,7 +577,7 @@ enum : int { kGeomShell = 0, kGeomSlab = 1, kGeomGrid = 2 };
 enum : int { kVelNone = 0, kVelConstRadial = 1, kVelLinear = 2 };
 enum : int { kSrcPoint = 0, kSrcCellN2 = 1 };
 enum : int { kSpecDelta = 0, kSpecGauss = 1, kSpecThermal = 2 };
-enum : int { kFateNone = 0, kFateEscaped = 1, kFateAbsorbed = 2, kFateCapped = 3 };
+enum : int { kFateNone = 0, kFateEscaped = 1, kFateAbsorbed = 2, kFateCapped = 3, kFateRedshifted = 4 };
 enum : int { kRegCavity = 0, kRegGas = 1, kRegOut = 2 };
 
 // Grid cell record (32 B, one aligned half cache line): gas velocity and
@@ -605,6 +605,10 @@ struct GridDev {
     double cdf_total;
     uint64_t ncell;
     double sigma_d;
+    double hubble;        // Hubble flow: gas velocity v_cell + hubble (p - href) (0 = none)
+    double href[3];
+    double hstep;         // largest Hubble shift of a sub-step, in units of v_th
+    double stop_dv;       // redshift stop (cm/s; 0 = none)
 };
 
 // One batch model: medium constants (meshless), dust, source, output slice.
@@ -668,10 +672,10 @@ struct OutDev {
 // so escaped / absorbed weights equal the counts.
 struct Counters {
     uint32_t emitted, escaped, absorbed, capped, handed_off, n_res, n_dust;
-    uint32_t peel_contrib, peel_dropped, peel_cut;
+    uint32_t peel_contrib, peel_dropped, peel_cut, redshifted;
     uint64_t main_visits, peel_visits, upar_trials;
     uint32_t max_events;    // longest finished history (interactions)
 };
-constexpr int kNumU64Counters = 13;
+constexpr int kNumU64Counters = 14;
 
 }  // namespace thor

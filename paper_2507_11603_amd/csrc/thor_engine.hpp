@@ -98,6 +98,45 @@ __device__ __forceinline__ void grid_fields(const GridDev& g, const int c[3], Fi
     fields_from_rec<R>(g, g.rec[cell_index(g, c)], f);
 }
 
+// Hubble flow of a grid medium: the cross-section is taken in the frame of
+// the gas (Section 2.2), which moves with the expansion, v(p) = v_cell +
+// H (p - href); along a flight the gas-frame frequency drifts by -H per unit
+// length.  Sub-cell stepping (Section 3.4): a cell crossing of length t is
+// cut into n equal steps, n the smallest with H t / n <= hstep v_th, each
+// with the profile at its midpoint.
+__device__ __forceinline__ void hubble_velocity(const GridDev& g, const double p[3], double vh[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) vh[i] = g.hubble * (p[i] - g.href[i]);
+}
+__device__ __forceinline__ int hubble_steps(const GridDev& g, double t, double vth) {
+    const double r = g.hubble * t / (g.hstep * vth);
+    return r > 1.0 ? int(ceil(r)) : 1;
+}
+// The cell fields with the gas velocity of point p (cell velocity + Hubble flow).
+template <class R>
+__device__ __forceinline__ Fields<R> with_hubble(const GridDev& g, const Fields<R>& f, const double p[3]) {
+    Fields<R> o = f;
+    double vh[3];
+    hubble_velocity(g, p, vh);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) o.v[i] = R(double(f.v[i]) + vh[i]);
+    return o;
+}
+// Optical depth of a peel-ray segment of length t along an axis in a Hubble
+// flow: u0 is the gas-frame offset (cm/s) at the segment's start.
+template <class R>
+__device__ __forceinline__ double hubble_segment_tau(const GridDev& g, double u0, double t, R vth, R a, double k0,
+                                                     double kd) {
+    const int n = hubble_steps(g, t, double(vth));
+    const double ds = t / n;
+    double tau = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const R x = R((u0 - g.hubble * ((j + 0.5) * ds)) / double(vth));
+        tau += (k0 * double(voigt<R>(a, x)) + kd) * ds;
+    }
+    return tau;
+}
+
 // choose among three values without indexing a private array
 template <class T> __device__ __forceinline__ T sel3(int a, T x, T y, T z) {
     return a == 0 ? x : (a == 1 ? y : z);
@@ -382,6 +421,8 @@ __device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const
         double pa = sel3(a, L0.p[0], L0.p[1], L0.p[2]);
         int64_t idx = int64_t(cell_index(g, L0.c));
         // first segment: from the event to the face, fields of the event's cell
+        // (their velocity includes the Hubble flow at the event)
+        const double href = sel3(a, g.href[0], g.href[1], g.href[2]);
         {
             const double face = pos ? lo + double(ca + 1) * dx : lo + double(ca) * dx;
             double t = pos ? face - pa : pa - face;
@@ -389,8 +430,13 @@ __device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const
             cnt.peel_visits++;
             if (f0.k0 > 0.0 || f0.kd > 0.0) {
                 const R va = sel3(a, f0.v[0], f0.v[1], f0.v[2]);
-                const R x = fdiv(dv_peel - (pos ? va : -va), f0.vth);
-                tau += (f0.k0 * double(voigt<R>(f0.a, x)) + f0.kd) * t;
+                if (g.hubble > 0.0) {
+                    tau += hubble_segment_tau<R>(g, double(dv_peel) - (pos ? double(va) : -double(va)), t, f0.vth,
+                                                 f0.a, f0.k0, f0.kd);
+                } else {
+                    const R x = fdiv(dv_peel - (pos ? va : -va), f0.vth);
+                    tau += (f0.k0 * double(voigt<R>(f0.a, x)) + f0.kd) * t;
+                }
                 cut = tau > o.tau_cut;
             }
             pa = face;
@@ -416,8 +462,15 @@ __device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const
                 fields_from_rec<R>(g, r[j], f);
                 if (f.k0 > 0.0 || f.kd > 0.0) {
                     const R va = sel3(a, f.v[0], f.v[1], f.v[2]);
-                    const R x = fdiv(dv_peel - (pos ? va : -va), f.vth);
-                    tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
+                    if (g.hubble > 0.0) {
+                        // gas-frame offset at the entry face, with the Hubble flow there
+                        const double hv = g.hubble * (pa - href);
+                        tau += hubble_segment_tau<R>(g, double(dv_peel) - (pos ? double(va) : -double(va)) -
+                                                            (pos ? hv : -hv), t, f.vth, f.a, f.k0, f.kd);
+                    } else {
+                        const R x = fdiv(dv_peel - (pos ? va : -va), f.vth);
+                        tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
+                    }
                     cut = tau > o.tau_cut;
                 }
                 pa = face;
@@ -478,14 +531,20 @@ __device__ __forceinline__ bool peel_first(const GridDev& g, const OutDev& o, co
     double tau = 0.0;
     if (f0.k0 > 0.0 || f0.kd > 0.0) {
         const R va = sel3(a, f0.v[0], f0.v[1], f0.v[2]);
-        const R x = fdiv(dv_peel - (pos ? va : -va), f0.vth);
-        // a sure cut needs no profile: the same test on a lower bound of H
-        // (each step of the expression is monotone in H)
-        if ((f0.k0 * double(voigt_floor(float(f0.a), float(x))) + f0.kd) * t > o.tau_cut) {
-            cnt.peel_cut++;
-            return false;
+        if (g.hubble > 0.0) {
+            // f0's velocity includes the Hubble flow at the event
+            tau = hubble_segment_tau<R>(g, double(dv_peel) - (pos ? double(va) : -double(va)), t, f0.vth, f0.a,
+                                        f0.k0, f0.kd);
+        } else {
+            const R x = fdiv(dv_peel - (pos ? va : -va), f0.vth);
+            // a sure cut needs no profile: the same test on a lower bound of H
+            // (each step of the expression is monotone in H)
+            if ((f0.k0 * double(voigt_floor(float(f0.a), float(x))) + f0.kd) * t > o.tau_cut) {
+                cnt.peel_cut++;
+                return false;
+            }
+            tau = (f0.k0 * double(voigt<R>(f0.a, x)) + f0.kd) * t;
         }
-        tau = (f0.k0 * double(voigt<R>(f0.a, x)) + f0.kd) * t;
         if (tau > o.tau_cut) { cnt.peel_cut++; return false; }
     }
     const int nxt = ca + (pos ? 1 : -1);
@@ -662,6 +721,7 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
         f0.vth = R(1); f0.a = R(0); f0.k0 = 0.0; f0.kd = 0.0; f0.v[0] = f0.v[1] = f0.v[2] = R(0);
     } else if constexpr (GRID) {
         grid_fields<R>(g, L.c, f0);
+        if (g.hubble > 0.0) f0 = with_hubble<R>(g, f0, L.p);
     } else {
         int nr, cm;
         (void)meshless_query<R>(m, L.p, L.region, pk.k, f0, &nr, &cm);
@@ -931,19 +991,46 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
             const Fields<R>& f = GRID ? cc.f : fl;
             cnt.main_visits++;
             double kt = 0.0;
-            if (f.k0 > 0.0 || f.kd > 0.0) {
-                const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
-                if constexpr (sizeof(R) == 4) kt = f.k0 * double(voigt32(f.a, x, dtab)) + f.kd;
-                else kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+            double s = -1.0;            // interaction site along the segment, if any
+            double tau_seg = pk.tau_a;  // tau at the end of the segment (Hubble sub-steps)
+            if (GRID && g.hubble > 0.0) {
+                double vh[3];
+                hubble_velocity(g, L.p, vh);
+                const double kd3[3] = {double(pk.k[0]), double(pk.k[1]), double(pk.k[2])};
+                // gas-frame offset at the segment start
+                const double u0 = double(pk.dv) - double(dot3<R>(f.v, pk.k)) - dot3d(vh, kd3);
+                if (g.stop_dv > 0.0 && u0 < -g.stop_dv) { fate = kFateRedshifted; break; }
+                if (f.k0 > 0.0 || f.kd > 0.0) {
+                    const int n = hubble_steps(g, t, double(f.vth));
+                    const double ds = t / n;
+                    for (int j = 0; j < n; ++j) {
+                        const R x = R((u0 - g.hubble * ((j + 0.5) * ds)) / double(f.vth));
+                        double ktj;
+                        if constexpr (sizeof(R) == 4) ktj = f.k0 * double(voigt32(f.a, x, dtab)) + f.kd;
+                        else ktj = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+                        if (tau_seg + ktj * ds >= pk.tau_t) {
+                            s = j * ds + div_tau<R>(pk.tau_t - tau_seg, ktj);
+                            kt = ktj;
+                            break;
+                        }
+                        tau_seg += ktj * ds;
+                    }
+                }
+            } else {
+                if (f.k0 > 0.0 || f.kd > 0.0) {
+                    const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
+                    if constexpr (sizeof(R) == 4) kt = f.k0 * double(voigt32(f.a, x, dtab)) + f.kd;
+                    else kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+                }
+                if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) s = div_tau<R>(pk.tau_t - pk.tau_a, kt);
             }
-            if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) {
+            if (s >= 0.0) {
                 if constexpr (Q && !PRE) {
                     // no room for this event's rays: end the turn before it (state
                     // unchanged); the wave claims a new run of slots
                     if (sl->left < uint32_t(o.n_obs)) break;
                 }
                 // interaction site where tau_current = tau_target along the step
-                const double s = div_tau<R>(pk.tau_t - pk.tau_a, kt);
 #pragma unroll
                 for (int i = 0; i < 3; ++i) L.p[i] += s * double(pk.k[i]);
                 pk.event++;
@@ -954,7 +1041,8 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
                 if constexpr (!GRID) f_site = fl;
             } else {
                 if (isinf(t)) { fate = kFateEscaped; break; }
-                pk.tau_a += kt * t;
+                if (GRID && g.hubble > 0.0) pk.tau_a = tau_seg;
+                else pk.tau_a += kt * t;
                 bool out;
                 if constexpr (GRID) {
                     out = grid_advance<R>(g, L.p, L.c, pk.k, t, cm);
@@ -977,7 +1065,11 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
         }
         if (go) {
             parked = false;
-            fate = interact<R, GRID, Q, PRE>(g, m, o, pk, L, GRID ? cc.f : f_site, kt_site, key, cnt, sb, sl,
+            // the gas at the site moves with the cell and, on a grid in a Hubble
+            // flow, with the expansion at the site
+            Fields<R> fs = GRID ? cc.f : f_site;
+            if (GRID && g.hubble > 0.0) fs = with_hubble<R>(g, fs, L.p);
+            fate = interact<R, GRID, Q, PRE>(g, m, o, pk, L, fs, kt_site, key, cnt, sb, sl,
                                              PRE ? pre + (pk.event - pre_event) : nullptr, js);
             if (fate != kFateNone) break;
             set_inverse();
@@ -1000,9 +1092,10 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 template <class R, bool GRID>
 __device__ void finish(const GridDev& g, const ModelDev& m, const OutDev& o, const Pkt<R>& pk, int fate,
                        Counters& cnt) {
-    if (fate == kFateEscaped) {
+    if (fate == kFateEscaped || fate == kFateRedshifted) {
         cnt.escaped++;
-        if (GRID && g.handoff) cnt.handed_off++;
+        if (fate == kFateRedshifted) cnt.redshifted++;
+        else if (GRID && g.handoff) cnt.handed_off++;
         const int b = bin_of(double(pk.dv) * m.spec_scale, m.spec_lo, m.spec_w, m.spec_nb);
         if (b >= 0) unsafeAtomicAdd(m.spec + uint64_t(blockIdx.x % uint32_t(m.spec_rep)) * uint32_t(m.spec_nb) + b, 1.0);
     } else if (fate == kFateAbsorbed) {
@@ -1034,7 +1127,7 @@ __device__ __forceinline__ void flush_counters(const Counters& c, unsigned long 
                                                unsigned long long* gmax = nullptr) {
     const uint64_t vals[kNumU64Counters] = {c.emitted, c.escaped, c.absorbed, c.capped, c.handed_off,
                                             c.n_res, c.n_dust, c.main_visits, c.peel_visits,
-                                            c.peel_contrib, c.peel_dropped, c.peel_cut, c.upar_trials};
+                                            c.peel_contrib, c.peel_dropped, c.peel_cut, c.upar_trials, c.redshifted};
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int i = 0; i < kNumU64Counters; ++i) {

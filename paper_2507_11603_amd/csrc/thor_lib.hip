@@ -484,6 +484,7 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
             const int left = pos ? dim - ca : ca + 1;       // >= 1
             const int mm = left < kLook ? left : kLook;
             bool cut = false;
+            const double href = sel3(a, g.href[0], g.href[1], g.href[2]);
             if constexpr (kAxis) {
                 AxisRec rc[kLook];
 #pragma unroll
@@ -495,9 +496,25 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
                     // every cell after the event's is crossed whole: segment = cell width
                     cnt.peel_visits++;
                     if (rc[j].k0 > 0.0f || rc[j].kd > 0.0f) {
-                        const float x = (dvp - (pos ? rc[j].v : -rc[j].v)) * rc[j].ivth;
                         const float av = float(kDampTimesVth) * rc[j].ivth;
-                        tau += (double(rc[j].k0) * double(voigt32(av, x, daw)) + double(rc[j].kd)) * dx;
+                        if (g.hubble > 0.0) {
+                            // entry face of cell j, the Hubble flow there, sub-steps
+                            const int cj = ca + (pos ? j : -j);
+                            const double entry = pos ? lo + double(cj) * dx : lo + double(cj + 1) * dx;
+                            const double hv = g.hubble * (entry - href);
+                            const double u0 = double(dvp) - (pos ? double(rc[j].v) : -double(rc[j].v)) -
+                                              (pos ? hv : -hv);
+                            const double vth = 1.0 / double(rc[j].ivth);
+                            const int n = hubble_steps(g, dx, vth);
+                            const double ds = dx / n;
+                            for (int q = 0; q < n; ++q) {
+                                const float x = float(u0 - g.hubble * ((q + 0.5) * ds)) * rc[j].ivth;
+                                tau += (double(rc[j].k0) * double(voigt32(av, x, daw)) + double(rc[j].kd)) * ds;
+                            }
+                        } else {
+                            const float x = (dvp - (pos ? rc[j].v : -rc[j].v)) * rc[j].ivth;
+                            tau += (double(rc[j].k0) * double(voigt32(av, x, daw)) + double(rc[j].kd)) * dx;
+                        }
                         cut = tau > o.tau_cut;
                     }
                 }
@@ -518,8 +535,14 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
                     fields_from_rec<R>(g, rc[j], f);
                     if (f.k0 > 0.0 || f.kd > 0.0) {
                         const R va = sel3(a, f.v[0], f.v[1], f.v[2]);
-                        const R x = fdiv(dvp - (pos ? va : -va), f.vth);
-                        tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
+                        if (g.hubble > 0.0) {
+                            const double hv = g.hubble * (pa - href);
+                            tau += hubble_segment_tau<R>(g, double(dvp) - (pos ? double(va) : -double(va)) -
+                                                                (pos ? hv : -hv), t, f.vth, f.a, f.k0, f.kd);
+                        } else {
+                            const R x = fdiv(dvp - (pos ? va : -va), f.vth);
+                            tau += (f.k0 * double(voigt<R>(f.a, x)) + f.kd) * t;
+                        }
                         cut = tau > o.tau_cut;
                     }
                     pa = face;
@@ -1258,7 +1281,8 @@ void collect_stats(thor_ctx* ctx, const unsigned long long* h, float ms, thor_st
     std::memset(st, 0, sizeof *st);
     uint64_t* dst[kNumU64Counters] = {&st->emitted, &st->escaped, &st->absorbed, &st->capped, &st->handed_off,
                                       &st->n_res, &st->n_dust, &st->main_visits, &st->peel_visits,
-                                      &st->peel_contrib, &st->peel_dropped, &st->peel_cut, &st->upar_trials};
+                                      &st->peel_contrib, &st->peel_dropped, &st->peel_cut, &st->upar_trials,
+                                      &st->redshifted};
     for (int i = 0; i < kNumU64Counters; ++i) *dst[i] = h[i];
     st->w_escaped = double(st->escaped);     // packet weights are 1
     st->w_absorbed = double(st->absorbed);
@@ -1406,6 +1430,8 @@ thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
         return THOR_OK;
     }
     if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return fail(THOR_E_INVAL, "bad grid dimensions");
+    if (!(g->hubble >= 0.0) || !(g->hubble_step >= 0.0) || !(g->stop_dv >= 0.0))
+        return fail(THOR_E_INVAL, "hubble, hubble_step and stop_dv must be >= 0");
     for (int i = 0; i < 3; ++i)
         if (!(g->hi[i] > g->lo[i])) return fail(THOR_E_INVAL, "grid needs lo < hi");
     if (!g->n_HI_field || !g->T_field || !g->vx || !g->vy || !g->vz) return fail(THOR_E_INVAL, "null grid field");
@@ -1466,6 +1492,10 @@ thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
     gd.rec = ctx->d_rec;
     gd.ncell = cells;
     gd.sigma_d = g->sigma_d;
+    gd.hubble = g->hubble;
+    for (int i = 0; i < 3; ++i) gd.href[i] = g->hubble_ref[i];
+    gd.hstep = g->hubble_step > 0.0 ? g->hubble_step : 0.1;
+    gd.stop_dv = g->stop_dv;
     ctx->has_geom = true;
     return THOR_OK;
 }

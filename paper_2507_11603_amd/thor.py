@@ -51,7 +51,9 @@ class thor_geometry(C.Structure):
                 ("n_HI_field", C.c_void_p), ("T_field", C.c_void_p), ("vx", C.c_void_p),
                 ("vy", C.c_void_p), ("vz", C.c_void_p), ("mem", C.c_int32),
                 ("boundary_handoff", C.c_int32), ("sigma_d", C.c_double), ("tau_d", C.c_double),
-                ("albedo", C.c_double), ("g_hg", C.c_double)]
+                ("albedo", C.c_double), ("g_hg", C.c_double),
+                ("hubble", C.c_double), ("hubble_ref", C.c_double * 3), ("hubble_step", C.c_double),
+                ("stop_dv", C.c_double)]
 
 
 class thor_source(C.Structure):
@@ -84,7 +86,7 @@ class thor_stats(C.Structure):
         ("w_escaped", C.c_double), ("w_absorbed", C.c_double), ("kernel_ms", C.c_double),
         ("transport_ms", C.c_double), ("peel_ms", C.c_double), ("passes", C.c_uint64),
         ("tail_ms", C.c_double), ("max_events", C.c_uint64), ("tail_events", C.c_uint64),
-        ("tail_main_visits", C.c_uint64), ("tail_peel_visits", C.c_uint64)]
+        ("tail_main_visits", C.c_uint64), ("tail_peel_visits", C.c_uint64), ("redshifted", C.c_uint64)]
 
     def to_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -276,6 +278,10 @@ def make_geometry(geom: dict, device_fields=None) -> thor_geometry:
     g.tau_d = geom.get("tau_d", 0.0)
     g.albedo = geom.get("albedo", 0.0)
     g.g_hg = geom.get("g_hg", 0.73)
+    g.hubble = geom.get("hubble", 0.0)
+    g.hubble_ref[:] = list(map(float, geom.get("hubble_ref", (0.0, 0.0, 0.0))))
+    g.hubble_step = geom.get("hubble_step", 0.0)
+    g.stop_dv = geom.get("stop_dv", 0.0)
     return g
 
 
@@ -471,6 +477,16 @@ def _field(t, name):
     return t
 
 
+def _check_out(t, name, shape, device):
+    """A caller-supplied output: contiguous float64 of the expected shape on
+    the fields' device (a wrong one would be written out of bounds)."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_contiguous()
+            and tuple(t.shape) == tuple(shape) and t.device == device):
+        raise ValueError("%s must be a contiguous float64 tensor of shape %s on %s" % (name, tuple(shape), device))
+    return t
+
+
 def ray_project(q, w=None, axis: int = 2, ds: float = 1.0, out=None):
     """Projection along `axis` (Section 3.5.1): returns device float64 images
     (Q, W) = (int q w ds, int w ds), each [j][i].  `out` may pass both images."""
@@ -482,11 +498,11 @@ def ray_project(q, w=None, axis: int = 2, ds: float = 1.0, out=None):
             raise ValueError("w must match q")
     nz, ny, nx = q.shape
     g = thor_ray_grid(nx, ny, nz, int(axis), float(ds))
+    shape = ray_image_shape(q.shape, axis) if axis in (0, 1, 2) else (1, 1)
     if out is None:
-        shape = ray_image_shape(q.shape, axis) if axis in (0, 1, 2) else (1, 1)
         out = (torch.empty(shape, dtype=torch.float64, device=q.device),
                torch.empty(shape, dtype=torch.float64, device=q.device))
-    Q, W = out
+    Q, W = (_check_out(t, n, shape, q.device) for t, n in zip(out, ("out[0]", "out[1]")))
     with torch.cuda.device(q.device):
         thor_ray_project(g, q.data_ptr(), None if w is None else w.data_ptr(), Q.data_ptr(),
                          W.data_ptr(), torch.cuda.current_stream(q.device).cuda_stream)
@@ -507,8 +523,9 @@ def ray_forest(n_HI, T, v_los, axis: int, ds: float, hubble: float, n_sub: int,
     g = thor_ray_grid(nx, ny, nz, int(axis), float(ds))
     o = thor_forest_opts(i0, ni, j0, nj, float(hubble), int(n_sub), int(nb), float(u_lo),
                          float(u_hi), PREC[precision])
-    tau = out if out is not None else torch.empty((max(nj, 0), max(ni, 0), int(nb)),
-                                                  dtype=torch.float64, device=n_HI.device)
+    shape = (max(nj, 0), max(ni, 0), int(nb))
+    tau = (_check_out(out, "out", shape, n_HI.device) if out is not None
+           else torch.empty(shape, dtype=torch.float64, device=n_HI.device))
     with torch.cuda.device(n_HI.device):
         thor_ray_forest(g, o, n_HI.data_ptr(), T.data_ptr(), v_los.data_ptr(), tau.data_ptr(),
                         torch.cuda.current_stream(n_HI.device).cuda_stream)

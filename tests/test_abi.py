@@ -112,3 +112,16 @@ def test_ray_calls_validate_on_the_host(lib):
     assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == -1
     o.precision, o.nj = 0, 0
     assert lib.thor_ray_forest(C.byref(g), C.byref(o), None, None, None, None, None) == 0
+
+
+def test_ray_outputs_are_checked_before_any_call():
+    """A caller-supplied output of the wrong shape, dtype or layout is refused
+    before the library writes into it (the check needs no GPU)."""
+    import torch
+    dev = torch.device("cpu")
+    ok = torch.zeros((4, 3), dtype=torch.float64)
+    assert thor._check_out(ok, "out", (4, 3), dev) is ok
+    for bad in (torch.zeros((3, 4), dtype=torch.float64), torch.zeros((4, 3), dtype=torch.float32),
+                torch.zeros((3, 4), dtype=torch.float64).t(), "not a tensor"):
+        with pytest.raises(ValueError):
+            thor._check_out(bad, "out", (4, 3), dev)

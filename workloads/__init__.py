@@ -210,13 +210,18 @@ def forest(n_grid: int = 512, box_pmpc: float = 17.22, hubble_kms_mpc: float = 2
 
 
 def web(n_grid: int = 1024, n_packets: int = 100_000_000, seed: int = 3, box_pmpc: float = 17.22,
-        fields=None, cube_npix: int = 512, cube_nb: int = 200, x_crit: float = 3.0):
+        fields=None, cube_npix: int = 512, cube_nb: int = 200, x_crit: float = 3.0, hubble_kms_mpc: float = 0.0,
+        stop_kms: float = 1233.0):
     L = box_pmpc * 1e3 * KPC
     if fields is None:
         fields = web_fields(n_grid)
     dens, temp, vx, vy, vz = fields
     geom = dict(kind="grid", lo=(0.0, 0.0, 0.0), hi=(L, L, L), n_HI_field=dens, T_field=temp,
                 vx=vx, vy=vy, vz=vz, boundary_handoff=1, sigma_d=0.0, albedo=0.0, g_hg=0.73)
+    if hubble_kms_mpc > 0.0:
+        # expansion about the box centre; packets stop once 5 A (1233 km/s) to the red
+        geom.update(hubble=hubble_kms_mpc * KMS / (1e3 * KPC), hubble_ref=(L / 2, L / 2, L / 2), hubble_step=0.1,
+                    stop_dv=stop_kms * KMS)
     src = dict(kind="cell_n2", spectrum="thermal", dv0=0.0, seed=seed)
     vlo, vhi = -1500.0 * KMS, 1500.0 * KMS
     opts = dict(phase="dipole", core_skip="fixed", x_crit=x_crit, observers=["+x", "+y", "+z"],
@@ -251,6 +256,30 @@ def outflow_sphere(N_HI: float = 2e18, T: float = 2e4, v_max_kms: float = 200.0,
     src = dict(kind="point", pos=(0.0, 0.0, 0.0), spectrum="delta", dv0=0.0, seed=seed)
     opts = dict(phase="dipole", spectrum=dict(nb=nb, lo=-v_range_kms * KMS, hi=v_range_kms * KMS))
     return dict(name="outflow_sphere", geom=geom, src=src, opts=opts, n_packets=n_packets)
+
+
+def hubble_box(n_grid: int = 32, box_mpc: float = 30.0, n_HI: float = 4.8e-11, T: float = 1e4,
+               hubble_kms_mpc: float = 100.0, stop_kms: float = 1233.0, n_packets: int = 1000, seed: int = 1,
+               observers=("+z",), cube_npix: int = 1, cube_v_kms: float = 0.01):
+    """Uniform static gas (no peculiar velocity) on a grid in a Hubble flow
+    centred on the box, a line-centre source at the centre, the redshift stop
+    at stop_kms; the +z peel cube is one pixel over the box face and one
+    narrow bin around dv = 0 (it then holds the emission rays)."""
+    L = box_mpc * 1e3 * KPC
+    shape = (n_grid,) * 3
+    dens = np.full(shape, n_HI, np.float32)
+    temp = np.full(shape, T, np.float32)
+    zero = np.zeros(shape, np.float32)
+    H = hubble_kms_mpc * KMS / (1e3 * KPC)
+    geom = dict(kind="grid", lo=(0.0, 0.0, 0.0), hi=(L, L, L), n_HI_field=dens, T_field=temp, vx=zero, vy=zero,
+                vz=zero, boundary_handoff=1, sigma_d=0.0, albedo=0.0, g_hg=0.73, hubble=H,
+                hubble_ref=(L / 2, L / 2, L / 2), hubble_step=0.1, stop_dv=stop_kms * KMS)
+    src = dict(kind="point", pos=(L / 2, L / 2, L / 2), spectrum="delta", dv0=0.0, seed=seed)
+    opts = dict(phase="dipole", observers=list(observers),
+                cube=dict(nx=cube_npix, ny=cube_npix, nb=1, img_lo=(0.0, 0.0), img_hi=(L, L),
+                          v_lo=-0.5 * cube_v_kms * KMS, v_hi=0.5 * cube_v_kms * KMS),
+                spectrum=dict(nb=200, lo=-2000.0 * KMS, hi=2000.0 * KMS))
+    return dict(name="hubble_box", geom=geom, src=src, opts=opts, n_packets=n_packets)
 
 
 # --------------------------------------------------------------------------
