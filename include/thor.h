@@ -212,6 +212,13 @@ typedef struct {
                                    uint64: bit-reproducible in any order and launch
                                    shape; a voxel holds at most 2^(64 - fixed_bits)) */
     int32_t fixed_bits;         /* FIXED64: 0 = 40 (units of 9.1e-13, voxel sums up to 1.7e7) */
+    int32_t presort;            /* PERSISTENT, unbounded, grid: 1 = take the queued packets in the
+                                   Morton order of their n_HI^2-weighted emission cells (drawn
+                                   first by a pre-pass, radix-sorted on the device, inside the
+                                   call's time) so that the packets in flight and their peel
+                                   rays are near each other; results do not change (each
+                                   packet's history depends only on its id); 0 = the library
+                                   default, negative = queue order */
 } thor_transport_opts;
 
 typedef enum { THOR_ACCUM_F32_ATOMIC = 0, THOR_ACCUM_FIXED64 = 1 } thor_accum;
@@ -239,6 +246,7 @@ typedef struct {
     uint64_t tail_main_visits;      /* main-march cell visits of the tail kernels */
     uint64_t tail_peel_visits;      /* peel cell visits of the tail kernels */
     uint64_t redshifted;            /* escaped through the redshift stop (part of escaped) */
+    double presort_ms;              /* of kernel_ms, the spatial presort of the queue */
 } thor_stats;
 
 /* Per-packet record (index = packet id - first id of its batch, batches in

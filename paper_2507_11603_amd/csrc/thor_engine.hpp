@@ -666,6 +666,18 @@ __device__ __forceinline__ void event_draws(const Key& key, uint32_t event, int 
 }
 
 // ----------------------------------------------------------------- emission
+// Cell of an n_HI^2-weighted emission (Section 3.4 "Emission"): the first
+// index whose inclusive prefix of n_HI^2 exceeds u times the total.
+__device__ __forceinline__ uint64_t emission_cell(const GridDev& g, double u) {
+    const double target = u * g.cdf_total;
+    uint64_t lo = 0, hi = g.ncell - 1;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (g.cdf[mid] > target) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 // Generator + photon initialisation (Section 3.4 "Emission").
 // Q: peel rays go to the seed buffer (sb, sl) instead of being marched here.
 template <class R, bool GRID, bool Q = false>
@@ -686,12 +698,7 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
     if (GRID && m.src_kind == kSrcCellN2) {
         const Uni2<double> d1 = draw<double>(key, kSlotECell, 0);
         const Uni2<double> d2 = draw<double>(key, kSlotEOffs, 0);
-        const double target = d1.a * g.cdf_total;
-        uint64_t lo = 0, hi = g.ncell - 1;   // first index with cdf > target
-        while (lo < hi) {
-            const uint64_t mid = lo + (hi - lo) / 2;
-            if (g.cdf[mid] > target) hi = mid; else lo = mid + 1;
-        }
+        const uint64_t lo = emission_cell(g, d1.a);
         L.c[0] = int(lo % uint64_t(g.nx));
         L.c[1] = int((lo / uint64_t(g.nx)) % uint64_t(g.ny));
         L.c[2] = int(lo / (uint64_t(g.nx) * uint64_t(g.ny)));

@@ -83,13 +83,17 @@ __device__ __forceinline__ int find_batch(const BatchDev* b, int nb, uint64_t q)
 // at most tail.max_waves waves (four per CU) are still running and a wave
 // holds at most desc->wide live packets, it appends them to the tail list and
 // exits; k_tail then runs each of them in a wave of its own.
+//
+// Queue order (perm, may be null): slot q of the queue holds packet perm[q]
+// (spatially sorted emission, see k_emit_keys); every packet's history
+// depends only on its photon id, so the order changes no result.
 template <class R, bool GRID, bool SEEDS>
 __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* __restrict__ models,
                                                     const BatchDev* __restrict__ batches,
                                                     const StepDesc* __restrict__ desc,
                                                     unsigned long long* cursor, OutDev o, PoolDev<R> pool,
                                                     TailDev<R> tail, SeedBuf sb, unsigned long long* gstats,
-                                                    unsigned long long* gmax) {
+                                                    unsigned long long* gmax, const uint64_t* __restrict__ perm) {
     const uint64_t gid = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const uint64_t q_end = desc->q_end;
     const int nbatch = desc->nbatch;
@@ -161,8 +165,9 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
             base = __shfl(base, leader, 64);
             const uint32_t rank = lane_rank(mask);
             if (need) {
-                const uint64_t q = base + rank;
-                if (q < q_end) {
+                const uint64_t qs = base + rank;
+                if (qs < q_end) {
+                    const uint64_t q = perm ? perm[qs] : qs;
                     const int bi = find_batch(batches, nbatch, q);
                     const BatchDev b = batches[bi];
                     emit<R, GRID, useq>(g, models[b.model], o, b.first_id + (q - b.q0), q, b.model, pk, cnt, &sb,
@@ -586,6 +591,38 @@ __global__ void k_fx_to_f32(const unsigned long long* __restrict__ src, float* _
         dst[i] = float(double(src[i]) * inv_scale);
 }
 
+// Sort keys of the queue for spatially ordered emission: the Morton code
+// (x, y, z bits interleaved) of each n_HI^2-weighted packet's emission cell,
+// drawn exactly as the generator draws it; other sources sort first.
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {   // bit i -> bit 3i (21 bits)
+    v &= 0x1FFFFFull;
+    v = (v | (v << 32)) & 0x1F00000000FFFFull;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+__global__ void k_emit_keys(GridDev g, const ModelDev* __restrict__ models, const BatchDev* __restrict__ batches,
+                            int nbatch, uint64_t q_end, uint64_t* __restrict__ keys, uint64_t* __restrict__ vals) {
+    for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < q_end;
+         q += uint64_t(gridDim.x) * blockDim.x) {
+        const BatchDev b = batches[find_batch(batches, nbatch, q)];
+        const ModelDev& m = models[b.model];
+        uint64_t key = 0;
+        if (m.src_kind == kSrcCellN2) {
+            const uint64_t id = b.first_id + (q - b.q0);
+            const Key k{m.seed, m.req, uint32_t(id), uint32_t(id >> 32)};
+            const uint64_t c = emission_cell(g, draw<double>(k, kSlotECell, 0).a);
+            const uint64_t x = c % uint64_t(g.nx), y = (c / uint64_t(g.nx)) % uint64_t(g.ny);
+            const uint64_t z = c / (uint64_t(g.nx) * uint64_t(g.ny));
+            key = spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+        }
+        keys[q] = key;
+        vals[q] = q;
+    }
+}
+
 // Marks every slot of a fresh seed buffer empty.
 __global__ void k_seed_clear(PeelSeed* s, uint64_t n) {
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
@@ -896,6 +933,12 @@ struct thor_ctx {
     hipGraphExec_t s_graph = nullptr;
     int s_graph_prec = -1, s_graph_grid = 0, s_graph_block = 0;
     unsigned char* d_scratch = nullptr;    // this device's no-allocation scratch (device address)
+    // spatial presort of the queue: keys and values, their sorted copies, hipCUB scratch
+    uint64_t* d_sort = nullptr;            // 4 arrays of sort_cap entries
+    uint64_t sort_cap = 0;
+    void* d_sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    double split_presort = 0.0;
 
     // serving (continuous batching of shell-model requests)
     bool s_init = false;
@@ -1121,6 +1164,9 @@ OutDev make_out(thor_ctx* ctx, const thor_transport_opts* o) {
     return out;
 }
 
+// Whether a call presorts its queue (library default: on for grids).
+bool presort_on(const thor_transport_opts* o) { return o->presort >= 0; }
+
 // Lanes of a persistent wave that wait at their interaction sites before
 // they interact together (0: each interacts when it gets there).
 uint32_t park_lanes(const thor_transport_opts* o) {
@@ -1168,7 +1214,7 @@ void launch_persistent(thor_ctx* ctx, hipStream_t stream, int grid, int block, c
                        const StepDesc* d_desc, unsigned long long* cursor, const OutDev& out,
                        const ModelDev* d_models, void* pool_pk, int* pool_alive, const SeedBuf& sb,
                        bool hand_off = false, unsigned long long* gmax = nullptr,
-                       unsigned long long* gstats = nullptr) {
+                       unsigned long long* gstats = nullptr, const uint64_t* perm = nullptr) {
     PoolDev<R> pool{reinterpret_cast<Pkt<R>*>(pool_pk), pool_alive};
     const TailDev<R> tail = tail_dev<R>(ctx, hand_off);
     if (!gstats) gstats = ctx->d_stats;
@@ -1176,10 +1222,10 @@ void launch_persistent(thor_ctx* ctx, hipStream_t stream, int grid, int block, c
     if constexpr (GRID) seeds = sb.s != nullptr;
     if (seeds)
         hipLaunchKernelGGL((k_persistent<R, GRID, GRID>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
-                           d_b, d_desc, cursor, out, pool, tail, sb, gstats, gmax);
+                           d_b, d_desc, cursor, out, pool, tail, sb, gstats, gmax, perm);
     else
         hipLaunchKernelGGL((k_persistent<R, GRID, false>), dim3(grid), dim3(block), 0, stream, ctx->grid, d_models,
-                           d_b, d_desc, cursor, out, pool, tail, sb, gstats, gmax);
+                           d_b, d_desc, cursor, out, pool, tail, sb, gstats, gmax, perm);
 }
 
 // The tail kernel over what the preceding persistent launch handed off (its
@@ -1358,7 +1404,8 @@ void thor_destroy(thor_ctx* ctx) {
                     ctx->d_rec_fate, ctx->d_pool_pk, ctx->d_pool_alive, ctx->d_done,
                     ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
                     ctx->d_seeds, ctx->d_seedctl, ctx->d_axr[0], ctx->d_axr[1], ctx->d_axr[2],
-                    ctx->d_tail_pk, ctx->d_tail_home, ctx->d_tailctl, ctx->d_xstats};
+                    ctx->d_tail_pk, ctx->d_tail_home, ctx->d_tailctl, ctx->d_xstats, ctx->d_sort,
+                    ctx->d_sort_tmp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& kv : ctx->s_reqs)
@@ -1691,15 +1738,63 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         unsigned long long* cur = ctx->d_stats + kNumU64Counters;
         double t_tr = 0.0, t_pp = 0.0, t_tail = 0.0;
         uint64_t passes = 0;
+        // spatial order of the queue: emission cells drawn by a pre-pass, Morton
+        // keys radix-sorted; the persistent kernel takes packets through the
+        // sorted permutation
+        const uint64_t* perm = nullptr;
+        ctx->split_presort = 0.0;
+        bool any_cell = false;
+        for (size_t i = 0; i < nb; ++i) any_cell |= ctx->pending[i].src.kind == THOR_SRC_CELL_N2;
+        if (grid && !bounded && any_cell && presort_on(opt) && q_end > 1) {
+            if (q_end > ctx->sort_cap) {
+                dfree(ctx, ctx->d_sort, ctx->sort_cap * 32);
+                ctx->d_sort = nullptr;
+                ctx->sort_cap = 0;
+                s = dalloc(ctx, (void**)&ctx->d_sort, q_end * 32, "presort keys");
+                if (s) return s;
+                ctx->sort_cap = q_end;
+            }
+            uint64_t* keys = ctx->d_sort;
+            uint64_t* vals = ctx->d_sort + ctx->sort_cap;
+            uint64_t* keys2 = ctx->d_sort + 2 * ctx->sort_cap;
+            uint64_t* vals2 = ctx->d_sort + 3 * ctx->sort_cap;
+            int bits = 1;
+            while ((1 << bits) < std::max(ctx->grid.nx, std::max(ctx->grid.ny, ctx->grid.nz))) ++bits;
+            const int end_bit = std::min(64, 3 * bits);
+            size_t need = 0;
+            HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, keys2, vals, vals2, (int64_t)q_end, 0,
+                                                           end_bit, ctx->stream));
+            if (need > ctx->sort_tmp_bytes) {
+                dfree(ctx, ctx->d_sort_tmp, ctx->sort_tmp_bytes);
+                ctx->d_sort_tmp = nullptr;
+                ctx->sort_tmp_bytes = 0;
+                s = dalloc(ctx, &ctx->d_sort_tmp, need, "presort scratch");
+                if (s) return s;
+                ctx->sort_tmp_bytes = need;
+            }
+            HIPCHK(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
+            hipLaunchKernelGGL(k_emit_keys, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->grid,
+                               ctx->d_models, ctx->d_batches, int(nb), q_end, keys, vals);
+            HIPCHK(ctx, hipGetLastError());
+            size_t tmp = ctx->sort_tmp_bytes;
+            HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(ctx->d_sort_tmp, tmp, keys, keys2, vals, vals2,
+                                                           (int64_t)q_end, 0, end_bit, ctx->stream));
+            HIPCHK(ctx, hipEventRecord(ctx->ev_b, ctx->stream));
+            HIPCHK(ctx, hipEventSynchronize(ctx->ev_b));
+            float ms = 0.0f;
+            HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev_a, ctx->ev_b));
+            ctx->split_presort = ms;
+            perm = vals2;
+        }
         for (;;) {
             if (seeds)
                 hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_seedctl, 2 + kXcds);
             if (hand_off)
                 hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_tailctl, 3);
             if (seeds || hand_off) HIPCHK(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
-            if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats)
+            if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats, nullptr, perm)
                            : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats);
-            else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats)
+            else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats, nullptr, perm)
                       : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats);
             if (hand_off) {
                 HIPCHK(ctx, hipEventRecord(ctx->ev_c, ctx->stream));
@@ -1774,6 +1869,7 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
     ctx->last.tail_events = hx[1 + 5] + hx[1 + 6];          // n_res + n_dust
     ctx->last.tail_main_visits = hx[1 + 7];
     ctx->last.tail_peel_visits = hx[1 + 8];
+    ctx->last.presort_ms = ctx->split_presort;
     if (out_stats) *out_stats = ctx->last;
     if (bounded) {
         // work left: queue not drained or packets parked in the pool
