@@ -319,6 +319,14 @@ const char *thor_last_error(void);
 thor_status thor_eval_voigt(thor_ctx *ctx, const double *a, const double *x, double *out,
                             uint64_t n, int32_t precision);
 
+/* Core-to-wing transition x_cw(a) of H(a, x) (Appendix A.2) by the quartic
+ * in ln a printed there, with the device code: a, out are device float64
+ * arrays of n entries (a > 0, normal); precision FP64 (library logarithm)
+ * or MIXED (FP32, logarithm from the exponent bits and an atanh series, the
+ * fast form of Appendix A.2).  Within 0.6 % of the exact Lambert-W value for
+ * 1.5e-5 <= a <= 1e-2. */
+thor_status thor_eval_xcw(thor_ctx *ctx, const double *a, double *out, uint64_t n, int32_t precision);
+
 /* Draw n u_parallel samples (eq. uparallel) at (x, a) with the kernels' own
  * sampler, photon ids 0..n-1, event `event`, key (seed, 0): out_u float64[n]
  * and out_trials uint32[n], device arrays. */

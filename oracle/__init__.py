@@ -96,6 +96,9 @@ def lib():
         L.or_voigt.argtypes = [d, d]
         L.or_dawson.restype = d
         L.or_dawson.argtypes = [d]
+        for fn in ("or_lambert_wm1", "or_xcw_exact", "or_xcw_b25"):
+            getattr(L, fn).restype = d
+            getattr(L, fn).argtypes = [d]
         L.or_line_params.argtypes = [d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
         L.or_philox4x32_10.argtypes = [C.POINTER(u32), C.POINTER(u32), C.POINTER(u32)]
         L.or_draw.argtypes = [u32, u32, u32, u32, u64, C.POINTER(d)]
@@ -151,6 +154,19 @@ def voigt(a, x):
 def dawson(x):
     f = lib().or_dawson
     return np.array([f(float(v)) for v in np.ravel(x)]).reshape(np.shape(x))
+
+
+def lambert_wm1(z):
+    """Lower real branch of Lambert's W on [-1/e, 0), elementwise."""
+    f = lib().or_lambert_wm1
+    return np.array([f(float(v)) for v in np.ravel(z)]).reshape(np.shape(z))
+
+
+def xcw(a, method="exact"):
+    """Core-to-wing transition x_cw(a) (Appendix A.2): "exact" by Lambert W,
+    "b25" by the quartic in ln a."""
+    f = {"exact": lib().or_xcw_exact, "b25": lib().or_xcw_b25}[method]
+    return np.array([f(float(v)) for v in np.ravel(a)]).reshape(np.shape(a))
 
 
 def philox(ctr, key):

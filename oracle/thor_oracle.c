@@ -97,6 +97,58 @@ static long double dawson_ld(long double x)
 
 double or_dawson(double x) { return (double)dawson_ld(x); }
 
+/* ---------------------------------------------- core-to-wing transition x_cw */
+/* Appendix A.2: x_cw(a) is where the Gaussian core exp(-x^2) of H(a,x) meets */
+/* its Lorentzian wing a/(sqrt(pi) x^2).  With y = -x^2 the condition reads  */
+/* y e^y = -a/sqrt(pi), so x_cw = sqrt(-W_{-1}(-a/sqrt(pi))), W_{-1} the     */
+/* lower real branch of Lambert's W (defined for -1/e <= z < 0).             */
+double or_lambert_wm1(double z)
+{
+    const double e = exp(1.0);
+    if (!(z >= -1.0 / e && z < 0.0))
+        return NAN;
+    double w;
+    if (z < -0.3) {
+        /* near the branch point z = -1/e: w = -1 - p - p^2/3, p = sqrt(2(1 + e z)) */
+        const double p = sqrt(fmax(0.0, 2.0 * (1.0 + e * z)));
+        w = -1.0 - p - p * p / 3.0;
+    } else {
+        /* asymptotic start for z -> 0-: w = L1 - L2 + L2/L1 */
+        const double L1 = log(-z), L2 = log(-L1);
+        w = L1 - L2 + L2 / L1;
+    }
+    /* Halley's iteration on f(w) = w e^w - z */
+    for (int it = 0; it < 64; ++it) {
+        const double ew = exp(w);
+        const double f = w * ew - z;
+        if (w == -1.0)
+            break;
+        const double step = f / (ew * (w + 1.0) - (w + 2.0) * f / (2.0 * w + 2.0));
+        w -= step;
+        if (fabs(step) <= 4e-16 * fabs(w))
+            break;
+    }
+    return w;
+}
+
+double or_xcw_exact(double a)
+{
+    return sqrt(-or_lambert_wm1(-a / sqrt(PI)));
+}
+
+/* the quartic in ln a of Appendix A.2 (five coefficients printed there) */
+double or_xcw_b25(double a)
+{
+    const double L = log(a);
+    const double c[5] = {1.03489162, -6.17680644e-1, -8.73073343e-2, -7.91384757e-3, -2.76037084e-4};
+    double s = 0.0, p = 1.0;
+    for (int i = 0; i < 5; ++i) {
+        s += c[i] * p;
+        p *= L;
+    }
+    return s;
+}
+
 /* |x| <= 6.5: Taylor series of the entire function w about the real point */
 /* x, w(x + i a) = sum_n (i a)^n w^(n)(x) / n!, with                        */
 /*   w(x) = exp(-x^2) + (2i/sqrt(pi)) F(x),                                 */

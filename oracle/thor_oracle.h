@@ -102,6 +102,11 @@ void or_line_params(double T, double *v_th, double *a, double *sigma0);
 double or_voigt(double a, double x);
 /* Dawson's integral (long-double power series), exported for its own pin */
 double or_dawson(double x);
+/* lower real branch W_{-1}(z) of Lambert's W, -1/e <= z < 0 (NaN outside) */
+double or_lambert_wm1(double z);
+/* core-to-wing transition x_cw(a): exact (Lambert W) and the quartic in ln a */
+double or_xcw_exact(double a);
+double or_xcw_b25(double a);
 /* Philox4x32-10 block function */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 /* the two 53-bit uniforms of a keyed draw */

@@ -226,7 +226,7 @@ __device__ __forceinline__ double voigt64(double a, double x) {
 // |x| = 40 (3e-14), N = 6 from |x| = 20 (1e-14) and N = 9 from |x| = 12
 // (4e-15); nearer the line the FP64 Voigt function.  1 / |z|^2 comes from the
 // hardware reciprocal refined by two Newton steps (FP64) or alone (FP32).
-// FP32 (voigt32): N = 4 beyond |x| = 6.5 (3e-6), where its Taylor branch ends.
+// FP32 (the forest kernel): N = 4 beyond |x| = 6.5 (3e-6).
 template <class R, int N>
 __device__ __forceinline__ R voigt_wing(R a, R x) {
     // c_n = (2n - 1)!! / 2^n
@@ -248,30 +248,46 @@ __device__ __forceinline__ R voigt_wing(R a, R x) {
     return -(zr * pi + zi * pr) * R(1.0 / kSqrtPi);         // -Im(zeta P) / sqrt(pi)
 }
 
+// FP32 H(a, x) in one form for every x, so that the lanes of a wave near the
+// line and in the wing run the same instructions except for g below.
+// Expanding w(x + i a) = w(x) + i a w'(x) - a^2 w''(x)/2 + ... with
+// w(x) = exp(-x^2) + (2i/sqrt(pi)) F(x) (F Dawson's integral) gives
+//   H = exp(-x^2) (1 - a^2 (2x^2 - 1)) - (2a/sqrt(pi)) g(x) + O(a^3),
+//   g(x) = 1 - 2x F(x).
+// |x| <= 6.5: F from the Dawson table; the a^3, a^4 terms are added when
+// a > 3e-3.  |x| > 6.5: g from its asymptotic series
+//   g = -(r/2)(1 + 3r/2 + 15r^2/4 + 105r^3/8 + 945r^4/16), r = 1/x^2
+// (truncation below 3e-6 relative), with the next order in a folded in as
+// x^2/(x^2 + a^2) (the first term of the series of w at x + i a is
+// a/(sqrt(pi)(x^2 + a^2)); the rest of the a^2 terms are below 1e-6
+// relative there).  Relative error below 2e-5 for a <= 0.05.
 __device__ __forceinline__ float voigt32(float a, float x, const float* tab = c_dawson32) {
     const float ax = fabsf(x);
     constexpr float two_rsqpi = float(2.0 / kSqrtPi);
-    if (ax <= 6.5f) {
-        const float e = __expf(-ax * ax);
-        float wr_p = e, wi_p = two_rsqpi * dawson32(ax, tab);
-        float wr = -2.0f * ax * wr_p, wi = fmaf(-2.0f * ax, wi_p, two_rsqpi);
-        // n = 1: Re(i a w') = -a Im w'
-        float sum = fmaf(-a, wi, wr_p);
-        // n = 2: Re((i a)^2 w'')/2 = -a^2 Re w''/2
-        float nr = fmaf(-2.0f * ax, wr, -2.0f * wr_p);
-        float ni = fmaf(-2.0f * ax, wi, -2.0f * wi_p);
-        sum = fmaf(-0.5f * a * a, nr, sum);
-        if (a > 3e-3f) {
-            // n = 3: Re((i a)^3 w''')/6 = a^3 Im w'''/6 ; n = 4: a^4 Re w''''/24
-            const float r3 = fmaf(-2.0f * ax, nr, -4.0f * wr), i3 = fmaf(-2.0f * ax, ni, -4.0f * wi);
-            const float r4 = fmaf(-2.0f * ax, r3, -6.0f * nr);
-            const float a2 = a * a;
-            sum = fmaf(a2 * a * (1.0f / 6.0f), i3, sum);
-            sum = fmaf(a2 * a2 * (1.0f / 24.0f), r4, sum);
-        }
-        return sum;
+    const float x2 = ax * ax;
+    const float e = __expf(-x2);
+    const bool core = ax <= 6.5f;
+    float g, c = 1.0f, wi_p = 0.0f;    // g here: (2/sqrt(pi)) g(x)
+    if (core) {
+        wi_p = two_rsqpi * dawson32(ax, tab);
+        g = fmaf(-2.0f * ax, wi_p, two_rsqpi);
+    } else {
+        const float r = __builtin_amdgcn_rcpf(x2);
+        g = (-0.5f * two_rsqpi) * r * fmaf(r, fmaf(r, fmaf(r, fmaf(r, 59.0625f, 13.125f), 3.75f), 1.5f), 1.0f);
+        c = x2 * __builtin_amdgcn_rcpf(fmaf(a, a, x2));
     }
-    return voigt_wing<float, 4>(a, ax);
+    float sum = fmaf(-a * c, g, e * fmaf(-a * a, fmaf(2.0f, x2, -1.0f), 1.0f));
+    if (a > 3e-3f && core) {
+        // n = 3: a^3 Im(w''')/6, n = 4: a^4 Re(w'''')/24, from w' = -2x w + 2i/sqrt(pi)
+        const float wr = -2.0f * ax * e, wi = g;
+        const float nr = fmaf(-2.0f * ax, wr, -2.0f * e), ni = fmaf(-2.0f * ax, wi, -2.0f * wi_p);
+        const float r3 = fmaf(-2.0f * ax, nr, -4.0f * wr), i3 = fmaf(-2.0f * ax, ni, -4.0f * wi);
+        const float r4 = fmaf(-2.0f * ax, r3, -6.0f * nr);
+        const float a2 = a * a;
+        sum = fmaf(a2 * a * (1.0f / 6.0f), i3, sum);
+        sum = fmaf(a2 * a2 * (1.0f / 24.0f), r4, sum);
+    }
+    return sum;
 }
 
 // A lower bound of H(a, x) that decides sure peel cuts without the profile.
@@ -289,6 +305,32 @@ __device__ __forceinline__ float voigt_floor(float a, float x) {
 template <class R> __device__ __forceinline__ R voigt(R a, R x);
 template <> __device__ __forceinline__ double voigt<double>(double a, double x) { return voigt64(a, x); }
 template <> __device__ __forceinline__ float voigt<float>(float a, float x) { return voigt32(a, x); }
+
+// ---------------------------------------------------------------------------
+// Core-to-wing transition x_cw(a) of H(a, x) (Appendix A.2: where exp(-x^2)
+// meets a/(sqrt(pi) x^2)), by the quartic in ln a printed there.  FP32 takes
+// ln a without the library logarithm: the exponent field gives e ln 2, the
+// mantissa m (folded into [sqrt(1/2), sqrt(2))) gives ln m = 2 atanh(s),
+// s = (m - 1)/(m + 1), |s| <= 0.172, by four terms of the atanh series
+// (truncation below 3e-8).  Positive normal a only.
+__device__ __forceinline__ float log_bits(float v) {
+    uint32_t b = __float_as_uint(v);
+    int e = int((b >> 23) & 0xFFu) - 127;
+    float m = __uint_as_float((b & 0x7FFFFFu) | 0x3F800000u);
+    if (m > 1.41421356f) { m *= 0.5f; e += 1; }
+    const float s = (m - 1.0f) * __builtin_amdgcn_rcpf(m + 1.0f);
+    const float s2 = s * s;
+    const float lm = 2.0f * s * (1.0f + s2 * (1.0f / 3.0f + s2 * (0.2f + s2 * (1.0f / 7.0f))));
+    return float(e) * 0.69314718f + lm;
+}
+template <class R>
+__device__ __forceinline__ R xcw_b25(R a) {
+    R L;
+    if constexpr (sizeof(R) == 8) L = log(a);
+    else L = log_bits(a);
+    return R(1.03489162) + L * (R(-6.17680644e-1) + L * (R(-8.73073343e-2) + L * (R(-7.91384757e-3) +
+                                                                                  L * R(-2.76037084e-4))));
+}
 
 // ---------------------------------------------------------------------------
 // u_parallel sampler, eq. (uparallel): f(u) ~ exp(-u^2) / ((x-u)^2 + a^2).

@@ -15,9 +15,13 @@
 
 #include "thor_device.hpp"
 
-// cells of a grid peel ray whose records are fetched together
+// cells of a grid peel ray whose records are fetched together: inline and
+// FP64 rays, and the FP32 rays of the peel pass
 #ifndef THOR_PEEL_LOOKAHEAD
 #define THOR_PEEL_LOOKAHEAD 2
+#endif
+#ifndef THOR_PASS_LOOKAHEAD
+#define THOR_PASS_LOOKAHEAD 6
 #endif
 
 namespace thor {

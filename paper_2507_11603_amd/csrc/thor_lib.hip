@@ -338,7 +338,8 @@ __global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restri
 // takes chunks of kPassChunk slots from per-XCD counters; a lane whose ray is
 // finished takes the next slot of the chunk (ballot + mbcnt), so lanes keep
 // marching while their neighbours' rays are long.  A ray advances
-// THOR_PEEL_LOOKAHEAD cells per round with their records fetched together;
+// THOR_PASS_LOOKAHEAD cells (FP32 pencil records; THOR_PEEL_LOOKAHEAD in
+// FP64) per round with their records fetched together;
 // segment lengths and the order of the tau sum are those of the serial march.
 // Contributions are summed per cube element in an LDS table of the workgroup
 // first and reach the cube once per element at the end (a point source
@@ -485,7 +486,7 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
             continue;
         }
         if (have) {
-            constexpr int kLook = THOR_PEEL_LOOKAHEAD;
+            constexpr int kLook = kAxis ? THOR_PASS_LOOKAHEAD : THOR_PEEL_LOOKAHEAD;
             const int left = pos ? dim - ca : ca + 1;       // >= 1
             const int mm = left < kLook ? left : kLook;
             bool cut = false;
@@ -570,10 +571,16 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
     flush_counters(cnt, gstats);
 }
 
-// FP32 pass: at most 80 VGPRs, six waves per SIMD to hide the gather latency.
+// FP32 pass: four waves per SIMD (at most 128 VGPRs), each lane with the
+// records of THOR_PASS_LOOKAHEAD cells in flight: on the 1024^3 web box six
+// cells at four waves beat two at six waves by 6 % (a wave's gathers are
+// latency-bound; more of them per lane hide more of it).
 // V: float32 cube, or unsigned long long for the fixed-point cube.
+#ifndef THOR_PEEL_WAVES
+#define THOR_PEEL_WAVES 4
+#endif
 template <class V>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(THOR_PEEL_WAVES)))
 void k_peel_pass_f32(GridDev g, OutDev o, SeedBuf sb, unsigned long long* work, unsigned long long* gstats) {
     peel_pass<float, V>(g, o, sb, work, gstats);
 }
@@ -687,6 +694,12 @@ template <class R>
 __global__ void k_eval_voigt(const double* a, const double* x, double* out, uint64_t n) {
     const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) out[i] = double(voigt<R>(R(a[i]), R(x[i])));
+}
+
+template <class R>
+__global__ void k_eval_xcw(const double* a, double* out, uint64_t n) {
+    const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = double(xcw_b25<R>(R(a[i])));
 }
 
 template <class R>
@@ -2056,6 +2069,22 @@ thor_status thor_eval_voigt(thor_ctx* ctx, const double* a, const double* x, dou
         hipLaunchKernelGGL(k_eval_voigt<double>, dim3(blocks), dim3(256), 0, ctx->stream, a, x, out, n);
     else if (precision == THOR_PREC_MIXED)
         hipLaunchKernelGGL(k_eval_voigt<float>, dim3(blocks), dim3(256), 0, ctx->stream, a, x, out, n);
+    else
+        return fail(THOR_E_INVAL, "bad precision");
+    HIPCHK(ctx, hipGetLastError());
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return THOR_OK;
+}
+
+thor_status thor_eval_xcw(thor_ctx* ctx, const double* a, double* out, uint64_t n, int32_t precision) {
+    CHECK_CTX(ctx);
+    if (!a || !out) return fail(THOR_E_INVAL, "null array");
+    if (n == 0) return THOR_OK;
+    const unsigned blocks = unsigned((n + 255) / 256);
+    if (precision == THOR_PREC_FP64)
+        hipLaunchKernelGGL(k_eval_xcw<double>, dim3(blocks), dim3(256), 0, ctx->stream, a, out, n);
+    else if (precision == THOR_PREC_MIXED)
+        hipLaunchKernelGGL(k_eval_xcw<float>, dim3(blocks), dim3(256), 0, ctx->stream, a, out, n);
     else
         return fail(THOR_E_INVAL, "bad precision");
     HIPCHK(ctx, hipGetLastError());

@@ -3,20 +3,22 @@ bench.py reports beside its roofline: bytes the L2 caches read from and
 write to the memory fabric, and VALU activity (VALUBusy, VALUUtilization,
 SQ_INSTS_VALU), per kernel and per batch.
 
-Reads are counted from the L2 read requests by size (TCC_EA0_RDREQ_32B,
-_64B, _128B): bytes = 32 n32 + 64 n64 + 128 n128.  (The derived FETCH_SIZE
-counts a 128-byte request as 64 bytes, so it reports half of a streaming
-copy.)  Writes come from WRITE_SIZE.  The passes must profile the same
-command, run with `--warmup 0` (so every dispatch of a kernel belongs to the
-timed call) and `--calib-copy-mib M`: the first dispatch is then a plain
-device copy of M MiB, which reads and writes exactly M MiB; the record keeps
-what the counters report for it as a check (read) and a scale (write).
+Reads come from FETCH_SIZE and writes from WRITE_SIZE (KiB per dispatch),
+each scaled by what it reports for a plain device copy of known size: the
+passes must profile the same command, run with `--warmup 0` (so every
+dispatch of a kernel belongs to the timed call) and `--calib-copy-mib M`, so
+that the first dispatch copies exactly M MiB (reads and writes M MiB).  The
+derived FETCH_SIZE counts a 128-byte request as 64 bytes, so its copy scale
+is about 2; a kernel whose requests are smaller than the copy's is then
+over-counted by up to that factor.  An optional pass over the L2 read
+requests by size (TCC_EA0_RDREQ_32B, _64B, _128B; bytes = 32 n32 + 64 n64 +
+128 n128) gives the reads without that assumption, kept beside them.
 
 The record carries a hash of the kernel sources; bench.py uses it only while
 the hash matches the sources it was built from.
 
-    python -m paper_2507_11603_amd.pmc_summary --reads DIR --write DIR --valu DIR \\
-        --copy-mib 1024 --batches 3 --out profiles/shell128_counters.json
+    python -m paper_2507_11603_amd.pmc_summary --fetch DIR --write DIR [--reads DIR] \\
+        [--valu DIR] [--hits DIR] --copy-mib 1024 --batches 1 --packets N --out RECORD.json
 """
 from __future__ import annotations
 
@@ -64,39 +66,49 @@ def _durations(rows):
     return {int(r["Dispatch_Id"]): int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows}
 
 
-def summarise(reads_dir: str, write_dir: str, valu_dir: str | None, copy_mib: int, batches: int,
-              packets: int = 0, hits_dir: str | None = None) -> dict:
-    rec = {"source_hash": source_hash(), "batches": batches, "packets": packets, "kernels": {}}
-    # reads: request counts by size
-    rows = _rows(reads_dir)
-    per = {sz: _per_dispatch(rows, "TCC_EA0_RDREQ_%dB" % sz) for sz in (32, 64, 128)}
-    names = per[128][1]
-    rbytes = collections.defaultdict(float)
-    for sz, (vals, _) in per.items():
-        for k, v in vals.items():
-            rbytes[k] += sz * v
-    first = min(rbytes)
-    if "copy" not in names[first].lower():
-        raise ValueError("first dispatch %r is not the calibration copy" % names[first])
-    rec["read_check"] = rbytes[first] / (copy_mib * 2.0 ** 20)     # 1.0: the copy reads what it copies
-    for kname in KERNELS:
-        ds = [k for k in rbytes if kname in names[k]]
-        if ds:
-            kr = rec["kernels"].setdefault(kname, {})
-            kr["launches"] = len(ds)
-            kr["read_bytes_per_batch"] = sum(rbytes[k] for k in ds) / batches
-    # writes: WRITE_SIZE (KiB), scaled by the copy
-    vals, names = _per_dispatch(_rows(write_dir), "WRITE_SIZE")
+def _scaled_kib(d: str, counter: str, copy_mib: int, batches: int, rec: dict, key: str, scale_key: str):
+    """Per-batch bytes of `counter` (KiB per dispatch) for each kernel, scaled
+    by the calibration copy (the first dispatch)."""
+    vals, names = _per_dispatch(_rows(d), counter)
     first = min(vals)
     if "copy" not in names[first].lower():
         raise ValueError("first dispatch %r is not the calibration copy" % names[first])
     scale = copy_mib * 1024.0 / vals[first]
-    rec["write_scale"] = scale
+    rec[scale_key] = scale
     for kname in KERNELS:
         ds = [k for k in vals if kname in names[k]]
         if ds:
             kr = rec["kernels"].setdefault(kname, {})
-            kr["write_bytes_per_batch"] = sum(vals[k] for k in ds) * 1024.0 * scale / batches
+            kr["launches"] = len(ds)
+            kr[key] = sum(vals[k] for k in ds) * 1024.0 * scale / batches
+
+
+def summarise(fetch_dir: str | None, write_dir: str, valu_dir: str | None, copy_mib: int, batches: int,
+              packets: int = 0, hits_dir: str | None = None, reads_dir: str | None = None) -> dict:
+    rec = {"source_hash": source_hash(), "batches": batches, "packets": packets, "kernels": {}}
+    if fetch_dir:
+        _scaled_kib(fetch_dir, "FETCH_SIZE", copy_mib, batches, rec, "read_bytes_per_batch", "fetch_scale")
+    if reads_dir:
+        # reads from the request counts by size
+        rows = _rows(reads_dir)
+        per = {sz: _per_dispatch(rows, "TCC_EA0_RDREQ_%dB" % sz) for sz in (32, 64, 128)}
+        names = per[128][1]
+        rbytes = collections.defaultdict(float)
+        for sz, (vals, _) in per.items():
+            for k, v in vals.items():
+                rbytes[k] += sz * v
+        first = min(rbytes)
+        if "copy" not in names[first].lower():
+            raise ValueError("first dispatch %r is not the calibration copy" % names[first])
+        rec["read_check"] = rbytes[first] / (copy_mib * 2.0 ** 20)     # 1.0: the copy reads what it copies
+        key = "read_req_bytes_per_batch" if fetch_dir else "read_bytes_per_batch"
+        for kname in KERNELS:
+            ds = [k for k in rbytes if kname in names[k]]
+            if ds:
+                kr = rec["kernels"].setdefault(kname, {})
+                kr["launches"] = len(ds)
+                kr[key] = sum(rbytes[k] for k in ds) / batches
+    _scaled_kib(write_dir, "WRITE_SIZE", copy_mib, batches, rec, "write_bytes_per_batch", "write_scale")
     if hits_dir:
         rows = _rows(hits_dir)
         for kname in KERNELS:
@@ -129,7 +141,8 @@ def summarise(reads_dir: str, write_dir: str, valu_dir: str | None, copy_mib: in
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--reads", required=True, help="pass with TCC_EA0_RDREQ_32B/_64B/_128B")
+    ap.add_argument("--fetch", default=None, help="pass with FETCH_SIZE")
+    ap.add_argument("--reads", default=None, help="pass with TCC_EA0_RDREQ_32B/_64B/_128B")
     ap.add_argument("--write", required=True, help="pass with WRITE_SIZE")
     ap.add_argument("--valu", default=None, help="pass with VALUBusy VALUUtilization SQ_INSTS_VALU")
     ap.add_argument("--hits", default=None, help="pass with TCC_HIT TCC_MISS")
@@ -137,10 +150,14 @@ def main():
     ap.add_argument("--batches", type=int, required=True)
     ap.add_argument("--packets", type=int, default=0, help="packets per batch")
     ap.add_argument("--command", default="", help="the profiled command, stored with the record")
+    ap.add_argument("--fields", default="", help="bench.py --fields of the profiled command")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    rec = summarise(a.reads, a.write, a.valu, a.copy_mib, a.batches, a.packets, a.hits)
+    if not (a.fetch or a.reads):
+        ap.error("--fetch or --reads is required")
+    rec = summarise(a.fetch, a.write, a.valu, a.copy_mib, a.batches, a.packets, a.hits, a.reads)
     rec["command"] = a.command
+    rec["fields"] = a.fields
     with open(a.out, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))

@@ -32,7 +32,7 @@ OUT = {"spectrum": 0, "cube": 1, "records": 2, "stats": 3, "cube_fixed": 4}
 ACCUM = {"f32": 0, "fixed64": 1}
 SYMBOLS = ["thor_create", "thor_destroy", "thor_load_grid", "thor_emit", "thor_transport",
            "thor_reset_outputs", "thor_read_spectra", "thor_output_bytes", "thor_last_error",
-           "thor_eval_voigt", "thor_sample_upar", "thor_submit", "thor_step", "thor_poll",
+           "thor_eval_voigt", "thor_eval_xcw", "thor_sample_upar", "thor_submit", "thor_step", "thor_poll",
            "thor_ray_project", "thor_ray_forest", "thor_ray_last_error", "thor_transport_noalloc"]
 
 
@@ -144,6 +144,7 @@ def lib():
             "thor_output_bytes": ([vp, C.c_int], u64),
             "thor_last_error": ([], C.c_char_p),
             "thor_eval_voigt": ([vp, vp, vp, vp, u64, i32], C.c_int),
+            "thor_eval_xcw": ([vp, vp, vp, u64, i32], C.c_int),
             "thor_sample_upar": ([vp, d, d, u32, u32, vp, vp, u64, i32], C.c_int),
             "thor_submit": ([vp, C.POINTER(thor_shell_request), C.POINTER(u64)], C.c_int),
             "thor_step": ([vp, u32, C.POINTER(thor_transport_opts)], C.c_int),
@@ -215,6 +216,10 @@ def thor_output_bytes(ctx, which: str) -> int:
 
 def thor_eval_voigt(ctx, a_ptr, x_ptr, out_ptr, n, precision):
     _check(lib().thor_eval_voigt(ctx, a_ptr, x_ptr, out_ptr, n, PREC[precision]))
+
+
+def thor_eval_xcw(ctx, a_ptr, out_ptr, n, precision):
+    _check(lib().thor_eval_xcw(ctx, a_ptr, out_ptr, n, PREC[precision]))
 
 
 def thor_sample_upar(ctx, x, a, seed, event, u_ptr, tr_ptr, n, precision):
@@ -434,6 +439,14 @@ class Transport:
         out = t.empty_like(x_t)
         thor_eval_voigt(self.ctx, a_t.data_ptr(), x_t.data_ptr(), out.data_ptr(), x_t.numel(), precision)
         return out.cpu().numpy().reshape(np.shape(x))
+
+    def xcw(self, a, precision="fp64") -> np.ndarray:
+        """Core-to-wing transition x_cw(a) by the Appendix A.2 quartic."""
+        t = self.torch
+        a_t = t.as_tensor(np.ascontiguousarray(a, dtype=np.float64).ravel(), device=self.device)
+        out = t.empty_like(a_t)
+        thor_eval_xcw(self.ctx, a_t.data_ptr(), out.data_ptr(), a_t.numel(), precision)
+        return out.cpu().numpy().reshape(np.shape(a))
 
     def sample_upar(self, x, a, n, seed=7, event=1, precision="fp64"):
         t = self.torch

@@ -11,6 +11,7 @@ warm-up calls come first), every kernel's dispatch count, total and average
 duration from the trace, and, when the bench line is given, the dominant
 kernel's average launch time that bench.py measured with HIP events, so the
 two can be compared.  The whole trace's per-kernel table follows.
+`--first-call -1` picks the longest call instead.
 """
 from __future__ import annotations
 
@@ -56,6 +57,12 @@ def summarise(trace_dir: str, first_call: int, calls: int, bench: dict | None, c
         if "k_spec_fold" in r["Kernel_Name"]:
             groups.append(cur)
             cur = []
+    if first_call < 0:
+        # the longest call (the timed 1e8-packet step of the default bench,
+        # whose autotuner and warm-up calls come first)
+        span = [sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in g) for g in groups]
+        first_call = max(range(len(groups)), key=lambda i: span[i])
+        calls = 1
     sel = [r for g in groups[first_call:first_call + calls] for r in g]
     lines = ["Command (from the repository root on the GPU host):", "", "```", command, "```", "",
              "Trace: `%s` (%d dispatches, %d thor_transport calls).  Calls %d..%d are the timed steps."

@@ -96,11 +96,14 @@ def test_forest_degenerate_inputs():
     shape = (4, 5, 6)
     n, T, v = fields(shape, 3)
     dn, dT, dv = dev(n), dev(T), dev(v)
-    # no rays: nothing is written
-    out = torch.full((1, 1, 8), 7.0, dtype=torch.float64, device="cuda")
-    thor.ray_forest(dn, dT, dv, 2, 1e21, 0.0, 1, (0, 0, 0, 1), 8, 0.0, 1e7, out=out)
+    # no rays: an empty result; a caller's output of another shape is refused
+    out = torch.empty((1, 0, 8), dtype=torch.float64, device="cuda")
+    r = thor.ray_forest(dn, dT, dv, 2, 1e21, 0.0, 1, (0, 0, 0, 1), 8, 0.0, 1e7, out=out)
     torch.cuda.synchronize()
-    assert torch.all(out == 7.0)
+    assert tuple(r.shape) == (1, 0, 8)
+    with pytest.raises(ValueError):
+        thor.ray_forest(dn, dT, dv, 2, 1e21, 0.0, 1, (0, 0, 0, 1), 8, 0.0, 1e7,
+                        out=torch.full((1, 1, 8), 7.0, dtype=torch.float64, device="cuda"))
     # all-empty gas: tau is exactly zero, even where T = 0
     z = torch.zeros_like(dn)
     tau = thor.ray_forest(z, torch.zeros_like(dT), dv, 1, 1e21, 6.6e-18, 2, (0, 6, 0, 4), 40, 0.0, 1e7)

@@ -92,6 +92,49 @@ def test_dawson_vs_mpmath():
     assert oracle.dawson([0.0])[0] == 0.0
 
 
+# ------------------------------------------------------------ x_cw (Appendix A.2)
+def test_lambert_wm1_vs_mpmath():
+    """The lower branch of Lambert's W against mpmath at 40 digits, from
+    z -> 0- to the branch point -1/e (where W is ill-conditioned: there the
+    bound is the conditioning, |dW/dz| ~ 1/sqrt(2 e (z + 1/e)))."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    z = -np.concatenate([np.logspace(-300, -1, 120), np.linspace(0.1, 1 / np.e, 60)[1:-1],
+                         [1 / np.e - 1e-6, 1 / np.e - 1e-12]])
+    got = oracle.lambert_wm1(z)
+    ref = np.array([float(mp.lambertw(mp.mpf(v), -1)) for v in z])
+    far = np.abs(1 + ref) > 1e-2
+    assert np.abs(got[far] / ref[far] - 1).max() < 1e-14
+    assert np.abs(got[~far] - ref[~far]).max() < 1e-7
+    assert np.isnan(oracle.lambert_wm1([-0.5, 0.0, 0.1])).all()
+
+
+def test_xcw_exact_is_the_core_wing_crossing():
+    """x_cw solves exp(-x^2) = a/(sqrt(pi) x^2) and equals
+    sqrt(-W_{-1}(-a/sqrt(pi))) by scipy's Lambert W; it lies beyond the
+    inflexion of the core (x > 1) and grows as a falls."""
+    a = np.logspace(-8, -1, 120)
+    x = oracle.xcw(a)
+    assert np.abs(np.exp(-x ** 2) * np.sqrt(np.pi) * x ** 2 / a - 1).max() < 1e-12
+    ref = np.sqrt(-special.lambertw(-a / np.sqrt(np.pi), -1).real)
+    assert np.abs(x / ref - 1).max() < 1e-14
+    assert np.all(np.diff(x) < 0) and x.min() > 1.0
+    # at 1e4 K (a = 4.72e-4) the core turns into the wing near 3.25 Doppler widths
+    _, a4, _ = oracle.line_params(1e4)
+    assert abs(oracle.xcw([a4])[0] - 3.2544) < 1e-3
+
+
+def test_xcw_b25_within_its_stated_accuracy():
+    """The Appendix A.2 quartic in ln a stays within 0.6 % of the exact x_cw
+    over the Lyman-alpha temperature range (a from 1.5e-5 to 1e-2, about
+    T = 22 K to 1e7 K) and departs from it outside (it is a fit, not a
+    limit: 10 % at a = 1e-6)."""
+    a = np.logspace(np.log10(1.5e-5), -2, 500)
+    rel = np.abs(oracle.xcw(a, "b25") / oracle.xcw(a) - 1)
+    assert rel.max() < 6e-3, rel.max()
+    assert abs(oracle.xcw([1e-6], "b25")[0] / oracle.xcw([1e-6])[0] - 1) > 0.05
+
+
 # ------------------------------------------------------------ Philox
 def _kat_rows():
     rows = []
