@@ -407,13 +407,14 @@ def rays_box(a, device_fields=False):
 
 
 def save_fields(a):
-    """Numpy fields of the web box to a directory (for the counter runs,
-    which load them instead of generating them once per pass)."""
+    """The web box's fields (--fields gpu or cpu) as numpy files in a
+    directory, for the counter runs, which load them (--fields npy:DIR)
+    instead of generating them under the profiler once per pass."""
     import numpy as np
 
-    import workloads as W
     os.makedirs(a.save_fields, exist_ok=True)
-    for k, v in zip(("n_HI", "T", "vx", "vy", "vz"), W.web_fields(a.grid)):
+    for k, v in zip(("n_HI", "T", "vx", "vy", "vz"), web_fields(a)):
+        v = v.cpu().numpy() if hasattr(v, "cpu") else np.asarray(v)
         np.save(os.path.join(a.save_fields, "%s.npy" % k), v)
         print("saved %s" % k, flush=True)
 
