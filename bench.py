@@ -63,9 +63,13 @@ def parse():
     ap.add_argument("--plain-packets", type=int, default=20_000,
                     help="packets of the plain FP64 path on the same box (0: skip)")
     ap.add_argument("--shell", type=int, default=20, help="batches of 1e6 packets of the 128^3 shell (0: skip)")
+    ap.add_argument("--sphere", type=int, default=100_000,
+                    help="packets of the meshless tau0 = 1e5 sphere, one persistent call (0: skip)")
+    ap.add_argument("--sphere-only", type=int, default=0, help="print only the sphere record")
     ap.add_argument("--serving", type=int, default=300, help="measured requests of the serving stream (0: skip)")
     ap.add_argument("--serving-warmup", type=int, default=60)
-    ap.add_argument("--serving-rate", type=float, default=200.0)
+    ap.add_argument("--serving-rate", type=float, default=200.0,
+                    help="Poisson arrival rate (requests/s); one GPU sustains about 170/s")
     ap.add_argument("--serving-step-events", type=int, default=4096)
     ap.add_argument("--serving-only", type=int, default=0, help="print only the serving record")
     ap.add_argument("--rays", type=int, default=1, help="raytracing driver figures (0: skip)")
@@ -339,22 +343,69 @@ def shell_box(a):
 def serving(a):
     """Open-loop stream of shell-model requests through the continuous-batching
     server: p50/p99 latency (completion - arrival) and sustained throughput."""
+    import numpy as np
+
     import workloads as W
     from paper_2507_11603_amd import serve
     stream = W.request_stream(a.serving + a.serving_warmup, rate_hz=a.serving_rate)
     srv = serve.ShellServer(precision=a.precision, step_events=a.serving_step_events)
     try:
-        r = srv.run_stream(stream, warmup=a.serving_warmup)
+            r = srv.run_stream(stream, warmup=a.serving_warmup, progress_s=20.0)
     finally:
         srv.close()
     pk = sum(q["n_packets"] for q in stream)
     span = stream[-1]["t_arrival"] - stream[0]["t_arrival"]
     return {"requests": a.serving, "warmup_requests": a.serving_warmup, "rate_hz": a.serving_rate,
-            "p50_ms": r["p50_s"] * 1e3, "p99_ms": r["p99_s"] * 1e3,
+            "p50_ms": r["p50_s"] * 1e3, "p90_ms": float(np.percentile(r["latency_s"], 90)) * 1e3,
+            "p99_ms": r["p99_s"] * 1e3, "sustained_requests_per_s": len(stream) / r["wall_s"],
             "offered_packets_per_s": pk / span, "sustained_packets_per_s": pk / r["wall_s"],
             "sustained_scatterings_per_s": r["scatterings"] / r["wall_s"], "wall_s": r["wall_s"],
             "steps": r["steps"], "step_events": a.serving_step_events, "budget_deferrals": r["deferrals"],
             "graph_steps": True}
+
+
+def sphere_box(a):
+    """The meshless static sphere (tau0 = 1e5, T = 1e4 K, line-centre point
+    source, isotropic phase, no dust, no core skipping): a.sphere packets in
+    one persistent call.  No field memory: bound by VALU issue; the roofline
+    takes the VALU instructions per packet from the sphere's counter record."""
+    import torch
+
+    import workloads as W
+    from paper_2507_11603_amd import thor
+    wl = W.sphere(tau0=1e5, n_packets=a.sphere)
+    T = thor.Transport(0)
+    try:
+        T.load(wl["geom"])
+        kw = dict(precision="mixed", path="persistent", waves_per_cu=8)
+        run_call(T, wl, max(1, a.sphere // 10), 10**12, **kw)     # warm-up
+        T.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T.emit(wl["src"], a.sphere, 0)
+        _, st = T.transport(wl["opts"], **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        T.close()
+    split = kernel_split(st)
+    scat = st["n_res"] + st["n_dust"]
+    out = {"workload": "static sphere tau0 = 1e5, T = 1e4 K, x = 0 point source, isotropic, no dust",
+           "packets": st["emitted"], "seconds": dt, "scatterings_per_s": scat / dt,
+           "scatterings_per_packet": scat / max(st["emitted"], 1), "kernel_ms": st["kernel_ms"],
+           "upar_trials_per_scattering": st["upar_trials"] / max(st["n_res"], 1),
+           "longest_history": st["max_events"], "kernels": split}
+    roof = {"bound": "valu", "kernel": "k_persistent<float, false, false>", "achieved": None,
+            "peak": VALU_PEAK_IPS, "unit": "wave64 VALU instructions/s", "frac": None}
+    rec = counter_record("sphere")
+    if rec is not None:
+        kr = rec["kernels"].get("k_persistent", {})
+        if "valu_insts_per_batch" in kr and split["transport"]["ms"] > 0:
+            ips = kr["valu_insts_per_batch"] / max(rec["packets"], 1) * st["emitted"] / (split["transport"]["ms"] / 1e3)
+            roof.update(achieved=ips, frac=ips / VALU_PEAK_IPS, counters=rec["path"],
+                        valu_busy_pct=kr.get("valu_busy_pct"), valu_lane_util_pct=kr.get("valu_lane_util_pct"))
+    out["roofline"] = roof
+    return out
 
 
 def rays_box(a, device_fields=False):
@@ -442,6 +493,9 @@ def main():
     if a.serving_only:
         print(json.dumps({"serving": serving(a)}), flush=True)
         return
+    if a.sphere_only:
+        print(json.dumps({"sphere": sphere_box(a)}), flush=True)
+        return
     kw = dict(precision=a.precision, path="persistent", waves_per_cu=a.waves_per_cu, block=a.block or 256,
               visits_per_turn=a.turn_visits or 256, wide_lanes=a.wide_lanes or 8, park_lanes=a.park_lanes or 32,
               refill_64ths=a.refill_64ths or 16, presort=a.presort)
@@ -495,6 +549,8 @@ def main():
     del wl["geom"]
     if a.shell:
         out["shell"] = shell_box(a)
+    if a.sphere:
+        out["sphere"] = sphere_box(a)
     if a.serving:
         out["serving"] = serving(a)
     if a.rays:

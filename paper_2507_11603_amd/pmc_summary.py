@@ -66,7 +66,14 @@ def _durations(rows):
     return {int(r["Dispatch_Id"]): int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows}
 
 
-def _scaled_kib(d: str, counter: str, copy_mib: int, batches: int, rec: dict, key: str, scale_key: str):
+def _pick(ds, last_only):
+    """Dispatches of one kernel: all of them, or only the last (the timed call
+    of a command whose warm-up call comes first)."""
+    return [max(ds)] if (last_only and ds) else ds
+
+
+def _scaled_kib(d: str, counter: str, copy_mib: int, batches: int, rec: dict, key: str, scale_key: str,
+                last_only: bool = False):
     """Per-batch bytes of `counter` (KiB per dispatch) for each kernel, scaled
     by the calibration copy (the first dispatch)."""
     vals, names = _per_dispatch(_rows(d), counter)
@@ -76,7 +83,7 @@ def _scaled_kib(d: str, counter: str, copy_mib: int, batches: int, rec: dict, ke
     scale = copy_mib * 1024.0 / vals[first]
     rec[scale_key] = scale
     for kname in KERNELS:
-        ds = [k for k in vals if kname in names[k]]
+        ds = _pick([k for k in vals if kname in names[k]], last_only)
         if ds:
             kr = rec["kernels"].setdefault(kname, {})
             kr["launches"] = len(ds)
@@ -84,10 +91,14 @@ def _scaled_kib(d: str, counter: str, copy_mib: int, batches: int, rec: dict, ke
 
 
 def summarise(fetch_dir: str | None, write_dir: str, valu_dir: str | None, copy_mib: int, batches: int,
-              packets: int = 0, hits_dir: str | None = None, reads_dir: str | None = None) -> dict:
+              packets: int = 0, hits_dir: str | None = None, reads_dir: str | None = None,
+              last_only: bool = False) -> dict:
     rec = {"source_hash": source_hash(), "batches": batches, "packets": packets, "kernels": {}}
+    if last_only:
+        rec["dispatches"] = "last of each kernel"
     if fetch_dir:
-        _scaled_kib(fetch_dir, "FETCH_SIZE", copy_mib, batches, rec, "read_bytes_per_batch", "fetch_scale")
+        _scaled_kib(fetch_dir, "FETCH_SIZE", copy_mib, batches, rec, "read_bytes_per_batch", "fetch_scale",
+                    last_only)
     if reads_dir:
         # reads from the request counts by size
         rows = _rows(reads_dir)
@@ -103,12 +114,12 @@ def summarise(fetch_dir: str | None, write_dir: str, valu_dir: str | None, copy_
         rec["read_check"] = rbytes[first] / (copy_mib * 2.0 ** 20)     # 1.0: the copy reads what it copies
         key = "read_req_bytes_per_batch" if fetch_dir else "read_bytes_per_batch"
         for kname in KERNELS:
-            ds = [k for k in rbytes if kname in names[k]]
+            ds = _pick([k for k in rbytes if kname in names[k]], last_only)
             if ds:
                 kr = rec["kernels"].setdefault(kname, {})
                 kr["launches"] = len(ds)
                 kr[key] = sum(rbytes[k] for k in ds) / batches
-    _scaled_kib(write_dir, "WRITE_SIZE", copy_mib, batches, rec, "write_bytes_per_batch", "write_scale")
+    _scaled_kib(write_dir, "WRITE_SIZE", copy_mib, batches, rec, "write_bytes_per_batch", "write_scale", last_only)
     if hits_dir:
         rows = _rows(hits_dir)
         for kname in KERNELS:
@@ -125,6 +136,8 @@ def summarise(fetch_dir: str | None, write_dir: str, valu_dir: str | None, copy_
             busy, _ = _per_dispatch(kr_rows, "VALUBusy")
             util, _ = _per_dispatch(kr_rows, "VALUUtilization")
             insts, _ = _per_dispatch(kr_rows, "SQ_INSTS_VALU")
+            if last_only and insts:
+                insts = {max(insts): insts[max(insts)]}
             if not insts:
                 continue
             dur = _durations(kr_rows)
@@ -151,11 +164,13 @@ def main():
     ap.add_argument("--packets", type=int, default=0, help="packets per batch")
     ap.add_argument("--command", default="", help="the profiled command, stored with the record")
     ap.add_argument("--fields", default="", help="bench.py --fields of the profiled command")
+    ap.add_argument("--last-only", action="store_true",
+                    help="count only the last dispatch of each kernel (the timed call after a warm-up)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     if not (a.fetch or a.reads):
         ap.error("--fetch or --reads is required")
-    rec = summarise(a.fetch, a.write, a.valu, a.copy_mib, a.batches, a.packets, a.hits, a.reads)
+    rec = summarise(a.fetch, a.write, a.valu, a.copy_mib, a.batches, a.packets, a.hits, a.reads, a.last_only)
     rec["command"] = a.command
     rec["fields"] = a.fields
     with open(a.out, "w") as f:

@@ -10,6 +10,7 @@ libthor.so.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 import time
 
 import numpy as np
@@ -99,11 +100,14 @@ class ShellServer:
                         out[h] = s
         return [out[h] for h in hs]
 
-    def run_stream(self, stream, warmup: int = 0, time_scale: float = 1.0, max_wall_s: float = 600.0):
+    def run_stream(self, stream, warmup: int = 0, time_scale: float = 1.0, max_wall_s: float = 600.0,
+                   progress_s: float = 0.0):
         """Open-loop arrivals: request i becomes available at t_arrival[i] *
         time_scale after the start.  Returns per-request latencies (completion -
-        arrival) of the requests after `warmup`, deferral count and throughput."""
+        arrival) of the requests after `warmup`, deferral count and throughput.
+        progress_s > 0: a line on stderr every that many seconds."""
         t0 = time.monotonic()
+        t_said = 0.0
         arrivals = [r["t_arrival"] * time_scale for r in stream]
         nxt = 0
         waiting = []          # arrived, not yet admitted
@@ -115,6 +119,10 @@ class ShellServer:
             now = time.monotonic() - t0
             if now > max_wall_s:
                 raise TimeoutError("stream did not finish within %.0f s" % max_wall_s)
+            if progress_s > 0.0 and now - t_said >= progress_s:
+                t_said = now
+                print("[serve] %.0f s: %d of %d requests done, %d live, %d waiting"
+                      % (now, len(done_at), len(stream), len(live), len(waiting)), file=sys.stderr, flush=True)
             while nxt < len(stream) and arrivals[nxt] <= now:
                 waiting.append(nxt)
                 nxt += 1
