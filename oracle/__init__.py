@@ -23,7 +23,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 GEOMETRY = {"shell": 0, "sphere": 0, "slab": 1, "grid": 2}
 VELOCITY = {"none": 0, "const_radial": 1, "linear": 2}
 SOURCE = {"point": 0, "cell_n2": 1}
-SPECTRUM = {"delta": 0, "gauss": 1, "thermal": 2}
+SPECTRUM = {"delta": 0, "gauss": 1, "thermal": 2, "flat": 3}
+LINE = {"lya": 0, "mg2": 1, "mg2k": 2}
 PHASE = {"iso": 0, "dipole": 1, "core_wing": 2, "hg": 3}
 CORE_SKIP = {"off": 0, "fixed": 1, "adaptive": 2}
 OBS_AXIS = {"+x": 0, "+y": 1, "+z": 2, "-x": 3, "-y": 4, "-z": 5}
@@ -53,13 +54,13 @@ class Geometry(C.Structure):
                 ("sigma_d", C.c_double), ("tau_d", C.c_double),
                 ("albedo", C.c_double), ("g_hg", C.c_double),
                 ("hubble", C.c_double), ("hubble_ref", C.c_double * 3), ("hubble_step", C.c_double),
-                ("stop_dv", C.c_double)]
+                ("stop_dv", C.c_double), ("line", C.c_int32)]
 
 
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pos", C.c_double * 3), ("spectrum", C.c_int32),
                 ("dv0", C.c_double), ("sigma_v", C.c_double),
-                ("seed", C.c_uint32), ("request_id", C.c_uint32)]
+                ("seed", C.c_uint32), ("request_id", C.c_uint32), ("lines", C.c_int32)]
 
 
 class Opts(C.Structure):
@@ -96,6 +97,7 @@ def lib():
         L.or_voigt.argtypes = [d, d]
         L.or_dawson.restype = d
         L.or_dawson.argtypes = [d]
+        L.or_species_params.argtypes = [C.c_int, d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
         for fn in ("or_lambert_wm1", "or_xcw_exact", "or_xcw_b25"):
             getattr(L, fn).restype = d
             getattr(L, fn).argtypes = [d]
@@ -136,6 +138,14 @@ def lib():
 
 
 # ----------------------------------------------------------------- scalars
+def species_params(line: str, T: float):
+    """(v_th, a, sigma0) of the reference line of a species ("lya", or "mg2":
+    the Mg II k line, with the Mg mass)."""
+    v, a, s = C.c_double(), C.c_double(), C.c_double()
+    lib().or_species_params(LINE[line], float(T), C.byref(v), C.byref(a), C.byref(s))
+    return v.value, a.value, s.value
+
+
 def line_params(T: float):
     """(v_th [cm/s], a, sigma0 [cm^2]) at temperature T (Section 2.3.1)."""
     v, a, s = C.c_double(), C.c_double(), C.c_double()
@@ -248,6 +258,7 @@ def make_structs(geom: dict, src: dict, opts: dict):
     g.hubble_ref[:] = list(map(float, geom.get("hubble_ref", (0.0, 0.0, 0.0))))
     g.hubble_step = geom.get("hubble_step", 0.0)
     g.stop_dv = geom.get("stop_dv", 0.0)
+    g.line = LINE[geom.get("line", "lya")]
 
     s = Source()
     s.kind = SOURCE[src.get("kind", "point")]
@@ -257,6 +268,7 @@ def make_structs(geom: dict, src: dict, opts: dict):
     s.sigma_v = src.get("sigma_v", 0.0)
     s.seed = src.get("seed", 1)
     s.request_id = src.get("request_id", 0)
+    s.lines = int(src.get("lines", 0))
 
     o = Opts()
     o.phase = PHASE[opts.get("phase", "iso")]

@@ -60,17 +60,39 @@ static const double LYA_A21 = 6.265e8;           /* s^-1 */
 static const double LYA_F12 = 0.4162;
 static const double PI = 3.14159265358979323846;
 
+/* The Mg II h and k resonance doublet (Section 2.4: fine-structure        */
+/* splitting of one transition; both lines start from the same ground      */
+/* level): k = 3s 2S1/2 - 3p 2P3/2 at 2796.352 A, h = 3s 2S1/2 - 3p 2P1/2   */
+/* at 2803.531 A; Einstein A and oscillator strengths of Morton (2003).    */
+static const double MG2K_LAMBDA = 2796.352e-8, MG2K_A21 = 2.60e8, MG2K_F12 = 0.6155;
+static const double MG2H_LAMBDA = 2803.531e-8, MG2H_A21 = 2.57e8, MG2H_F12 = 0.3058;
+static const double M_MAGNESIUM = 24.305 * 1.66053906660e-24;   /* g */
+
 /* Section 2.3.1: x = (c/v_th)(nu - nu0)/nu0, v_th = sqrt(2 k T / m).      */
 /* Doppler width dnu_D = nu0 v_th / c = v_th / lambda0, damping parameter  */
 /* a = A21 / (4 pi dnu_D), line-centre cross-section                        */
 /* sigma0 = f12 sqrt(pi) e^2 / (m_e c dnu_D), sigma(x) = sigma0 H(a, x).    */
+static void transition_params(double lambda0, double a21, double f12, double mass, double T,
+                              double *v_th, double *a, double *sigma0)
+{
+    double vth = sqrt(2.0 * K_BOLTZ * T / mass);
+    double dnu_d = vth / lambda0;
+    *v_th = vth;
+    *a = a21 / (4.0 * PI * dnu_d);
+    *sigma0 = f12 * sqrt(PI) * E_CHARGE * E_CHARGE / (M_ELECTRON * C_LIGHT * dnu_d);
+}
+
 void or_line_params(double T, double *v_th, double *a, double *sigma0)
 {
-    double vth = sqrt(2.0 * K_BOLTZ * T / M_HYDROGEN);
-    double dnu_d = vth / LYA_LAMBDA;
-    *v_th = vth;
-    *a = LYA_A21 / (4.0 * PI * dnu_d);
-    *sigma0 = LYA_F12 * sqrt(PI) * E_CHARGE * E_CHARGE / (M_ELECTRON * C_LIGHT * dnu_d);
+    transition_params(LYA_LAMBDA, LYA_A21, LYA_F12, M_HYDROGEN, T, v_th, a, sigma0);
+}
+
+void or_species_params(int line, double T, double *v_th, double *a, double *sigma0)
+{
+    if (line == OR_LINE_MG2 || line == OR_LINE_MG2K)
+        transition_params(MG2K_LAMBDA, MG2K_A21, MG2K_F12, M_MAGNESIUM, T, v_th, a, sigma0);
+    else
+        or_line_params(T, v_th, a, sigma0);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -233,7 +255,7 @@ void or_draw(uint32_t seed, uint32_t request_id, uint32_t slot, uint32_t event, 
 }
 
 /* RNG slot map.  Event 0 is the emission, event e >= 1 the e-th interaction. */
-enum { SLOT_E_DIR = 0, SLOT_E_GAUSS = 1, SLOT_E_CELL = 2, SLOT_E_OFFS = 3, SLOT_E_TAU = 4 };
+enum { SLOT_E_DIR = 0, SLOT_E_GAUSS = 1, SLOT_E_CELL = 2, SLOT_E_OFFS = 3, SLOT_E_TAU = 4, SLOT_E_LINE = 5 };
 enum { SLOT_TYPE = 0, SLOT_UPERP = 1, SLOT_MU = 2, SLOT_TAU = 3, SLOT_UPAR = 4 };
 
 /* ---------------------------------------------------------------------- */
@@ -437,6 +459,15 @@ typedef struct {
     /* homogeneous meshless medium */
     double n, T, vth, a, sig0, k0, kd, sigd;
     double xcrit;
+    /* resonant lines (Section 2.4): nl transitions; line 0 is the reference
+     * whose per-cell v_th, a and k0 the medium carries.  Line j sits at lab
+     * offset lc[j] (cm/s) from line 0's centre; its dimensionless frequency
+     * is x_j = lrho[j] (x - lc[j]/v_th) (lrho = lambda_j/lambda_0, the ratio
+     * of the Doppler widths), its damping parameter lam[j] a and its
+     * line-centre opacity lk[j] k0; lw[j]: emission probability (oscillator
+     * strengths, Section 5.3) */
+    int nl;
+    double lc[2], lrho[2], lam[2], lk[2], lw[2];
     /* grid */
     double dx[3];
     int dims[3];
@@ -458,6 +489,28 @@ typedef struct {
 
 static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 
+/* Resonant opacity at gas-frame offset x (units of the reference line's    */
+/* v_th): a doublet sums its transitions (Section 2.4).  *k_first: line 0's */
+/* share.                                                                    */
+static double line_opacity(const model_t *m, double k0, double a, double vth, double x, double *k_first)
+{
+    double k = k0 * or_voigt(a, x);
+    if (k_first)
+        *k_first = k;
+    for (int j = 1; j < m->nl; ++j)
+        k += k0 * m->lk[j] * or_voigt(a * m->lam[j], m->lrho[j] * (x - m->lc[j] / vth));
+    return k;
+}
+
+/* Lab-frame offset of a photon leaving line j at offset x_j from its centre */
+/* (in that line's Doppler units) with gas velocity component vk.            */
+static double line_dv(const model_t *m, int j, double xj, double vth, double vk)
+{
+    if (j == 0)
+        return xj * vth + vk;
+    return (xj / m->lrho[j]) * vth + m->lc[j] + vk;
+}
+
 static void grid_fields(const model_t *m, const int c[3], cellf_t *f)
 {
     const or_geometry *g = m->g;
@@ -469,7 +522,7 @@ static void grid_fields(const model_t *m, const int c[3], cellf_t *f)
     f->v[2] = (double)g->f_vz[idx];
     if (n > 0.0) {
         double sig0;
-        or_line_params((double)g->f_T[idx], &f->vth, &f->a, &sig0);
+        or_species_params(g->line, (double)g->f_T[idx], &f->vth, &f->a, &sig0);
         f->k0 = n * sig0;
         f->kd = g->sigma_d * n;
     } else {
@@ -729,11 +782,11 @@ static void peel(const model_t *m, const loc_t *L0, int o, double weight, double
                 double ds = t / n;
                 for (int j = 0; j < n; ++j) {
                     double x = (u0 - m->g->hubble * ((j + 0.5) * ds)) / f.vth;
-                    tau += (f.k0 * or_voigt(f.a, x) + f.kd) * ds;
+                    tau += (line_opacity(m, f.k0, f.a, f.vth, x, NULL) + f.kd) * ds;
                 }
             } else {
                 double x = (dv_peel - dot3(f.v, k)) / f.vth;
-                double kt = f.k0 * or_voigt(f.a, x) + f.kd;
+                double kt = line_opacity(m, f.k0, f.a, f.vth, x, NULL) + f.kd;
                 if (isinf(t)) { cut = 1; break; }
                 tau += kt * t;
             }
@@ -842,16 +895,29 @@ static void emit_packet(const model_t *m, const or_source *src, uint64_t id, emi
     double z = 0.0;
     if (src->spectrum != OR_SPEC_DELTA) {
         draw2(seed, req, SLOT_E_GAUSS, 0, id, &ua, &ub);
-        z = sqrt(-2.0 * log(1.0 - ua)) * cos(2.0 * PI * ub);
+        if (src->spectrum != OR_SPEC_FLAT)
+            z = sqrt(-2.0 * log(1.0 - ua)) * cos(2.0 * PI * ub);
+    }
+    /* a doublet source emits in line j with probability lw[j] (the ratio of  */
+    /* the oscillator strengths), at that line's centre offset                */
+    double lcen = 0.0;
+    if (src->lines && m->nl > 1) {
+        double ul, unused;
+        draw2(seed, req, SLOT_E_LINE, 0, id, &ul, &unused);
+        if (ul >= m->lw[0])
+            lcen = m->lc[1];
     }
     if (src->spectrum == OR_SPEC_THERMAL) {
         /* gas-frame Doppler profile of the emitting cell, then the lab frame */
-        dv_loc = src->dv0 + f0.vth * z / sqrt(2.0);
+        dv_loc = src->dv0 + f0.vth * z / sqrt(2.0) + lcen;
         dv = dv_loc + dot3(v0, k);
     } else if (src->spectrum == OR_SPEC_GAUSS) {
-        dv = src->dv0 + src->sigma_v * z;
+        dv = src->dv0 + src->sigma_v * z + lcen;
+    } else if (src->spectrum == OR_SPEC_FLAT) {
+        /* flat continuum over dv0 +- sigma_v (Section 4's doublet test) */
+        dv = src->dv0 + src->sigma_v * (2.0 * ua - 1.0) + lcen;
     } else {
-        dv = src->dv0;
+        dv = src->dv0 + lcen;
     }
     e->L = L;
     e->f0 = f0;
@@ -969,7 +1035,7 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
                 double ds = t / n;
                 for (int j = 0; j < n; ++j) {
                     double x = (u0 - g->hubble * ((j + 0.5) * ds)) / f.vth;
-                    double ktj = f.k0 * or_voigt(f.a, x) + f.kd;
+                    double ktj = line_opacity(m, f.k0, f.a, f.vth, x, NULL) + f.kd;
                     if (tau_acc + ktj * ds >= tau_target) {
                         s = j * ds + (tau_target - tau_acc) / ktj;
                         kt = ktj;
@@ -981,7 +1047,7 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
         } else {
             if (f.k0 > 0.0 || f.kd > 0.0) {
                 double x = (dv - dot3(f.v, k)) / f.vth;
-                kh = f.k0 * or_voigt(f.a, x);
+                kh = line_opacity(m, f.k0, f.a, f.vth, x, NULL);
                 kt = kh + f.kd;
             }
             if (kt > 0.0 && tau_acc + kt * t >= tau_target)
@@ -1027,10 +1093,26 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
                 ++n_dust;
                 st->n_dust++;
             } else {
-                /* Resonant scattering (Sections 2.3.1, 3.4, 3.4.2). */
+                /* Resonant scattering (Sections 2.3.1, 3.4, 3.4.2).  A doublet */
+                /* scatters in line j with probability k_j / (k_0 + k_1) at the */
+                /* site, from the same uniform rescaled to the resonant share,  */
+                /* and re-emits in that line (both decay to the one ground      */
+                /* level); the fine-structure line 2P1/2 -> 2S1/2 re-emits       */
+                /* isotropically (Section 2.4).                                   */
                 double x = (dv - dot3(f.v, k)) / f.vth;
+                int j = 0;
+                if (m->nl > 1) {
+                    double k_first;
+                    double kres = line_opacity(m, f.k0, f.a, f.vth, x, &k_first);
+                    double u_line = (utype * kt - f.kd) / (kt - f.kd);
+                    if (u_line * kres >= k_first)
+                        j = 1;
+                }
+                double xj = j == 0 ? x : m->lrho[j] * (x - m->lc[j] / f.vth);
+                double aj = j == 0 ? f.a : f.a * m->lam[j];
+                int phj = j == 0 ? op->phase : OR_PHASE_ISO;
                 scatter_t sc;
-                resonant_scatter(x, f.a, k, m->xcrit, op->phase, seed, req, event, id, &sc);
+                resonant_scatter(xj, aj, k, m->xcrit, phj, seed, req, event, id, &sc);
                 st->upar_trials += sc.trials;
                 for (int i = 0; i < 3; ++i) kout[i] = sc.kout[i];
                 for (int o = 0; o < op->n_obs; ++o) {
@@ -1038,9 +1120,9 @@ static void transport_one(const model_t *m, const or_source *src, uint64_t id, d
                     obs_dir(op->obs_axis[o], ko);
                     double c = w * phase_value(sc.phase, dot3(k, ko), 0.0) / (2.0 * PI);
                     double xo = sc.x_atom + dot3(sc.u, ko);
-                    peel(m, &L, o, c, xo * f.vth + dot3(f.v, ko), cube, st);
+                    peel(m, &L, o, c, line_dv(m, j, xo, f.vth, dot3(f.v, ko)), cube, st);
                 }
-                dv = sc.x_out * f.vth + dot3(f.v, kout);
+                dv = line_dv(m, j, sc.x_out, f.vth, dot3(f.v, kout));
                 ++n_res;
                 st->n_res++;
             }
@@ -1094,6 +1176,20 @@ static int model_init(model_t *m, const or_geometry *g, const or_source *s, cons
     memset(m, 0, sizeof *m);
     m->g = g;
     m->o = o;
+    m->nl = 1;
+    m->lrho[0] = 1.0; m->lam[0] = 1.0; m->lk[0] = 1.0; m->lw[0] = 1.0;
+    if (g->line == OR_LINE_MG2) {
+        /* line 0 = k (reference), line 1 = h, redward by c (1 - lambda_k/lambda_h) */
+        m->nl = 2;
+        m->lc[1] = C_LIGHT * (MG2K_LAMBDA / MG2H_LAMBDA - 1.0);
+        m->lrho[1] = MG2H_LAMBDA / MG2K_LAMBDA;
+        m->lam[1] = (MG2H_A21 * MG2H_LAMBDA) / (MG2K_A21 * MG2K_LAMBDA);
+        m->lk[1] = (MG2H_F12 * MG2H_LAMBDA) / (MG2K_F12 * MG2K_LAMBDA);
+        m->lw[0] = MG2K_F12 / (MG2K_F12 + MG2H_F12);
+        m->lw[1] = 1.0 - m->lw[0];
+    } else if (g->line != OR_LINE_LYA && g->line != OR_LINE_MG2K) {
+        return -1;
+    }
     if (g->kind == OR_GRID) {
         m->dims[0] = g->nx; m->dims[1] = g->ny; m->dims[2] = g->nz;
         for (int ax = 0; ax < 3; ++ax)
@@ -1117,7 +1213,7 @@ static int model_init(model_t *m, const or_geometry *g, const or_source *s, cons
             return -6;
     } else {
         double L = g->r_outer - g->r_inner;
-        or_line_params(g->T, &m->vth, &m->a, &m->sig0);
+        or_species_params(g->line, g->T, &m->vth, &m->a, &m->sig0);
         m->n = g->tau0 > 0.0 ? g->tau0 / (m->sig0 * L) : g->n_HI;
         m->k0 = m->n * m->sig0;
         m->sigd = g->tau_d > 0.0 ? g->tau_d / (m->n * L) : g->sigma_d;

@@ -24,7 +24,11 @@ enum { OR_SHELL = 0, OR_SLAB = 1, OR_GRID = 2 };
 enum { OR_VEL_NONE = 0, OR_VEL_CONST_RADIAL = 1, OR_VEL_LINEAR = 2 };
 /* source kinds / spectra */
 enum { OR_SRC_POINT = 0, OR_SRC_CELL_N2 = 1 };
-enum { OR_SPEC_DELTA = 0, OR_SPEC_GAUSS = 1, OR_SPEC_THERMAL = 2 };
+enum { OR_SPEC_DELTA = 0, OR_SPEC_GAUSS = 1, OR_SPEC_THERMAL = 2, OR_SPEC_FLAT = 3 };
+/* resonant line of the medium: Lyman alpha, the Mg II h and k doublet, or
+ * the Mg II k line alone (Mg II: frequencies relative to the k line,
+ * densities of Mg II) */
+enum { OR_LINE_LYA = 0, OR_LINE_MG2 = 1, OR_LINE_MG2K = 2 };
 /* phase functions, core skipping */
 enum { OR_PHASE_ISO = 0, OR_PHASE_DIPOLE = 1, OR_PHASE_CORE_WING = 2 };
 enum { OR_CS_OFF = 0, OR_CS_FIXED = 1, OR_CS_ADAPTIVE = 2 };
@@ -55,14 +59,17 @@ typedef struct {
      * Hubble shift is at most hubble_step v_th (0 = 0.1), each evaluated at its
      * midpoint; stop_dv > 0: redshift stop (cm/s) */
     double hubble, hubble_ref[3], hubble_step, stop_dv;
+    int32_t line;              /* OR_LINE_*: the absorbing species and its transitions */
 } or_geometry;
 
 typedef struct {
     int32_t kind;
     double pos[3];
     int32_t spectrum;
-    double dv0, sigma_v;       /* cm/s */
+    double dv0, sigma_v;       /* cm/s; FLAT: dv0 +- sigma_v */
     uint32_t seed, request_id;
+    int32_t lines;             /* doublet media: 1 = emit in either line with probability
+                                  in the ratio of the oscillator strengths, 0 = at dv0 */
 } or_source;
 
 typedef struct {
@@ -98,6 +105,8 @@ typedef struct {
 
 /* line constants at temperature T: thermal speed (cm/s), Voigt a, sigma_0 (cm^2) */
 void or_line_params(double T, double *v_th, double *a, double *sigma0);
+/* the same for the reference line of a species (OR_LINE_*) */
+void or_species_params(int line, double T, double *v_th, double *a, double *sigma0);
 /* Voigt-Hjerting function H(a,x) = Re w(x + i a) */
 double or_voigt(double a, double x);
 /* Dawson's integral (long-double power series), exported for its own pin */

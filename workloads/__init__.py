@@ -258,6 +258,27 @@ def outflow_sphere(N_HI: float = 2e18, T: float = 2e4, v_max_kms: float = 200.0,
     return dict(name="outflow_sphere", geom=geom, src=src, opts=opts, n_packets=n_packets)
 
 
+def mg2_sphere(log_N: float = 14.5, T: float = 1e4, v_max_kms: float = 500.0, n_packets: int = 10000,
+               seed: int = 1, continuum_kms=(-1500.0, 1000.0), step_f: float = 0.05, line: str = "mg2",
+               spectrum: str = "flat", dv0_kms: float = 0.0, nb: int = 250):
+    """Section 4's doublet test: a homogeneous sphere of Mg II column 10^log_N
+    (centre to edge) at T with the linear outflow v = v_max r/R, a central
+    source of a flat continuum over `continuum_kms` (relative to the k line;
+    `spectrum="delta"` emits at dv0 instead), dipole phase in the k line
+    (isotropic in h); escape spectrum over the continuum's range."""
+    R = KPC
+    lo, hi = continuum_kms
+    geom = dict(kind="sphere", r_inner=0.0, r_outer=R, n_HI=10.0 ** log_N / R, T=T, line=line,
+                v_profile="linear" if v_max_kms else "none", v_max=v_max_kms * KMS, step_f=step_f)
+    if spectrum == "flat":
+        src = dict(kind="point", pos=(0.0, 0.0, 0.0), spectrum="flat", dv0=0.5 * (lo + hi) * KMS,
+                   sigma_v=0.5 * (hi - lo) * KMS, seed=seed)
+    else:
+        src = dict(kind="point", pos=(0.0, 0.0, 0.0), spectrum="delta", dv0=dv0_kms * KMS, seed=seed)
+    opts = dict(phase="dipole", spectrum=dict(nb=nb, lo=lo * KMS, hi=hi * KMS))
+    return dict(name="mg2_sphere", geom=geom, src=src, opts=opts, n_packets=n_packets)
+
+
 def hubble_box(n_grid: int = 32, box_mpc: float = 30.0, n_HI: float = 4.8e-11, T: float = 1e4,
                hubble_kms_mpc: float = 100.0, stop_kms: float = 1233.0, n_packets: int = 1000, seed: int = 1,
                observers=("+z",), cube_npix: int = 1, cube_v_kms: float = 0.01):
