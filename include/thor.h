@@ -104,16 +104,30 @@ typedef struct {
      * cell faces) escapes (beyond that shift the IGM is taken as transparent),
      * counted in thor_stats.redshifted and not as a hand-off. */
     double hubble, hubble_ref[3], hubble_step, stop_dv;
+    /* Resonant line (THOR_LINE_*).  LYA: Lyman alpha of H I.  MG2: the Mg II
+     * h and k doublet (Section 2.4: the two lines' cross-sections add; a
+     * resonant scattering picks the line by its share of the opacity at the
+     * site and re-emits in it, h isotropically), densities of Mg II, every
+     * frequency offset relative to the k line (2796.352 A; h lies 767.6 km/s
+     * to the red).  MG2K: the k line alone.  MG2 and MG2K need a meshless
+     * medium (THOR_E_UNSUPPORTED on a grid); their packets are not handed to
+     * the tail kernel. */
+    int32_t line;
 } thor_geometry;
+
+typedef enum { THOR_LINE_LYA = 0, THOR_LINE_MG2 = 1, THOR_LINE_MG2K = 2 } thor_line;
 
 /* ---------------------------------------------------------------- sources */
 typedef enum { THOR_SRC_POINT = 0, THOR_SRC_CELL_N2 = 1 } thor_source_kind;
-typedef enum { THOR_SPEC_DELTA = 0, THOR_SPEC_GAUSS = 1, THOR_SPEC_THERMAL = 2 } thor_spectrum_kind;
+typedef enum { THOR_SPEC_DELTA = 0, THOR_SPEC_GAUSS = 1, THOR_SPEC_THERMAL = 2, THOR_SPEC_FLAT = 3 } thor_spectrum_kind;
 
 /* Generator (Section 3.4 "Emission"): isotropic directions; frequency
  * DELTA dv0, GAUSS dv0 + sigma_v N(0,1) (source frame = lab frame), or
  * THERMAL: the gas-frame Doppler profile of the emitting cell,
- * dv0 + v_th N(0,1)/sqrt(2), shifted to the lab frame by v.k.
+ * dv0 + v_th N(0,1)/sqrt(2), shifted to the lab frame by v.k; FLAT: a flat
+ * continuum, dv0 + sigma_v U(-1, 1).  lines = 1 in a doublet medium: each
+ * packet is emitted in line 1 with probability f_1 / (f_0 + f_1) (the
+ * oscillator strengths), its frequency shifted to that line's centre.
  * POINT: emitted at pos.  CELL_N2 (grid only): cell drawn with probability
  * proportional to n_HI^2, uniform position inside the cell.
  * Packet ids and (seed, request_id) key the Philox4x32-10 stream. */
@@ -123,6 +137,7 @@ typedef struct {
     int32_t spectrum;
     double dv0, sigma_v;
     uint32_t seed, request_id;
+    int32_t lines;
 } thor_source;
 
 /* ---------------------------------------------------------------- transport */

@@ -31,6 +31,12 @@ constexpr double kA21 = 6.265e8;
 constexpr double kF12 = 0.4162;
 // Section 2.3.1: v_th = sqrt(2kT/m); Doppler width dnu_D = v_th / lambda0,
 // a = A21 / (4 pi dnu_D), sigma0 = f12 sqrt(pi) e^2 / (m_e c dnu_D).
+// Mg II h and k (a fine-structure doublet from one ground level): k = 3s
+// 2S1/2 - 3p 2P3/2 at 2796.352 A, h = 3s 2S1/2 - 3p 2P1/2 at 2803.531 A,
+// Einstein A and oscillator strengths of Morton (2003); Mg mass 24.305 u.
+constexpr double kMassMg = 24.305 * 1.66053906660e-24;
+constexpr double kMgKLambda = 2796.352e-8, kMgKA21 = 2.60e8, kMgKF12 = 0.6155;
+constexpr double kMgHLambda = 2803.531e-8, kMgHA21 = 2.57e8, kMgHF12 = 0.3058;
 constexpr double kVth2PerT = 2.0 * kBoltzmann / kMassH;
 constexpr double kDampTimesVth = kA21 * kLambda0 / (4.0 * kPi);
 constexpr double kSigma0TimesVth = kF12 * kSqrtPi * kCharge * kCharge * kLambda0 / (kMassE * kClight);
@@ -87,7 +93,7 @@ template <> __device__ __forceinline__ Uni2<float> draw<float>(const Key& k, uin
 }
 
 // Slot map: event 0 = emission, event e >= 1 = e-th interaction.
-enum : uint32_t { kSlotEDir = 0, kSlotEGauss = 1, kSlotECell = 2, kSlotEOffs = 3, kSlotETau = 4 };
+enum : uint32_t { kSlotEDir = 0, kSlotEGauss = 1, kSlotECell = 2, kSlotEOffs = 3, kSlotETau = 4, kSlotELine = 5 };
 enum : uint32_t { kSlotType = 0, kSlotUperp = 1, kSlotMu = 2, kSlotTau = 3, kSlotUpar = 4 };
 
 // Division: IEEE in FP64; reciprocal-based (about 1 ulp) in the FP32 path.
@@ -618,7 +624,8 @@ template <class R> __device__ __forceinline__ void onb(const R n[3], R e1[3], R 
 enum : int { kGeomShell = 0, kGeomSlab = 1, kGeomGrid = 2 };
 enum : int { kVelNone = 0, kVelConstRadial = 1, kVelLinear = 2 };
 enum : int { kSrcPoint = 0, kSrcCellN2 = 1 };
-enum : int { kSpecDelta = 0, kSpecGauss = 1, kSpecThermal = 2 };
+enum : int { kLineLya = 0, kLineMg2 = 1, kLineMg2K = 2 };
+enum : int { kSpecDelta = 0, kSpecGauss = 1, kSpecThermal = 2, kSpecFlat = 3 };
 enum : int { kFateNone = 0, kFateEscaped = 1, kFateAbsorbed = 2, kFateCapped = 3, kFateRedshifted = 4 };
 enum : int { kRegCavity = 0, kRegGas = 1, kRegOut = 2 };
 
@@ -666,6 +673,13 @@ struct ModelDev {
     int spec_rep;               // copies of it (workgroup b adds into copy b mod spec_rep), folded after the call
     double spec_lo, spec_w, spec_scale;
     unsigned long long* done;   // packets finished (escaped, absorbed, capped)
+    // resonant lines (Section 2.4): nl = 2 for a doublet.  Line 1 sits at lab
+    // offset lc1 (cm/s) from line 0's centre; its dimensionless frequency is
+    // lrho1 (x - lc1 / v_th), its damping parameter lam1 a, its line-centre
+    // opacity lk1 k0; a doublet source (lines = 1) emits in line 0 with
+    // probability lw0.
+    int nl, lines;
+    double lc1, lrho1, lam1, lk1, lw0;
 };
 
 struct BatchDev {

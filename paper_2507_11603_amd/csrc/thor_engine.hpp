@@ -51,6 +51,16 @@ template <class R> __device__ __forceinline__ R dot3(const R a[3], const R b[3])
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// Opacity of a meshless doublet's second line (Section 2.4: a doublet's
+// cross-section is the sum of its lines') at line 0's gas-frame offset x.
+template <class R>
+__device__ __forceinline__ double second_line_k(const ModelDev& m, double k0, R a, R vth, R x, const float* dtab) {
+    const R x1 = R(m.lrho1) * (x - R(m.lc1) / vth);
+    const R a1 = a * R(m.lam1);
+    if constexpr (sizeof(R) == 4) return (k0 * m.lk1) * double(voigt32(a1, x1, dtab));
+    else return (k0 * m.lk1) * double(voigt<R>(a1, x1));
+}
+
 // sin and cos of 2 pi u
 template <class R> __device__ __forceinline__ R sincos2pi(R u, R* c);
 template <> __device__ __forceinline__ double sincos2pi<double>(double u, double* c) {
@@ -494,7 +504,9 @@ __device__ void peel(const GridDev& g, const ModelDev& m, const OutDev& o, const
             cnt.peel_visits++;
             if (f.k0 > 0.0 || f.kd > 0.0) {
                 const R x = fdiv(dv_peel - dot3<R>(f.v, k), f.vth);
-                const double kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+                double kh = f.k0 * double(voigt<R>(f.a, x));
+                if (m.nl > 1) kh += second_line_k<R>(m, f.k0, f.a, f.vth, x, c_dawson32);
+                const double kt = kh + f.kd;
                 if (isinf(t)) { cut = true; break; }
                 tau += kt * t;
             } else if (isinf(t)) {
@@ -737,21 +749,30 @@ __device__ void emit(const GridDev& g, const ModelDev& m, const OutDev& o, uint6
         int nr, cm;
         (void)meshless_query<R>(m, L.p, L.region, pk.k, f0, &nr, &cm);
     }
-    R z = R(0);
+    R z = R(0), uflat = R(0);
     if (m.spectrum != kSpecDelta) {
         const Uni2<R> d = draw<R>(key, kSlotEGauss, 0);
-        R cs;
-        (void)sincos2pi<R>(d.b, &cs);
-        z = M<R>::sqrt(R(-2) * M<R>::log(R(1) - d.a)) * cs;
+        if (m.spectrum == kSpecFlat) {
+            uflat = d.a;
+        } else {
+            R cs;
+            (void)sincos2pi<R>(d.b, &cs);
+            z = M<R>::sqrt(R(-2) * M<R>::log(R(1) - d.a)) * cs;
+        }
     }
+    // a doublet source emits in line 1 with probability 1 - lw0, at its centre
+    R lcen = R(0);
+    if (m.lines && m.nl > 1 && draw<double>(key, kSlotELine, 0).a >= m.lw0) lcen = R(m.lc1);
     R dv_loc = R(0);
     if (m.spectrum == kSpecThermal) {
-        dv_loc = R(m.dv0) + f0.vth * z / R(1.4142135623730951);
+        dv_loc = R(m.dv0) + f0.vth * z / R(1.4142135623730951) + lcen;
         pk.dv = dv_loc + dot3<R>(f0.v, pk.k);
     } else if (m.spectrum == kSpecGauss) {
-        pk.dv = R(m.dv0) + R(m.sigma_v) * z;
+        pk.dv = R(m.dv0) + R(m.sigma_v) * z + lcen;
+    } else if (m.spectrum == kSpecFlat) {
+        pk.dv = R(m.dv0) + R(m.sigma_v) * (R(2) * uflat - R(1)) + lcen;   // flat continuum dv0 +- sigma_v
     } else {
-        pk.dv = R(m.dv0);
+        pk.dv = R(m.dv0) + lcen;
     }
     cnt.emitted++;
     if (L.region != kRegOut) {
@@ -844,9 +865,26 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
         pk.n_dust++;
         cnt.n_dust++;
     } else {
-        const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
+        R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
+        R aj = f.a;
+        int line = 0;
+        if constexpr (!GRID && !PRE) {
+            if (m.nl > 1) {
+                // a doublet scatters in line 1 with probability k_1 / (k_0 + k_1)
+                // at the site (the same uniform rescaled to the resonant share)
+                // and re-emits in that line; h (2P1/2) re-emits isotropically
+                const double k_first = f.k0 * double(voigt<R>(f.a, x));
+                const double kres = k_first + second_line_k<R>(m, f.k0, f.a, f.vth, x, c_dawson32);
+                const double u_line = (dtyp.a * kt - f.kd) / (kt - f.kd);
+                if (u_line * kres >= k_first) {
+                    line = 1;
+                    x = R(m.lrho1) * (x - R(m.lc1) / f.vth);
+                    aj = f.a * R(m.lam1);
+                }
+            }
+        }
         uint32_t trials = 0;
-        const R upar = upar_sample<R>(x, f.a, key, pk.event, &trials, PRE ? pre->up : nullptr);
+        const R upar = upar_sample<R>(x, aj, key, pk.event, &trials, PRE ? pre->up : nullptr);
         cnt.upar_trials += trials;
         R rho2, cps, sps;
         if constexpr (PRE) {
@@ -864,7 +902,7 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
 #pragma unroll
         for (int i = 0; i < 3; ++i) u[i] = upar * pk.k[i] + up1 * e1[i] + up2 * e2[i];
         const R x_atom = x - upar;
-        int ph = o.phase;
+        int ph = line ? int(kPhaseIso) : o.phase;
         if (ph == kPhaseCoreWing && fabs(x_atom) >= R(0.2)) ph = kPhaseDipole;
         R mu, s_, cphi, sphi;
         if constexpr (PRE) {
@@ -905,11 +943,14 @@ __device__ __forceinline__ int interact(const GridDev& g, const ModelDev& m, con
                 const R ko[3] = {R(kd[0]), R(kd[1]), R(kd[2])};
                 const double c = double(phase_value<R>(ph, dot3<R>(pk.k, ko), R(0))) / (2.0 * kPi);
                 const R xo = x_atom + dot3<R>(u, ko);
-                peel<R, GRID>(g, m, o, L, f, ob, c, xo * f.vth + dot3<R>(f.v, ko), cnt);
+                const R dvo = line ? (xo / R(m.lrho1)) * f.vth + R(m.lc1) + dot3<R>(f.v, ko)
+                                   : xo * f.vth + dot3<R>(f.v, ko);
+                peel<R, GRID>(g, m, o, L, f, ob, c, dvo, cnt);
             }
         }
         const R x_out = x_atom + dot3<R>(u, kout);
-        pk.dv = x_out * f.vth + dot3<R>(f.v, kout);
+        if (line) pk.dv = (x_out / R(m.lrho1)) * f.vth + R(m.lc1) + dot3<R>(f.v, kout);
+        else pk.dv = x_out * f.vth + dot3<R>(f.v, kout);
         pk.n_res++;
         cnt.n_res++;
     }
@@ -1030,8 +1071,21 @@ __device__ int advance(const GridDev& g, const ModelDev& m, const OutDev& o, Pkt
             } else {
                 if (f.k0 > 0.0 || f.kd > 0.0) {
                     const R x = fdiv(pk.dv - dot3<R>(f.v, pk.k), f.vth);
-                    if constexpr (sizeof(R) == 4) kt = f.k0 * double(voigt32(f.a, x, dtab)) + f.kd;
-                    else kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+                    if constexpr (!GRID) {
+                        if (m.nl > 1) {
+                            // doublet: both lines' opacities (meshless media)
+                            double kh;
+                            if constexpr (sizeof(R) == 4) kh = f.k0 * double(voigt32(f.a, x, dtab));
+                            else kh = f.k0 * double(voigt<R>(f.a, x));
+                            kt = (kh + second_line_k<R>(m, f.k0, f.a, f.vth, x, dtab)) + f.kd;
+                        } else {
+                            if constexpr (sizeof(R) == 4) kt = f.k0 * double(voigt32(f.a, x, dtab)) + f.kd;
+                            else kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+                        }
+                    } else {
+                        if constexpr (sizeof(R) == 4) kt = f.k0 * double(voigt32(f.a, x, dtab)) + f.kd;
+                        else kt = f.k0 * double(voigt<R>(f.a, x)) + f.kd;
+                    }
                 }
                 if (kt > 0.0 && pk.tau_a + kt * t >= pk.tau_t) s = div_tau<R>(pk.tau_t - pk.tau_a, kt);
             }

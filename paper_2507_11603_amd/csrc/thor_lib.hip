@@ -1022,6 +1022,19 @@ void line_params(double T, double* vth, double* a, double* sig0) {
     *sig0 = kSigma0TimesVth / v;
 }
 
+// Line 0 of the medium's species at temperature T (v_th, a, sigma0).
+void species_params(int line, double T, double* vth, double* a, double* sig0) {
+    if (line == THOR_LINE_LYA) {
+        line_params(T, vth, a, sig0);
+        return;
+    }
+    const double v = std::sqrt(2.0 * kBoltzmann * T / kMassMg);
+    const double dnu = v / kMgKLambda;
+    *vth = v;
+    *a = kMgKA21 / (4.0 * kPi * dnu);
+    *sig0 = kMgKF12 * kSqrtPi * kCharge * kCharge / (kMassE * kClight * dnu);
+}
+
 // Model constants of a batch (meshless medium constants, source, outputs).
 thor_status make_model(thor_ctx* ctx, const thor_source& s, const thor_transport_opts& o, ModelDev& m) {
     const thor_geometry& g = ctx->geom;
@@ -1037,10 +1050,20 @@ thor_status make_model(thor_ctx* ctx, const thor_source& s, const thor_transport
     m.sigma_v = s.sigma_v;
     m.seed = s.seed;
     m.req = s.request_id;
+    m.nl = 1;
+    m.lines = s.lines;
+    if (g.line == THOR_LINE_MG2) {
+        m.nl = 2;
+        m.lc1 = kClight * (kMgKLambda / kMgHLambda - 1.0);
+        m.lrho1 = kMgHLambda / kMgKLambda;
+        m.lam1 = (kMgHA21 * kMgHLambda) / (kMgKA21 * kMgKLambda);
+        m.lk1 = (kMgHF12 * kMgHLambda) / (kMgKF12 * kMgKLambda);
+        m.lw0 = kMgKF12 / (kMgKF12 + kMgHF12);
+    }
     if (g.kind != THOR_GEOM_GRID) {
         const double L = g.r_outer - g.r_inner;
         double sig0;
-        line_params(g.T, &m.vth, &m.a, &sig0);
+        species_params(g.line, g.T, &m.vth, &m.a, &sig0);
         m.r_in = g.r_inner;
         m.r_out = g.r_outer;
         m.n = g.tau0 > 0.0 ? g.tau0 / (sig0 * L) : g.n_HI;
@@ -1067,7 +1090,7 @@ thor_status make_model(thor_ctx* ctx, const thor_source& s, const thor_transport
     m.spec_scale = 1.0;
     if (o.spec_T_ref > 0.0) {
         double vth, a, s0;
-        line_params(o.spec_T_ref, &vth, &a, &s0);
+        species_params(g.line, o.spec_T_ref, &vth, &a, &s0);
         m.spec_scale = 1.0 / vth;
     }
     m.done = nullptr;
@@ -1467,6 +1490,9 @@ thor_status thor_load_grid(thor_ctx* ctx, const thor_geometry* g) {
     if (g->kind < 0 || g->kind > 2) return fail(THOR_E_INVAL, "bad geometry kind %d", g->kind);
     if (g->albedo < 0.0 || g->albedo > 1.0) return fail(THOR_E_INVAL, "albedo must be in [0, 1]");
     if (g->g_hg <= -1.0 || g->g_hg >= 1.0) return fail(THOR_E_INVAL, "g_hg must be in (-1, 1)");
+    if (g->line < THOR_LINE_LYA || g->line > THOR_LINE_MG2K) return fail(THOR_E_INVAL, "bad line %d", g->line);
+    if (g->line != THOR_LINE_LYA && g->kind == THOR_GEOM_GRID)
+        return fail(THOR_E_UNSUPPORTED, "the Mg II lines need a meshless medium");
     if (g->kind != THOR_GEOM_GRID) {
         if (!(g->r_outer > g->r_inner) || g->r_inner < 0.0) return fail(THOR_E_INVAL, "need 0 <= r_inner < r_outer");
         if (!(g->T > 0.0)) return fail(THOR_E_INVAL, "T must be positive");
@@ -1565,8 +1591,10 @@ thor_status thor_emit(thor_ctx* ctx, const thor_source* src, uint64_t n_packets,
     if (!src) return fail(THOR_E_INVAL, "null source");
     if (!ctx->has_geom) return fail(THOR_E_STATE, "thor_load_grid first");
     if (src->kind != THOR_SRC_POINT && src->kind != THOR_SRC_CELL_N2) return fail(THOR_E_INVAL, "bad source kind");
-    if (src->spectrum < 0 || src->spectrum > 2) return fail(THOR_E_INVAL, "bad source spectrum");
-    if (src->spectrum == THOR_SPEC_GAUSS && src->sigma_v < 0.0) return fail(THOR_E_INVAL, "sigma_v < 0");
+    if (src->spectrum < 0 || src->spectrum > 3) return fail(THOR_E_INVAL, "bad source spectrum");
+    if ((src->spectrum == THOR_SPEC_GAUSS || src->spectrum == THOR_SPEC_FLAT) && src->sigma_v < 0.0)
+        return fail(THOR_E_INVAL, "sigma_v < 0");
+    if (src->lines != 0 && src->lines != 1) return fail(THOR_E_INVAL, "lines must be 0 or 1");
     if (src->kind == THOR_SRC_CELL_N2 && ctx->geom.kind != THOR_GEOM_GRID)
         return fail(THOR_E_INVAL, "CELL_N2 sources need a grid");
     if (src->spectrum == THOR_SPEC_THERMAL && ctx->geom.kind != THOR_GEOM_GRID)
@@ -1702,7 +1730,9 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         const uint32_t turn = opt->visits_per_turn > 0 ? uint32_t(opt->visits_per_turn) : 256u;
         if (opt->step_events > 0xFFFFFFFFull) return fail(THOR_E_INVAL, "step_events must fit 32 bits");
         // unbounded calls hand the last packets of drained waves to k_tail
-        const bool hand_off = !bounded && wide_lanes(opt) > 0;
+        // the tail kernel's events run on draws evaluated ahead for one line;
+        // doublet packets stay in the persistent kernel
+        const bool hand_off = !bounded && wide_lanes(opt) > 0 && ctx->geom.line == THOR_LINE_LYA;
         *ctx->h_desc = StepDesc{q_end, int(nb), uint32_t(opt->step_events), turn, hand_off ? wide_lanes(opt) : 0u,
                                 park_lanes(opt), refill_64ths(opt), 0u};
         HIPCHK(ctx, hipMemcpyAsync(ctx->d_desc, ctx->h_desc, sizeof(StepDesc), hipMemcpyHostToDevice, ctx->stream));

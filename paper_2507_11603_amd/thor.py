@@ -22,7 +22,8 @@ STATUS = {0: "THOR_OK", 1: "THOR_INCOMPLETE", -1: "THOR_E_INVAL", -2: "THOR_E_NO
 GEOM = {"shell": 0, "sphere": 0, "slab": 1, "grid": 2}
 VEL = {"none": 0, "const_radial": 1, "linear": 2}
 SRC = {"point": 0, "cell_n2": 1}
-SPEC = {"delta": 0, "gauss": 1, "thermal": 2}
+SPEC = {"delta": 0, "gauss": 1, "thermal": 2, "flat": 3}
+LINE = {"lya": 0, "mg2": 1, "mg2k": 2}
 PREC = {"fp64": 0, "mixed": 1}
 PATH = {"plain": 0, "persistent": 1}
 PHASE = {"iso": 0, "dipole": 1, "core_wing": 2}
@@ -53,13 +54,13 @@ class thor_geometry(C.Structure):
                 ("boundary_handoff", C.c_int32), ("sigma_d", C.c_double), ("tau_d", C.c_double),
                 ("albedo", C.c_double), ("g_hg", C.c_double),
                 ("hubble", C.c_double), ("hubble_ref", C.c_double * 3), ("hubble_step", C.c_double),
-                ("stop_dv", C.c_double)]
+                ("stop_dv", C.c_double), ("line", C.c_int32)]
 
 
 class thor_source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pos", C.c_double * 3), ("spectrum", C.c_int32),
                 ("dv0", C.c_double), ("sigma_v", C.c_double),
-                ("seed", C.c_uint32), ("request_id", C.c_uint32)]
+                ("seed", C.c_uint32), ("request_id", C.c_uint32), ("lines", C.c_int32)]
 
 
 class thor_transport_opts(C.Structure):
@@ -288,6 +289,7 @@ def make_geometry(geom: dict, device_fields=None) -> thor_geometry:
     g.hubble_ref[:] = list(map(float, geom.get("hubble_ref", (0.0, 0.0, 0.0))))
     g.hubble_step = geom.get("hubble_step", 0.0)
     g.stop_dv = geom.get("stop_dv", 0.0)
+    g.line = LINE[geom.get("line", "lya")]
     return g
 
 
@@ -300,6 +302,7 @@ def make_source(src: dict) -> thor_source:
     s.sigma_v = src.get("sigma_v", 0.0)
     s.seed = src.get("seed", 1)
     s.request_id = src.get("request_id", 0)
+    s.lines = int(src.get("lines", 0))
     return s
 
 
