@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--sphere", type=int, default=100_000,
                     help="packets of the meshless tau0 = 1e5 sphere, one persistent call (0: skip)")
     ap.add_argument("--sphere-only", type=int, default=0, help="print only the sphere record")
+    ap.add_argument("--mg2", type=int, default=1_000_000,
+                    help="packets per outflow velocity of the Mg II doublet sphere (0: skip)")
+    ap.add_argument("--mg2-only", type=int, default=0, help="print only the Mg II record")
     ap.add_argument("--serving", type=int, default=300, help="measured requests of the serving stream (0: skip)")
     ap.add_argument("--serving-warmup", type=int, default=60)
     ap.add_argument("--serving-rate", type=float, default=200.0,
@@ -408,6 +411,49 @@ def sphere_box(a):
     return out
 
 
+def mg2_box(a):
+    """Section 4's doublet test: the Mg II sphere (column 10^14.5 cm^-2,
+    T = 1e4 K) with the linear outflow v = v_max r/R for v_max = 100, 200,
+    500, 1000 km/s, lit by a flat continuum over -1500..1000 km/s around the
+    k line; a.mg2 packets per velocity, mixed precision, one persistent call
+    each.  Reports the throughput and the share of the escaping flux blueward
+    of the doublet's midpoint, F_blue / F_tot."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2507_11603_amd import thor
+    out = {"workload": "Mg II h+k sphere, N = 10^14.5 cm^-2, T = 1e4 K, linear outflow, flat continuum "
+                       "-1500..1000 km/s, dipole (k) / isotropic (h)", "packets": a.mg2, "runs": []}
+    c_h = -767.6e5
+    for v in (100.0, 200.0, 500.0, 1000.0):
+        wl = W.mg2_sphere(v_max_kms=v, n_packets=a.mg2)
+        T = thor.Transport(0)
+        try:
+            T.load(wl["geom"])
+            kw = dict(precision="mixed", path="persistent", waves_per_cu=8)
+            run_call(T, wl, max(1, a.mg2 // 10), 10**12, **kw)
+            T.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            T.emit(wl["src"], a.mg2, 0)
+            _, st = T.transport(wl["opts"], **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            spec = T.spectrum()
+        finally:
+            T.close()
+        sp = wl["opts"]["spectrum"]
+        centres = sp["lo"] + (np.arange(sp["nb"]) + 0.5) * (sp["hi"] - sp["lo"]) / sp["nb"]
+        out["runs"].append({"v_max_kms": v, "seconds": dt, "packets_per_s": st["emitted"] / dt,
+                            "scatterings_per_s": (st["n_res"] + st["n_dust"]) / dt,
+                            "scatterings_per_packet": st["n_res"] / max(st["emitted"], 1),
+                            "segments_per_s": st["main_visits"] / (st["kernel_ms"] / 1e3),
+                            "blue_fraction": float(spec[centres > 0.5 * c_h].sum() / spec.sum()),
+                            "spectrum_50_bins": [int(x) for x in spec.reshape(50, -1).sum(axis=1)]})
+    return out
+
+
 def rays_box(a, device_fields=False):
     """Raytracing driver on the forest workload (web box at z = 2): column-
     density projections along each axis (HBM-bound: 4 B read per cell) and
@@ -496,6 +542,9 @@ def main():
     if a.sphere_only:
         print(json.dumps({"sphere": sphere_box(a)}), flush=True)
         return
+    if a.mg2_only:
+        print(json.dumps({"mg2": mg2_box(a)}), flush=True)
+        return
     kw = dict(precision=a.precision, path="persistent", waves_per_cu=a.waves_per_cu, block=a.block or 256,
               visits_per_turn=a.turn_visits or 256, wide_lanes=a.wide_lanes or 8, park_lanes=a.park_lanes or 32,
               refill_64ths=a.refill_64ths or 16, presort=a.presort)
@@ -551,6 +600,8 @@ def main():
         out["shell"] = shell_box(a)
     if a.sphere:
         out["sphere"] = sphere_box(a)
+    if a.mg2:
+        out["mg2"] = mg2_box(a)
     if a.serving:
         out["serving"] = serving(a)
     if a.rays:

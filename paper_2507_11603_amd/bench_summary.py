@@ -60,6 +60,11 @@ def render(d: dict, command: str, stats: str | None) -> str:
         L.append("* %s: %d packets in %.2f s, %.4g scatterings/s, longest history %d; dominant `%s`"
                  % (s["workload"], s["packets"], s["seconds"], s["scatterings_per_s"], s["longest_history"],
                     s.get("dominant")))
+    if "mg2" in d:
+        g = d["mg2"]
+        L.append("* %s, %d packets per velocity: %s" % (g["workload"], g["packets"], "; ".join(
+            "%g km/s: %.3g packets/s, %.3g segments/s, F_blue/F_tot %.3f" % (
+                r["v_max_kms"], r["packets_per_s"], r["segments_per_s"], r["blue_fraction"]) for r in g["runs"])))
     if "serving" in d:
         s = d["serving"]
         L.append("* serving: %d requests (+%d warm-up) at %.0f req/s: p50 %.1f ms, p99 %.1f ms; offered %.4g "
