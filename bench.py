@@ -31,7 +31,7 @@ BYTES_PER_VISIT = 20.0         # (vx, vy, vz, n_HI, T) float32 per cell visit
 METRIC = "photon scatterings/s on 1 MI355X (vs FP64 plain path); p50/p99 shell-request latency"
 # knobs the autotuner searches on the web box (the others keep the library
 # defaults; every candidate costs three runs of the steady-state sample)
-WEB_SPACE = dict(park_lanes=[16, 32, 48], refill_64ths=[8, 16, 32], wide_lanes=[8, 16])
+WEB_SPACE = dict(park_lanes=[16, 32, 48], refill_64ths=[8, 16, 32], wide_lanes=[8, 16], presort=[0, 2, -1])
 KERNEL_NAMES = {"transport": "k_persistent<float, true, true>", "tail": "k_tail<float, true, true>",
                 "peel_pass": "k_peel_pass_f32"}
 
@@ -431,7 +431,7 @@ def mg2_box(a):
         T = thor.Transport(0)
         try:
             T.load(wl["geom"])
-            kw = dict(precision="mixed", path="persistent", waves_per_cu=8)
+            kw = dict(precision="mixed", path="persistent", waves_per_cu=8, presort=a.presort)
             run_call(T, wl, max(1, a.mg2 // 10), 10**12, **kw)
             T.reset()
             torch.cuda.synchronize()

@@ -227,13 +227,17 @@ typedef struct {
                                    uint64: bit-reproducible in any order and launch
                                    shape; a voxel holds at most 2^(64 - fixed_bits)) */
     int32_t fixed_bits;         /* FIXED64: 0 = 40 (units of 9.1e-13, voxel sums up to 1.7e7) */
-    int32_t presort;            /* PERSISTENT, unbounded, grid: 1 = take the queued packets in the
-                                   Morton order of their n_HI^2-weighted emission cells (drawn
-                                   first by a pre-pass, radix-sorted on the device, inside the
-                                   call's time) so that the packets in flight and their peel
-                                   rays are near each other; results do not change (each
-                                   packet's history depends only on its id); 0 = the library
-                                   default, negative = queue order */
+    int32_t presort;            /* PERSISTENT, unbounded: order in which the queued packets are
+                                   taken (keys drawn by a pre-pass, radix-sorted on the device,
+                                   inside the call's time); results do not change (each packet's
+                                   history depends only on its id).  1 = spatial: the Morton
+                                   order of n_HI^2-weighted emission cells (grids), so that the
+                                   packets in flight and their peel rays are near each other;
+                                   2 = frequency: the emitted offset (Section 7.1's pre-sorting),
+                                   so that a wave's packets start alike; 0 = the library default
+                                   (1 for grids with CELL_N2 sources, 2 for meshless media whose
+                                   sources spread in frequency, else none); -1 = queue order;
+                                   other values THOR_E_INVAL */
 } thor_transport_opts;
 
 typedef enum { THOR_ACCUM_F32_ATOMIC = 0, THOR_ACCUM_FIXED64 = 1 } thor_accum;

@@ -5,8 +5,9 @@ packet slots of the launch: lanes x one packet each), park_lanes (how many
 lanes wait at their interaction sites before they interact together),
 refill_64ths (the share of a turn's lanes that must have finished before the
 wave ends the turn and refills them), wide_lanes (the live-lane count at
-which a drained wave hands its packets to the tail kernel) and
-visits_per_turn.
+which a drained wave hands its packets to the tail kernel), visits_per_turn
+and presort (the order in which queued packets are taken: the library
+default, by emitted frequency, or as queued).
 
 Every candidate transports the same sample of the workload (the same photon
 ids, hence the same histories and the same work); its score is the median
@@ -25,10 +26,11 @@ import statistics
 CACHE = os.environ.get("THOR_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "thor_autotune.json"))
 
-DEFAULTS = dict(waves_per_cu=8, block=256, park_lanes=32, refill_64ths=16, wide_lanes=8, visits_per_turn=256)
+DEFAULTS = dict(waves_per_cu=8, block=256, park_lanes=32, refill_64ths=16, wide_lanes=8, visits_per_turn=256,
+                presort=0)
 SPACE = dict(park_lanes=[-1, 16, 24, 32, 40], refill_64ths=[8, 16, 32, 64], waves_per_cu=[4, 8],
-             block=[64, 128, 256], wide_lanes=[4, 8, 16], visits_per_turn=[64, 256, 1024])
-VERSION = 4
+             block=[64, 128, 256], wide_lanes=[4, 8, 16], visits_per_turn=[64, 256, 1024], presort=[0, 2, -1])
+VERSION = 5
 
 
 def _key(device_name: str, workload: str, precision: str, sample: int) -> str:

@@ -598,9 +598,12 @@ __global__ void k_fx_to_f32(const unsigned long long* __restrict__ src, float* _
         dst[i] = float(double(src[i]) * inv_scale);
 }
 
-// Sort keys of the queue for spatially ordered emission: the Morton code
-// (x, y, z bits interleaved) of each n_HI^2-weighted packet's emission cell,
-// drawn exactly as the generator draws it; other sources sort first.
+// Sort keys of the queue.  mode 1 (spatial): the Morton code (x, y, z bits
+// interleaved) of each n_HI^2-weighted packet's emission cell, drawn exactly
+// as the generator draws it; other sources sort first.  mode 2 (frequency):
+// the packet's emitted offset in the source frame (line centre, Gaussian or
+// flat draw, the doublet line chosen; the thermal draw without its cell's
+// width), its IEEE bits mapped to an order-preserving integer.
 __device__ __forceinline__ uint64_t spread3(uint64_t v) {   // bit i -> bit 3i (21 bits)
     v &= 0x1FFFFFull;
     v = (v | (v << 32)) & 0x1F00000000FFFFull;
@@ -611,15 +614,30 @@ __device__ __forceinline__ uint64_t spread3(uint64_t v) {   // bit i -> bit 3i (
     return v;
 }
 __global__ void k_emit_keys(GridDev g, const ModelDev* __restrict__ models, const BatchDev* __restrict__ batches,
-                            int nbatch, uint64_t q_end, uint64_t* __restrict__ keys, uint64_t* __restrict__ vals) {
+                            int nbatch, uint64_t q_end, uint64_t* __restrict__ keys, uint64_t* __restrict__ vals,
+                            int mode) {
     for (uint64_t q = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < q_end;
          q += uint64_t(gridDim.x) * blockDim.x) {
         const BatchDev b = batches[find_batch(batches, nbatch, q)];
         const ModelDev& m = models[b.model];
         uint64_t key = 0;
-        if (m.src_kind == kSrcCellN2) {
-            const uint64_t id = b.first_id + (q - b.q0);
-            const Key k{m.seed, m.req, uint32_t(id), uint32_t(id >> 32)};
+        const uint64_t id = b.first_id + (q - b.q0);
+        const Key k{m.seed, m.req, uint32_t(id), uint32_t(id >> 32)};
+        if (mode == 2) {
+            double off = m.dv0;
+            if (m.spectrum != kSpecDelta) {
+                const Uni2<double> d = draw<double>(k, kSlotEGauss, 0);
+                if (m.spectrum == kSpecFlat) {
+                    off += m.sigma_v * (2.0 * d.a - 1.0);
+                } else {
+                    const double z = sqrt(-2.0 * log(1.0 - d.a)) * cospi(2.0 * d.b);
+                    off += (m.spectrum == kSpecGauss ? m.sigma_v : 1.0) * z;
+                }
+            }
+            if (m.lines && m.nl > 1 && draw<double>(k, kSlotELine, 0).a >= m.lw0) off += m.lc1;
+            const uint64_t bits = uint64_t(__double_as_longlong(off));
+            key = (bits >> 63) ? ~bits : (bits | (1ull << 63));
+        } else if (m.src_kind == kSrcCellN2) {
             const uint64_t c = emission_cell(g, draw<double>(k, kSlotECell, 0).a);
             const uint64_t x = c % uint64_t(g.nx), y = (c / uint64_t(g.nx)) % uint64_t(g.ny);
             const uint64_t z = c / (uint64_t(g.nx) * uint64_t(g.ny));
@@ -1104,6 +1122,7 @@ thor_status check_opts(const thor_transport_opts* o) {
     if (o->phase < 0 || o->phase > 2) return fail(THOR_E_INVAL, "bad phase function");
     if (o->core_skip < 0 || o->core_skip > 2) return fail(THOR_E_INVAL, "bad core_skip");
     if (o->n_obs < 0 || o->n_obs > 6) return fail(THOR_E_INVAL, "n_obs must be 0..6");
+    if (o->presort < -1 || o->presort > 2) return fail(THOR_E_INVAL, "presort must be -1, 0, 1 or 2");
     for (int i = 0; i < o->n_obs; ++i)
         if (o->obs_axis[i] < 0 || o->obs_axis[i] > 5) return fail(THOR_E_INVAL, "bad observer axis");
     if (o->n_obs > 0) {
@@ -1200,8 +1219,16 @@ OutDev make_out(thor_ctx* ctx, const thor_transport_opts* o) {
     return out;
 }
 
-// Whether a call presorts its queue (library default: on for grids).
-bool presort_on(const thor_transport_opts* o) { return o->presort >= 0; }
+// The presort of a call: 0 none, 1 spatial, 2 frequency.  The library
+// default is spatial for grids with n_HI^2-weighted sources, by frequency
+// for meshless media whose sources spread in frequency (Gaussian, flat,
+// doublet lines), none otherwise.
+int presort_mode(const thor_transport_opts* o, bool grid, bool any_cell, bool any_spread) {
+    if (o->presort < 0) return 0;
+    if (o->presort == 2) return 2;
+    if (grid) return any_cell ? 1 : 0;
+    return o->presort == 0 && any_spread ? 2 : 0;
+}
 
 // Lanes of a persistent wave that wait at their interaction sites before
 // they interact together (0: each interacts when it gets there).
@@ -1786,9 +1813,14 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         // sorted permutation
         const uint64_t* perm = nullptr;
         ctx->split_presort = 0.0;
-        bool any_cell = false;
-        for (size_t i = 0; i < nb; ++i) any_cell |= ctx->pending[i].src.kind == THOR_SRC_CELL_N2;
-        if (grid && !bounded && any_cell && presort_on(opt) && q_end > 1) {
+        bool any_cell = false, any_spread = false;
+        for (size_t i = 0; i < nb; ++i) {
+            const thor_source& src = ctx->pending[i].src;
+            any_cell |= src.kind == THOR_SRC_CELL_N2;
+            any_spread |= src.spectrum != THOR_SPEC_DELTA || (src.lines && ctx->geom.line == THOR_LINE_MG2);
+        }
+        const int sort_mode = bounded ? 0 : presort_mode(opt, grid, any_cell, any_spread);
+        if (sort_mode && q_end > 1) {
             if (q_end > ctx->sort_cap) {
                 dfree(ctx, ctx->d_sort, ctx->sort_cap * 32);
                 ctx->d_sort = nullptr;
@@ -1802,8 +1834,9 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
             uint64_t* keys2 = ctx->d_sort + 2 * ctx->sort_cap;
             uint64_t* vals2 = ctx->d_sort + 3 * ctx->sort_cap;
             int bits = 1;
-            while ((1 << bits) < std::max(ctx->grid.nx, std::max(ctx->grid.ny, ctx->grid.nz))) ++bits;
-            const int end_bit = std::min(64, 3 * bits);
+            if (grid)
+                while ((1 << bits) < std::max(ctx->grid.nx, std::max(ctx->grid.ny, ctx->grid.nz))) ++bits;
+            const int end_bit = sort_mode == 2 ? 64 : std::min(64, 3 * bits);
             size_t need = 0;
             HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, keys2, vals, vals2, (int64_t)q_end, 0,
                                                            end_bit, ctx->stream));
@@ -1817,7 +1850,7 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
             }
             HIPCHK(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
             hipLaunchKernelGGL(k_emit_keys, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->grid,
-                               ctx->d_models, ctx->d_batches, int(nb), q_end, keys, vals);
+                               ctx->d_models, ctx->d_batches, int(nb), q_end, keys, vals, sort_mode);
             HIPCHK(ctx, hipGetLastError());
             size_t tmp = ctx->sort_tmp_bytes;
             HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(ctx->d_sort_tmp, tmp, keys, keys2, vals, vals2,
@@ -1836,9 +1869,9 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
                 hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_tailctl, 3);
             if (seeds || hand_off) HIPCHK(ctx, hipEventRecord(ctx->ev_a, ctx->stream));
             if (fp64) grid ? launch_persistent<double, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats, nullptr, perm)
-                           : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats);
+                           : launch_persistent<double, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats, nullptr, perm);
             else grid ? launch_persistent<float, true>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats, nullptr, perm)
-                      : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats);
+                      : launch_persistent<float, false>(ctx, ctx->stream, gsize, block, ctx->d_batches, ctx->d_desc, cur, out, ctx->d_models, ppk, pal, sb, hand_off, ctx->d_xstats, nullptr, perm);
             if (hand_off) {
                 HIPCHK(ctx, hipEventRecord(ctx->ev_c, ctx->stream));
                 if (fp64) grid ? launch_tail<double, true>(ctx, ctx->d_desc, out, ppk, pal, sb)

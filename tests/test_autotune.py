@@ -22,10 +22,11 @@ class FakeTransport:
         self.samples.add((n, first))
 
     def transport(self, opts, precision, path, waves_per_cu, block, park_lanes, refill_64ths, wide_lanes,
-                  visits_per_turn):
+                  visits_per_turn, presort):
         self.calls += 1
         ms = (10.0 + abs(waves_per_cu - 4) + abs(park_lanes - 24) / 8.0 + (block != 128)
-              + abs(refill_64ths - 32) / 16.0 + abs(wide_lanes - 16) / 4.0 + abs(visits_per_turn - 1024) / 512.0)
+              + abs(refill_64ths - 32) / 16.0 + abs(wide_lanes - 16) / 4.0 + abs(visits_per_turn - 1024) / 512.0
+              + (presort != 2))
         if self.calls % 3 == 0:
             ms += 1000.0
         return 0, {"kernel_ms": ms}
@@ -39,7 +40,7 @@ def test_tune_coordinate_search_with_median(monkeypatch, tmp_path):
     wl = {"src": {}, "opts": {}}
     best, table = autotune.tune(T, wl, "fake-web", sample=10, repeats=3)
     assert best == {"waves_per_cu": 4, "block": 128, "park_lanes": 24, "refill_64ths": 32, "wide_lanes": 16,
-                    "visits_per_turn": 1024}
+                    "visits_per_turn": 1024, "presort": 2}
     # every candidate ran on the same packets
     assert T.samples == {(10, 7 * 10**12)}
     assert len(table) <= sum(len(v) for v in autotune.SPACE.values())

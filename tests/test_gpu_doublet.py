@@ -142,3 +142,24 @@ def test_mg2_lines_refused_on_grids(gpu):
         assert "meshless" in str(e.value)
     finally:
         T.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_frequency_presort_changes_only_the_order(gpu, precision):
+    """Queue sorted by emitted frequency (presort 2, Section 7.1's
+    pre-sorting) on the flat continuum through the Mg II outflow: records,
+    spectrum and the physical counters equal those of the queue order."""
+    n = 20000
+    wl = W.mg2_sphere(n_packets=n, v_max_kms=500.0, seed=5)
+    res = []
+    for presort in (-1, 2):
+        r = gpu.run(wl, n=n, precision=precision, path="persistent", records=True, presort=presort)
+        res.append(r)
+    a, b = res
+    _say("frequency presort %s: %.2f ms of %.2f ms" % (precision, b["stats"]["presort_ms"], b["stats"]["kernel_ms"]))
+    assert a["stats"]["presort_ms"] == 0.0 and b["stats"]["presort_ms"] > 0.0
+    assert np.array_equal(a["spectrum"], b["spectrum"])
+    for k in ("n_res", "n_dust", "fate", "dv"):
+        assert np.array_equal(a["records"][k], b["records"][k]), k
+    for k in ("emitted", "escaped", "n_res", "main_visits", "upar_trials"):
+        assert a["stats"][k] == b["stats"][k], k
