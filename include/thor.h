@@ -238,6 +238,12 @@ typedef struct {
                                    (1 for grids with CELL_N2 sources, 2 for meshless media whose
                                    sources spread in frequency, else none); -1 = queue order;
                                    other values THOR_E_INVAL */
+    int32_t seed_sort;          /* peel-seed path: before each peel pass the buffer's rays are
+                                   sorted by (axis, pencil index of their front cell), so that
+                                   the rays a wave marches together share cache lines; 0 = the
+                                   library default (on), 1 = on, -1 = buffer order.  Only the
+                                   order of the cube's additions changes (FIXED64 cubes are
+                                   identical) */
 } thor_transport_opts;
 
 typedef enum { THOR_ACCUM_F32_ATOMIC = 0, THOR_ACCUM_FIXED64 = 1 } thor_accum;
@@ -265,7 +271,8 @@ typedef struct {
     uint64_t tail_main_visits;      /* main-march cell visits of the tail kernels */
     uint64_t tail_peel_visits;      /* peel cell visits of the tail kernels */
     uint64_t redshifted;            /* escaped through the redshift stop (part of escaped) */
-    double presort_ms;              /* of kernel_ms, the spatial presort of the queue */
+    double presort_ms;              /* of kernel_ms, the presort of the queue */
+    double seedsort_ms;             /* of kernel_ms, the sorts of the seed buffer before the peel passes */
 } thor_stats;
 
 /* Per-packet record (index = packet id - first id of its batch, batches in

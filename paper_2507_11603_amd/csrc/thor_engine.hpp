@@ -341,6 +341,7 @@ struct SeedBuf {
     unsigned long long* count;     // slots claimed this step
     unsigned long long* parked;    // waves with a lane stopped by a full buffer
     uint32_t chunk;                // slots a lane claims at a time, >= observers
+    const uint32_t* order;         // peel pass: slots in this order (null: buffer order)
 };
 
 // observers the seed path serves (more go through the inline march)

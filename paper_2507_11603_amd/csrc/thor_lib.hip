@@ -448,7 +448,7 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
             const uint64_t room = end - cur;
             const uint32_t take = uint64_t(__popcll(m)) < room ? uint32_t(__popcll(m)) : uint32_t(room);
             if (mine && r < take) {
-                PeelSeed* slot = sb.s + (cur + r);
+                PeelSeed* slot = sb.s + (sb.order ? uint64_t(sb.order[cur + r]) : (cur + r));
                 const PeelSeed sd = *slot;
                 if (sd.obs >= 0) {
                     slot->obs = -1;          // the slot is free for the next step
@@ -645,6 +645,32 @@ __global__ void k_emit_keys(GridDev g, const ModelDev* __restrict__ models, cons
         }
         keys[q] = key;
         vals[q] = q;
+    }
+}
+
+// Sort keys of the seed buffer's first n slots for the peel pass: the ray's
+// axis, the pencil of its front cell and the 256-cell block of that pencil
+// it starts in (one 4 KiB page of 16-byte pencil records), so that the rays
+// a wave marches together run along the same pencils and pages; empty slots
+// sort last.  Rays of one key keep their buffer order (the sort is stable).
+__global__ void k_seed_keys(GridDev g, OutDev o, SeedBuf sb, uint64_t n, uint32_t max_blocks,
+                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const uint32_t nx = uint32_t(g.nx), ny = uint32_t(g.ny), nz = uint32_t(g.nz);
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        const PeelSeed* sd = sb.s + i;
+        const int obs = sd->obs;
+        uint32_t key = 3u * max_blocks;
+        if (obs >= 0) {
+            const int a = sel3(obs, o.obs_axis[0], o.obs_axis[1], o.obs_axis[2]) % 3;
+            const uint32_t x = uint32_t(sd->c[0]), y = uint32_t(sd->c[1]), z = uint32_t(sd->c[2]);
+            // pencil index and position along the pencil, as the pencil records are laid out
+            const uint32_t pencil = a == 0 ? z * ny + y : (a == 1 ? z * nx + x : y * nx + x);
+            const uint32_t pos = a == 0 ? x : (a == 1 ? y : z);
+            const uint32_t per = ((a == 0 ? nx : (a == 1 ? ny : nz)) + 255u) >> 8;
+            key = uint32_t(a) * max_blocks + pencil * per + (pos >> 8);
+        }
+        keys[i] = key;
+        vals[i] = uint32_t(i);
     }
 }
 
@@ -970,6 +996,15 @@ struct thor_ctx {
     void* d_sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
     double split_presort = 0.0;
+    // sort of the seed buffer before each peel pass: keys and slot indices,
+    // their sorted copies, hipCUB scratch
+    uint32_t* d_skeys = nullptr;           // 2 arrays of ssort_cap
+    uint32_t* d_svals = nullptr;           // 2 arrays of ssort_cap
+    uint64_t ssort_cap = 0;
+    void* d_ssort_tmp = nullptr;
+    size_t ssort_tmp_bytes = 0;
+    double split_ssort = 0.0;
+    hipEvent_t ev_s = nullptr;             // end of the seed sort of a round
 
     // serving (continuous batching of shell-model requests)
     bool s_init = false;
@@ -1123,6 +1158,7 @@ thor_status check_opts(const thor_transport_opts* o) {
     if (o->core_skip < 0 || o->core_skip > 2) return fail(THOR_E_INVAL, "bad core_skip");
     if (o->n_obs < 0 || o->n_obs > 6) return fail(THOR_E_INVAL, "n_obs must be 0..6");
     if (o->presort < -1 || o->presort > 2) return fail(THOR_E_INVAL, "presort must be -1, 0, 1 or 2");
+    if (o->seed_sort < -1 || o->seed_sort > 1) return fail(THOR_E_INVAL, "seed_sort must be -1, 0 or 1");
     for (int i = 0; i < o->n_obs; ++i)
         if (o->obs_axis[i] < 0 || o->obs_axis[i] > 5) return fail(THOR_E_INVAL, "bad observer axis");
     if (o->n_obs > 0) {
@@ -1308,6 +1344,56 @@ void launch_tail(thor_ctx* ctx, const StepDesc* d_desc, const OutDev& out, void*
                            ctx->d_models, d_desc, out, pool, tail, sb, ctx->d_xstats + 1, ctx->d_xstats);
 }
 
+// Whether the peel pass takes its rays in sorted order (library default: yes).
+bool seed_sort_on(const thor_transport_opts* o) { return o->seed_sort >= 0; }
+
+// Sorts the first n slots of the seed buffer by (axis, pencil, 256-cell
+// block of the front cell) into sb->order (k_seed_keys).
+thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n) {
+    if (ctx->ssort_cap < ctx->seed_cap) {
+        dfree(ctx, ctx->d_skeys, ctx->ssort_cap * 8);
+        dfree(ctx, ctx->d_svals, ctx->ssort_cap * 8);
+        ctx->d_skeys = nullptr;
+        ctx->d_svals = nullptr;
+        ctx->ssort_cap = 0;
+        thor_status s = dalloc(ctx, (void**)&ctx->d_skeys, ctx->seed_cap * 8, "seed sort keys");
+        if (s) return s;
+        s = dalloc(ctx, (void**)&ctx->d_svals, ctx->seed_cap * 8, "seed sort slots");
+        if (s) return s;
+        ctx->ssort_cap = ctx->seed_cap;
+    }
+    uint32_t* keys = ctx->d_skeys;
+    uint32_t* keys2 = ctx->d_skeys + ctx->ssort_cap;
+    uint32_t* vals = ctx->d_svals;
+    uint32_t* vals2 = ctx->d_svals + ctx->ssort_cap;
+    const uint64_t nx = uint64_t(ctx->grid.nx), ny = uint64_t(ctx->grid.ny), nz = uint64_t(ctx->grid.nz);
+    const uint64_t max_blocks = std::max(ny * nz * ((nx + 255) / 256),
+                                         std::max(nz * nx * ((ny + 255) / 256), ny * nx * ((nz + 255) / 256)));
+    const uint64_t top = 3 * max_blocks;             // the key of an empty slot
+    if (top >= (uint64_t(1) << 32)) return THOR_OK;  // too many pencils for 32-bit keys: buffer order
+    int end_bit = 1;
+    while (end_bit < 32 && (uint64_t(1) << end_bit) <= top) ++end_bit;
+    size_t need = 0;
+    HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, keys2, vals, vals2, (int64_t)n, 0, end_bit,
+                                                   ctx->stream));
+    if (need > ctx->ssort_tmp_bytes) {
+        dfree(ctx, ctx->d_ssort_tmp, ctx->ssort_tmp_bytes);
+        ctx->d_ssort_tmp = nullptr;
+        ctx->ssort_tmp_bytes = 0;
+        thor_status s = dalloc(ctx, &ctx->d_ssort_tmp, need, "seed sort scratch");
+        if (s) return s;
+        ctx->ssort_tmp_bytes = need;
+    }
+    hipLaunchKernelGGL(k_seed_keys, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->grid, out, *sb, n,
+                       uint32_t(max_blocks), keys, vals);
+    HIPCHK(ctx, hipGetLastError());
+    size_t tmp = ctx->ssort_tmp_bytes;
+    HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(ctx->d_ssort_tmp, tmp, keys, keys2, vals, vals2, (int64_t)n, 0,
+                                                   end_bit, ctx->stream));
+    sb->order = vals2;
+    return THOR_OK;
+}
+
 // Tail list of `slots` packets of either precision.
 thor_status ensure_tail(thor_ctx* ctx, uint64_t slots) {
     if (ctx->d_tail_pk && ctx->tail_slots >= slots) return THOR_OK;
@@ -1345,6 +1431,7 @@ thor_status ensure_seeds(thor_ctx* ctx, uint64_t slots, SeedBuf* sb) {
         if (s) return s;
     }
     sb->s = ctx->d_seeds;
+    sb->order = nullptr;
     sb->cap = ctx->seed_cap;
     sb->count = ctx->d_seedctl;
     sb->parked = ctx->d_seedctl + 1;
@@ -1433,7 +1520,7 @@ thor_status thor_create(thor_ctx** out, int hip_device, void* hip_stream, uint64
     if (!s) s = dalloc(ctx, (void**)&ctx->d_xstats, (kNumU64Counters + 1) * 8, "tail counters");
     if (!s && (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess ||
                hipEventCreate(&ctx->ev_a) != hipSuccess || hipEventCreate(&ctx->ev_b) != hipSuccess ||
-               hipEventCreate(&ctx->ev_c) != hipSuccess))
+               hipEventCreate(&ctx->ev_c) != hipSuccess || hipEventCreate(&ctx->ev_s) != hipSuccess))
         s = fail(THOR_E_DEVICE, "hipEventCreate failed");
     if (!s) {
         // the no-allocation scratch of this device (hipSetDevice above made it current)
@@ -1468,7 +1555,7 @@ void thor_destroy(thor_ctx* ctx) {
                     ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
                     ctx->d_seeds, ctx->d_seedctl, ctx->d_axr[0], ctx->d_axr[1], ctx->d_axr[2],
                     ctx->d_tail_pk, ctx->d_tail_home, ctx->d_tailctl, ctx->d_xstats, ctx->d_sort,
-                    ctx->d_sort_tmp};
+                    ctx->d_sort_tmp, ctx->d_skeys, ctx->d_svals, ctx->d_ssort_tmp};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& kv : ctx->s_reqs)
@@ -1486,6 +1573,7 @@ void thor_destroy(thor_ctx* ctx) {
     if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
     if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
     if (ctx->ev_c) (void)hipEventDestroy(ctx->ev_c);
+    if (ctx->ev_s) (void)hipEventDestroy(ctx->ev_s);
     delete ctx;
 }
 
@@ -1806,13 +1894,14 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
             hipLaunchKernelGGL(k_zero_u32, dim3(ctx->num_cu), dim3(256), 0, ctx->stream,
                                reinterpret_cast<unsigned*>(ctx->d_pool_alive), ctx->pool_slots);
         unsigned long long* cur = ctx->d_stats + kNumU64Counters;
-        double t_tr = 0.0, t_pp = 0.0, t_tail = 0.0;
+        double t_tr = 0.0, t_pp = 0.0, t_tail = 0.0, t_ss = 0.0;
         uint64_t passes = 0;
         // spatial order of the queue: emission cells drawn by a pre-pass, Morton
         // keys radix-sorted; the persistent kernel takes packets through the
         // sorted permutation
         const uint64_t* perm = nullptr;
         ctx->split_presort = 0.0;
+        ctx->split_ssort = 0.0;
         bool any_cell = false, any_spread = false;
         for (size_t i = 0; i < nb; ++i) {
             const thor_source& src = ctx->pending[i].src;
@@ -1893,18 +1982,32 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
                 }
                 break;
             }
-            if (fp64) launch_peel_pass<double>(ctx, out, sb);
-            else launch_peel_pass<float>(ctx, out, sb);
+            SeedBuf sbp = sb;
+            if (seed_sort_on(opt)) {
+                unsigned long long claimed = 0;
+                HIPCHK(ctx, hipMemcpyAsync(&claimed, ctx->d_seedctl, 8, hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+                const uint64_t nseeds = std::min<uint64_t>(claimed, sb.cap);
+                if (nseeds > 1) {
+                    s = sort_seeds(ctx, out, &sbp, nseeds);
+                    if (s) return s;
+                }
+            }
+            HIPCHK(ctx, hipEventRecord(ctx->ev_s, ctx->stream));
+            if (fp64) launch_peel_pass<double>(ctx, out, sbp);
+            else launch_peel_pass<float>(ctx, out, sbp);
             HIPCHK(ctx, hipGetLastError());
             HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
             unsigned long long ctl[4];
             HIPCHK(ctx, hipMemcpyAsync(ctl, ctx->d_seedctl, sizeof ctl, hipMemcpyDeviceToHost, ctx->stream));
             HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-            float ms_tr = 0.0f, ms_pp = 0.0f;
+            float ms_tr = 0.0f, ms_pp = 0.0f, ms_ss = 0.0f;
             HIPCHK(ctx, hipEventElapsedTime(&ms_tr, ctx->ev_a, ctx->ev_b));
-            HIPCHK(ctx, hipEventElapsedTime(&ms_pp, ctx->ev_b, ctx->ev1));
+            HIPCHK(ctx, hipEventElapsedTime(&ms_ss, ctx->ev_b, ctx->ev_s));
+            HIPCHK(ctx, hipEventElapsedTime(&ms_pp, ctx->ev_s, ctx->ev1));
             t_tr += ms_tr;
             t_pp += ms_pp;
+            t_ss += ms_ss;
             if (hand_off) {
                 float ms_tl = 0.0f;
                 HIPCHK(ctx, hipEventElapsedTime(&ms_tl, ctx->ev_c, ctx->ev_b));
@@ -1917,6 +2020,7 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
             ctx->split_tr = t_tr;
             ctx->split_pp = t_pp;
             ctx->split_tail = t_tail;
+            ctx->split_ssort = t_ss;
             ctx->split_passes = passes;
         }
     }
@@ -1946,6 +2050,7 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
     ctx->last.tail_main_visits = hx[1 + 7];
     ctx->last.tail_peel_visits = hx[1 + 8];
     ctx->last.presort_ms = ctx->split_presort;
+    ctx->last.seedsort_ms = ctx->split_ssort;
     if (out_stats) *out_stats = ctx->last;
     if (bounded) {
         // work left: queue not drained or packets parked in the pool

@@ -302,16 +302,18 @@ def test_sphere_spectrum_vs_stored_oracle(gpu, precision, path):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_fixed64_cube_is_bit_reproducible(gpu, precision):
     """accum FIXED64: the integer cube is the same bit for bit whatever the
-    launch shape, parking, refill threshold or seed-buffer size (the order of
-    the additions changes, integer sums do not); records are identical; its
-    float32 view matches the float-atomic cube to float rounding."""
+    launch shape, parking, refill threshold, seed-buffer size or order of the
+    peel pass's rays (the order of the additions changes, integer sums do
+    not); records are identical; its float32 view matches the float-atomic
+    cube to float rounding."""
     import torch
     wl = W.shell(n_grid=64, n_packets=20000, cube_nb=64)
     o = wl["opts"]
     shape = (1, o["cube"]["ny"], o["cube"]["nx"], o["cube"]["nb"])
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     variants = [dict(), dict(waves_per_cu=2, park_lanes=-1, refill_64ths=64, seed_slots=256 * n_cu),
-                dict(waves_per_cu=4, block=128, park_lanes=16, refill_64ths=8, wide_lanes=-1)]
+                dict(waves_per_cu=4, block=128, park_lanes=16, refill_64ths=8, wide_lanes=-1),
+                dict(seed_sort=-1, seed_slots=1024 * n_cu)]
     res = []
     for kw in variants:
         T = gpu.Transport(0)
