@@ -244,6 +244,14 @@ typedef struct {
                                    library default (on), 1 = on, -1 = buffer order.  Only the
                                    order of the cube's additions changes (FIXED64 cubes are
                                    identical) */
+    int32_t fuse_bins;          /* peel-seed path, photon fusing (Section 3.4.1), 0 = off.  m > 0:
+                                   before each peel pass, rays of one round that start in the
+                                   same cell towards the same observer and whose peeled
+                                   frequencies fall in the same 1/m of a cube frequency bin
+                                   (and the same cube element) are merged into one ray, weight
+                                   sum w exp(-tau_first), marched at the first ray's frequency.
+                                   Changes results (within the frequency tolerance); which rays
+                                   share a round depends on scheduling */
 } thor_transport_opts;
 
 typedef enum { THOR_ACCUM_F32_ATOMIC = 0, THOR_ACCUM_FIXED64 = 1 } thor_accum;
@@ -273,6 +281,7 @@ typedef struct {
     uint64_t redshifted;            /* escaped through the redshift stop (part of escaped) */
     double presort_ms;              /* of kernel_ms, the presort of the queue */
     double seedsort_ms;             /* of kernel_ms, the sorts of the seed buffer before the peel passes */
+    uint64_t peel_fused;            /* peel rays merged away by photon fusing */
 } thor_stats;
 
 /* Per-packet record (index = packet id - first id of its batch, batches in

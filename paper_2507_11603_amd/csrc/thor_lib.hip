@@ -674,6 +674,62 @@ __global__ void k_seed_keys(GridDev g, OutDev o, SeedBuf sb, uint64_t n, uint32_
     }
 }
 
+// Keys for photon fusing (Section 3.4.1): observer, the pencil-order index
+// of the front cell and the peeled frequency's 1/m sub-bin of a cube
+// frequency bin (m = fuse_bins).  Rays of one key start in the same cell
+// towards the same observer and end in the same cube element; they are
+// merged into one ray (k_seed_fuse).  Empty slots sort last.
+__global__ void k_fuse_keys(GridDev g, OutDev o, SeedBuf sb, uint64_t n, int m, uint64_t* __restrict__ keys,
+                            uint32_t* __restrict__ vals) {
+    const uint64_t nx = uint64_t(g.nx), ny = uint64_t(g.ny), nz = uint64_t(g.nz);
+    const uint64_t nc = nx * ny * nz;
+    const uint64_t nsub = uint64_t(o.cube_nb) * uint64_t(m);
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        const PeelSeed sd = sb.s[i];
+        uint64_t key = uint64_t(o.n_obs) * nc * nsub;      // empty: past every ray's key
+        if (sd.obs >= 0) {
+            const int a = sel3(sd.obs, o.obs_axis[0], o.obs_axis[1], o.obs_axis[2]) % 3;
+            const uint64_t x = uint64_t(sd.c[0]), y = uint64_t(sd.c[1]), z = uint64_t(sd.c[2]);
+            const uint64_t idx = a == 0 ? (z * ny + y) * nx + x : (a == 1 ? (z * nx + x) * ny + y : (y * nx + x) * nz + z);
+            const double u = (sd.dv - o.v_lo) / o.v_w * double(m);
+            uint64_t sub = u > 0.0 ? uint64_t(u) : 0;
+            sub = sub < nsub ? sub : nsub - 1;
+            key = (uint64_t(sd.obs) * nc + idx) * nsub + sub;
+        }
+        keys[i] = key;
+        vals[i] = uint32_t(i);
+    }
+}
+
+// Merges each run of equal fusing keys (and equal cube elements) in the
+// sorted order into its first seed: weight sum_j w_j exp(-tau_j) with the
+// first segments' optical depths folded in (tau 0), the first seed's
+// frequency for the rest of the ray; the others are emptied.  *fused counts
+// the rays merged away.
+__global__ void k_seed_fuse(SeedBuf sb, const uint64_t* __restrict__ keys, const uint32_t* __restrict__ order,
+                            uint64_t n, uint64_t empty, unsigned long long* fused) {
+    unsigned long long merged = 0;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
+        if (keys[i] >= empty) continue;
+        PeelSeed* head = sb.s + order[i];
+        if (i > 0 && keys[i - 1] == keys[i] && sb.s[order[i - 1]].cube == head->cube) continue;   // not a run head
+        double w = head->w * exp(-head->tau);
+        uint64_t j = i + 1;
+        for (; j < n && keys[j] == keys[i]; ++j) {
+            PeelSeed* t = sb.s + order[j];
+            if (t->cube != head->cube) break;
+            w += t->w * exp(-t->tau);
+            t->obs = -1;
+            ++merged;
+        }
+        if (j > i + 1) {
+            head->w = w;
+            head->tau = 0.0;
+        }
+    }
+    if (merged) atomicAdd(fused, merged);
+}
+
 // Marks every slot of a fresh seed buffer empty.
 __global__ void k_seed_clear(PeelSeed* s, uint64_t n) {
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
@@ -1004,6 +1060,9 @@ struct thor_ctx {
     void* d_ssort_tmp = nullptr;
     size_t ssort_tmp_bytes = 0;
     double split_ssort = 0.0;
+    uint64_t* d_fkeys = nullptr;           // photon fusing: 2 arrays of 64-bit keys of ssort_cap
+    uint64_t fkeys_cap = 0;
+    unsigned long long* d_fused = nullptr; // rays merged away by fusing in the last call
     hipEvent_t ev_s = nullptr;             // end of the seed sort of a round
 
     // serving (continuous batching of shell-model requests)
@@ -1159,6 +1218,7 @@ thor_status check_opts(const thor_transport_opts* o) {
     if (o->n_obs < 0 || o->n_obs > 6) return fail(THOR_E_INVAL, "n_obs must be 0..6");
     if (o->presort < -1 || o->presort > 2) return fail(THOR_E_INVAL, "presort must be -1, 0, 1 or 2");
     if (o->seed_sort < -1 || o->seed_sort > 1) return fail(THOR_E_INVAL, "seed_sort must be -1, 0 or 1");
+    if (o->fuse_bins < 0 || o->fuse_bins > 4096) return fail(THOR_E_INVAL, "fuse_bins must be in 0..4096");
     for (int i = 0; i < o->n_obs; ++i)
         if (o->obs_axis[i] < 0 || o->obs_axis[i] > 5) return fail(THOR_E_INVAL, "bad observer axis");
     if (o->n_obs > 0) {
@@ -1349,7 +1409,9 @@ bool seed_sort_on(const thor_transport_opts* o) { return o->seed_sort >= 0; }
 
 // Sorts the first n slots of the seed buffer by (axis, pencil, 256-cell
 // block of the front cell) into sb->order (k_seed_keys).
-thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n) {
+thor_status fuse_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n, int m);
+
+thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n, int fuse_bins) {
     if (ctx->ssort_cap < ctx->seed_cap) {
         dfree(ctx, ctx->d_skeys, ctx->ssort_cap * 8);
         dfree(ctx, ctx->d_svals, ctx->ssort_cap * 8);
@@ -1362,6 +1424,7 @@ thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n
         if (s) return s;
         ctx->ssort_cap = ctx->seed_cap;
     }
+    if (fuse_bins > 0) return fuse_seeds(ctx, out, sb, n, fuse_bins);
     uint32_t* keys = ctx->d_skeys;
     uint32_t* keys2 = ctx->d_skeys + ctx->ssort_cap;
     uint32_t* vals = ctx->d_svals;
@@ -1390,6 +1453,50 @@ thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n
     size_t tmp = ctx->ssort_tmp_bytes;
     HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(ctx->d_ssort_tmp, tmp, keys, keys2, vals, vals2, (int64_t)n, 0,
                                                    end_bit, ctx->stream));
+    sb->order = vals2;
+    return THOR_OK;
+}
+
+// Photon fusing (Section 3.4.1): the round's seeds sorted by the fusing key
+// (k_fuse_keys), runs merged (k_seed_fuse); sb->order is the sorted order.
+thor_status fuse_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n, int m) {
+    if (ctx->fkeys_cap < ctx->ssort_cap) {
+        dfree(ctx, ctx->d_fkeys, ctx->fkeys_cap * 16);
+        ctx->d_fkeys = nullptr;
+        ctx->fkeys_cap = 0;
+        thor_status s = dalloc(ctx, (void**)&ctx->d_fkeys, ctx->ssort_cap * 16, "fusing keys");
+        if (s) return s;
+        ctx->fkeys_cap = ctx->ssort_cap;
+    }
+    uint64_t* keys = ctx->d_fkeys;
+    uint64_t* keys2 = ctx->d_fkeys + ctx->fkeys_cap;
+    uint32_t* vals = ctx->d_svals;
+    uint32_t* vals2 = ctx->d_svals + ctx->ssort_cap;
+    const uint64_t top = uint64_t(out.n_obs) * ctx->grid.ncell * uint64_t(out.cube_nb) * uint64_t(m);   // empty key
+    if (top == 0 || top / uint64_t(out.n_obs) / uint64_t(out.cube_nb) / uint64_t(m) != ctx->grid.ncell)
+        return fail(THOR_E_INVAL, "fusing keys overflow 64 bits (grid x bins x fuse_bins too large)");
+    int end_bit = 1;
+    while (end_bit < 64 && (uint64_t(1) << end_bit) <= top) ++end_bit;
+    size_t need = 0;
+    HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, keys2, vals, vals2, (int64_t)n, 0, end_bit,
+                                                   ctx->stream));
+    if (need > ctx->ssort_tmp_bytes) {
+        dfree(ctx, ctx->d_ssort_tmp, ctx->ssort_tmp_bytes);
+        ctx->d_ssort_tmp = nullptr;
+        ctx->ssort_tmp_bytes = 0;
+        thor_status s = dalloc(ctx, &ctx->d_ssort_tmp, need, "seed sort scratch");
+        if (s) return s;
+        ctx->ssort_tmp_bytes = need;
+    }
+    hipLaunchKernelGGL(k_fuse_keys, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->grid, out, *sb, n, m, keys,
+                       vals);
+    HIPCHK(ctx, hipGetLastError());
+    size_t tmp = ctx->ssort_tmp_bytes;
+    HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(ctx->d_ssort_tmp, tmp, keys, keys2, vals, vals2, (int64_t)n, 0,
+                                                   end_bit, ctx->stream));
+    hipLaunchKernelGGL(k_seed_fuse, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, *sb, keys2, vals2, n, top,
+                       ctx->d_fused);
+    HIPCHK(ctx, hipGetLastError());
     sb->order = vals2;
     return THOR_OK;
 }
@@ -1555,7 +1662,7 @@ void thor_destroy(thor_ctx* ctx) {
                     ctx->d_s_models, ctx->d_s_batches, ctx->d_s_cursor, ctx->d_s_pool, ctx->d_s_alive,
                     ctx->d_seeds, ctx->d_seedctl, ctx->d_axr[0], ctx->d_axr[1], ctx->d_axr[2],
                     ctx->d_tail_pk, ctx->d_tail_home, ctx->d_tailctl, ctx->d_xstats, ctx->d_sort,
-                    ctx->d_sort_tmp, ctx->d_skeys, ctx->d_svals, ctx->d_ssort_tmp};
+                    ctx->d_sort_tmp, ctx->d_skeys, ctx->d_svals, ctx->d_ssort_tmp, ctx->d_fkeys, ctx->d_fused};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     for (auto& kv : ctx->s_reqs)
@@ -1902,6 +2009,11 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         const uint64_t* perm = nullptr;
         ctx->split_presort = 0.0;
         ctx->split_ssort = 0.0;
+        if (opt->fuse_bins > 0 && !ctx->d_fused) {
+            s = dalloc(ctx, (void**)&ctx->d_fused, 8, "fusing counter");
+            if (s) return s;
+        }
+        if (ctx->d_fused) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_fused, 1);
         bool any_cell = false, any_spread = false;
         for (size_t i = 0; i < nb; ++i) {
             const thor_source& src = ctx->pending[i].src;
@@ -1983,13 +2095,13 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
                 break;
             }
             SeedBuf sbp = sb;
-            if (seed_sort_on(opt)) {
+            if (seed_sort_on(opt) || opt->fuse_bins > 0) {
                 unsigned long long claimed = 0;
                 HIPCHK(ctx, hipMemcpyAsync(&claimed, ctx->d_seedctl, 8, hipMemcpyDeviceToHost, ctx->stream));
                 HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
                 const uint64_t nseeds = std::min<uint64_t>(claimed, sb.cap);
                 if (nseeds > 1) {
-                    s = sort_seeds(ctx, out, &sbp, nseeds);
+                    s = sort_seeds(ctx, out, &sbp, nseeds, opt->fuse_bins);
                     if (s) return s;
                 }
             }
@@ -2051,6 +2163,11 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
     ctx->last.tail_peel_visits = hx[1 + 8];
     ctx->last.presort_ms = ctx->split_presort;
     ctx->last.seedsort_ms = ctx->split_ssort;
+    if (ctx->d_fused) {
+        unsigned long long f = 0;
+        HIPCHK(ctx, hipMemcpy(&f, ctx->d_fused, 8, hipMemcpyDeviceToHost));
+        ctx->last.peel_fused = f;
+    }
     if (out_stats) *out_stats = ctx->last;
     if (bounded) {
         // work left: queue not drained or packets parked in the pool

@@ -76,7 +76,7 @@ class thor_transport_opts(C.Structure):
                 ("seed_slots", C.c_uint64),
                 ("wide_lanes", C.c_int32), ("park_lanes", C.c_int32), ("refill_64ths", C.c_int32),
                 ("accum", C.c_int32), ("fixed_bits", C.c_int32), ("presort", C.c_int32),
-                ("seed_sort", C.c_int32)]
+                ("seed_sort", C.c_int32), ("fuse_bins", C.c_int32)]
 
 
 STAT_U64 = ("emitted", "escaped", "absorbed", "capped", "handed_off", "n_res", "n_dust",
@@ -89,7 +89,7 @@ class thor_stats(C.Structure):
         ("transport_ms", C.c_double), ("peel_ms", C.c_double), ("passes", C.c_uint64),
         ("tail_ms", C.c_double), ("max_events", C.c_uint64), ("tail_events", C.c_uint64),
         ("tail_main_visits", C.c_uint64), ("tail_peel_visits", C.c_uint64), ("redshifted", C.c_uint64),
-        ("presort_ms", C.c_double), ("seedsort_ms", C.c_double)]
+        ("presort_ms", C.c_double), ("seedsort_ms", C.c_double), ("peel_fused", C.c_uint64)]
 
     def to_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -310,7 +310,8 @@ def make_source(src: dict) -> thor_source:
 def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_events=0,
               waves_per_cu=0, block=0, visits_per_turn=0, use_graph=False,
               inline_peel=False, seed_slots=0, wide_lanes=0, park_lanes=0,
-              refill_64ths=0, accum="f32", fixed_bits=0, presort=0, seed_sort=0) -> thor_transport_opts:
+              refill_64ths=0, accum="f32", fixed_bits=0, presort=0, seed_sort=0,
+              fuse_bins=0) -> thor_transport_opts:
     o = thor_transport_opts()
     o.precision = PREC[precision]
     o.path = PATH[path]
@@ -347,6 +348,7 @@ def make_opts(opts: dict, precision="fp64", path="plain", records=False, step_ev
     o.fixed_bits = int(fixed_bits)
     o.presort = int(presort)
     o.seed_sort = int(seed_sort)
+    o.fuse_bins = int(fuse_bins)
     return o
 
 

@@ -374,3 +374,42 @@ def test_presort_changes_only_the_order(gpu, precision):
     # current cell again there, and which packets those are depends on timing
     for k in ("main_visits", "peel_visits"):
         assert abs(st1[k] / st0[k] - 1) < 1e-3, k
+
+
+# ------------------------------------------------------------ photon fusing
+def test_photon_fusing_bounds(gpu):
+    """Photon fusing (Section 3.4.1) on the 64^3 web box, three observers:
+    histories are untouched; with 4096 sub-bins per cube bin (rays merged only
+    when their frequencies agree to 4 m/s) the cube equals the unfused one to
+    1e-6 in total and 1e-4 on the voxels holding >= 1e-3 of the flux; with one
+    sub-bin per cube bin rays merge more often and the total flux stays within
+    1 % (the merged rays are marched at one frequency of the bin)."""
+    wl = W.web(n_grid=64, fields=W.web_fields(64), cube_npix=32, cube_nb=50)
+    o = wl["opts"]
+    shape = (len(o["observers"]), o["cube"]["ny"], o["cube"]["nx"], o["cube"]["nb"])
+    res = {}
+    for m in (0, 4096, 1):
+        T = gpu.Transport(0)
+        try:
+            T.load(wl["geom"])
+            T.emit(wl["src"], 20000, 0)
+            _, st = T.transport(o, precision="mixed", path="persistent", records=True, fuse_bins=m)
+            res[m] = (T.cube(shape).astype(np.float64), T.records(), st)
+        finally:
+            T.close()
+    c0, r0, s0 = res[0]
+    assert s0["peel_fused"] == 0
+    for m in (4096, 1):
+        c, r, st = res[m]
+        for k in ("n_res", "fate", "dv"):
+            assert np.array_equal(r[k], r0[k]), k
+        tot = abs(c.sum() / c0.sum() - 1)
+        _say("fusing m=%d: %d rays merged (%.3f of the peel contributions), total flux %.2e off, peel visits %d vs %d"
+             % (m, st["peel_fused"], st["peel_fused"] / max(st["peel_contrib"], 1), tot, st["peel_visits"],
+                s0["peel_visits"]))
+        if m == 4096:
+            assert tot < 1e-6
+            sel = c0 >= 1e-3 * c0.sum()
+            assert np.abs(c[sel] / c0[sel] - 1).max() < 1e-4
+        else:
+            assert st["peel_fused"] > 0 and tot < 1e-2
