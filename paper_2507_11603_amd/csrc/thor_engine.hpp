@@ -342,6 +342,8 @@ struct SeedBuf {
     unsigned long long* parked;    // waves with a lane stopped by a full buffer
     uint32_t chunk;                // slots a lane claims at a time, >= observers
     const uint32_t* order;         // peel pass: slots in this order (null: buffer order)
+    uint32_t* keys;                // sort key of each written slot (null: none kept)
+    uint32_t key_blocks;           // pencil blocks of one axis in the keys
 };
 
 // observers the seed path serves (more go through the inline march)
@@ -609,14 +611,39 @@ __device__ __forceinline__ bool seed_make(const GridDev& g, const OutDev& o, con
     return true;
 }
 
+// Sort key of a seed for the peel pass: the ray's axis, the pencil of its
+// front cell and the 256-cell block of that pencil it starts in (one 4 KiB
+// page of 16-byte pencil records), so that once sorted the rays a wave
+// marches together run along the same pencils and pages.
+__device__ __forceinline__ uint32_t seed_key(const GridDev& g, const OutDev& o, const PeelSeed& sd,
+                                             uint32_t key_blocks) {
+    const uint32_t nx = uint32_t(g.nx), ny = uint32_t(g.ny), nz = uint32_t(g.nz);
+    const int a = sel3(sd.obs, o.obs_axis[0], o.obs_axis[1], o.obs_axis[2]) % 3;
+    const uint32_t x = uint32_t(sd.c[0]), y = uint32_t(sd.c[1]), z = uint32_t(sd.c[2]);
+    // pencil index and position along the pencil, as the pencil records are laid out
+    const uint32_t pencil = a == 0 ? z * ny + y : (a == 1 ? z * nx + x : y * nx + x);
+    const uint32_t pos = a == 0 ? x : (a == 1 ? y : z);
+    const uint32_t per = ((a == 0 ? nx : (a == 1 ? ny : nz)) + 255u) >> 8;
+    return uint32_t(a) * key_blocks + pencil * per + (pos >> 8);
+}
+
+// Marks the rest of a lane's run of slots, which it gives up, empty in the
+// sort keys (all ones: after every ray, so the peel pass meets them last).
+__device__ __forceinline__ void seed_release(const SeedBuf& sb, SeedLane& sl) {
+    if (sb.keys)
+        for (uint32_t i = 0; i < sl.left; ++i) sb.keys[sl.cur + i] = ~0u;
+    sl.left = 0;
+}
+
 // The same, written to the lane's claimed slots (room for it was checked
-// before the event).
+// before the event), with its sort key.
 template <class R>
 __device__ __forceinline__ void seed_emit(const GridDev& g, const OutDev& o, const Loc& L, const Fields<R>& f, int ob,
                                           double weight, R dv_peel, Counters& cnt, const SeedBuf& sb, SeedLane& sl) {
     PeelSeed sd;
     if (!seed_make<R>(g, o, L, f, ob, weight, dv_peel, cnt, sd)) return;
     sb.s[sl.cur] = sd;
+    if (sb.keys) sb.keys[sl.cur] = seed_key(g, o, sd, sb.key_blocks);
     ++sl.cur;
     --sl.left;
 }

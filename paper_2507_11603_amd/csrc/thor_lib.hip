@@ -146,6 +146,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
                 base = __shfl(base, leader, 64);
                 if (low) {
                     const uint64_t mine = base + uint64_t(lane_rank(lm)) * sb.chunk;
+                    seed_release(sb, sl);
                     if (mine + sb.chunk <= sb.cap) {
                         sl.cur = mine;
                         sl.left = sb.chunk;
@@ -212,6 +213,7 @@ __global__ __launch_bounds__(256) void k_persistent(GridDev g, const ModelDev* _
             }
         }
     }
+    if constexpr (useq) seed_release(sb, sl);
     if (useq && __ballot(stalled) && (threadIdx.x & 63) == 0) atomicAdd(sb.parked, 1ull);
     if (hand_off && (threadIdx.x & 63) == 0) atomicAdd(tail.gone, 1ull);
     if (pool.alive) {
@@ -314,7 +316,16 @@ __global__ __launch_bounds__(64) void k_tail(GridDev g, const ModelDev* __restri
                     keep = seed_make<R>(g, o, L, j.f, j.ob, double(j.pv) / (2.0 * kPi), j.dvp, cnt, sd);
                 }
                 const uint64_t km = __ballot(keep);
-                if (keep) sb.s[base + lane_rank(km)] = sd;
+                if (keep) {
+                    const uint64_t slot = base + lane_rank(km);
+                    sb.s[slot] = sd;
+                    if (sb.keys) sb.keys[slot] = seed_key(g, o, sd, sb.key_blocks);
+                }
+                // the turn's slots past its kept rays stay empty
+                const uint64_t need = uint64_t(per) * uint64_t(o.n_obs);
+                if (sb.keys)
+                    for (uint64_t i = uint64_t(__popcll(km)) + uint64_t(lane); i < need; i += 64)
+                        sb.keys[base + i] = ~0u;
             }
             // every read of this turn's draws and jobs precedes the next turn's stores
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -648,30 +659,10 @@ __global__ void k_emit_keys(GridDev g, const ModelDev* __restrict__ models, cons
     }
 }
 
-// Sort keys of the seed buffer's first n slots for the peel pass: the ray's
-// axis, the pencil of its front cell and the 256-cell block of that pencil
-// it starts in (one 4 KiB page of 16-byte pencil records), so that the rays
-// a wave marches together run along the same pencils and pages; empty slots
-// sort last.  Rays of one key keep their buffer order (the sort is stable).
-__global__ void k_seed_keys(GridDev g, OutDev o, SeedBuf sb, uint64_t n, uint32_t max_blocks,
-                            uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const uint32_t nx = uint32_t(g.nx), ny = uint32_t(g.ny), nz = uint32_t(g.nz);
-    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x) {
-        const PeelSeed* sd = sb.s + i;
-        const int obs = sd->obs;
-        uint32_t key = 3u * max_blocks;
-        if (obs >= 0) {
-            const int a = sel3(obs, o.obs_axis[0], o.obs_axis[1], o.obs_axis[2]) % 3;
-            const uint32_t x = uint32_t(sd->c[0]), y = uint32_t(sd->c[1]), z = uint32_t(sd->c[2]);
-            // pencil index and position along the pencil, as the pencil records are laid out
-            const uint32_t pencil = a == 0 ? z * ny + y : (a == 1 ? z * nx + x : y * nx + x);
-            const uint32_t pos = a == 0 ? x : (a == 1 ? y : z);
-            const uint32_t per = ((a == 0 ? nx : (a == 1 ? ny : nz)) + 255u) >> 8;
-            key = uint32_t(a) * max_blocks + pencil * per + (pos >> 8);
-        }
-        keys[i] = key;
-        vals[i] = uint32_t(i);
-    }
+// Slot indices 0..n-1 (the values the seed sort permutes).
+__global__ void k_iota_u32(uint32_t* __restrict__ v, uint64_t n) {
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += uint64_t(gridDim.x) * blockDim.x)
+        v[i] = uint32_t(i);
 }
 
 // Keys for photon fusing (Section 3.4.1): observer, the pencil-order index
@@ -1407,11 +1398,10 @@ void launch_tail(thor_ctx* ctx, const StepDesc* d_desc, const OutDev& out, void*
 // Whether the peel pass takes its rays in sorted order (library default: yes).
 bool seed_sort_on(const thor_transport_opts* o) { return o->seed_sort >= 0; }
 
-// Sorts the first n slots of the seed buffer by (axis, pencil, 256-cell
-// block of the front cell) into sb->order (k_seed_keys).
-thor_status fuse_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n, int m);
-
-thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n, int fuse_bins) {
+// Arrays of the seed sort: keys (written by the transport kernels with each
+// seed) and slot indices (0..cap-1, never changed), each with a second copy
+// the sort writes.  Sets sb->keys when 32-bit keys suffice.
+thor_status ensure_seed_sort(thor_ctx* ctx, SeedBuf* sb) {
     if (ctx->ssort_cap < ctx->seed_cap) {
         dfree(ctx, ctx->d_skeys, ctx->ssort_cap * 8);
         dfree(ctx, ctx->d_svals, ctx->ssort_cap * 8);
@@ -1423,19 +1413,37 @@ thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n
         s = dalloc(ctx, (void**)&ctx->d_svals, ctx->seed_cap * 8, "seed sort slots");
         if (s) return s;
         ctx->ssort_cap = ctx->seed_cap;
+        hipLaunchKernelGGL(k_iota_u32, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->d_svals, ctx->ssort_cap);
+        HIPCHK(ctx, hipGetLastError());
     }
+    const uint64_t nx = uint64_t(ctx->grid.nx), ny = uint64_t(ctx->grid.ny), nz = uint64_t(ctx->grid.nz);
+    const uint64_t blocks = std::max(ny * nz * ((nx + 255) / 256),
+                                     std::max(nz * nx * ((ny + 255) / 256), ny * nx * ((nz + 255) / 256)));
+    sb->keys = nullptr;
+    sb->key_blocks = 0;
+    if (3 * blocks < (uint64_t(1) << 32)) {          // else: too many pencils for 32-bit keys, buffer order
+        sb->keys = ctx->d_skeys;
+        sb->key_blocks = uint32_t(blocks);
+    }
+    return THOR_OK;
+}
+
+thor_status fuse_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n, int m);
+
+// Sorts the first n slots of the seed buffer by the keys the transport
+// kernels wrote (seed_key) into sb->order; photon fusing sorts by its own keys.
+thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n, int fuse_bins) {
     if (fuse_bins > 0) return fuse_seeds(ctx, out, sb, n, fuse_bins);
+    if (!sb->keys) return THOR_OK;
     uint32_t* keys = ctx->d_skeys;
     uint32_t* keys2 = ctx->d_skeys + ctx->ssort_cap;
     uint32_t* vals = ctx->d_svals;
     uint32_t* vals2 = ctx->d_svals + ctx->ssort_cap;
-    const uint64_t nx = uint64_t(ctx->grid.nx), ny = uint64_t(ctx->grid.ny), nz = uint64_t(ctx->grid.nz);
-    const uint64_t max_blocks = std::max(ny * nz * ((nx + 255) / 256),
-                                         std::max(nz * nx * ((ny + 255) / 256), ny * nx * ((nz + 255) / 256)));
-    const uint64_t top = 3 * max_blocks;             // the key of an empty slot
-    if (top >= (uint64_t(1) << 32)) return THOR_OK;  // too many pencils for 32-bit keys: buffer order
+    // slots claimed but left empty keep stale keys: they sort anywhere and the
+    // pass skips them
+    const uint64_t top = 3 * uint64_t(sb->key_blocks);
     int end_bit = 1;
-    while (end_bit < 32 && (uint64_t(1) << end_bit) <= top) ++end_bit;
+    while (end_bit < 32 && (uint64_t(1) << end_bit) < top) ++end_bit;
     size_t need = 0;
     HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need, keys, keys2, vals, vals2, (int64_t)n, 0, end_bit,
                                                    ctx->stream));
@@ -1447,9 +1455,6 @@ thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n
         if (s) return s;
         ctx->ssort_tmp_bytes = need;
     }
-    hipLaunchKernelGGL(k_seed_keys, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->grid, out, *sb, n,
-                       uint32_t(max_blocks), keys, vals);
-    HIPCHK(ctx, hipGetLastError());
     size_t tmp = ctx->ssort_tmp_bytes;
     HIPCHK(ctx, hipcub::DeviceRadixSort::SortPairs(ctx->d_ssort_tmp, tmp, keys, keys2, vals, vals2, (int64_t)n, 0,
                                                    end_bit, ctx->stream));
@@ -1460,6 +1465,7 @@ thor_status sort_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n
 // Photon fusing (Section 3.4.1): the round's seeds sorted by the fusing key
 // (k_fuse_keys), runs merged (k_seed_fuse); sb->order is the sorted order.
 thor_status fuse_seeds(thor_ctx* ctx, const OutDev& out, SeedBuf* sb, uint64_t n, int m) {
+    sb->keys = nullptr;                 // the transport's keys are not used here
     if (ctx->fkeys_cap < ctx->ssort_cap) {
         dfree(ctx, ctx->d_fkeys, ctx->fkeys_cap * 16);
         ctx->d_fkeys = nullptr;
@@ -1984,6 +1990,11 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
             }
             if (s) return s;
             sb.chunk = uint32_t(std::max<uint64_t>(ev_rays, std::min<uint64_t>(kSeedChunk, slots / (2 * lanes))));
+            if (seed_sort_on(opt) || opt->fuse_bins > 0) {
+                s = ensure_seed_sort(ctx, &sb);
+                if (s) return s;
+                if (opt->fuse_bins > 0) { sb.keys = nullptr; sb.key_blocks = 0; }
+            }
             if (!bounded) {
                 // packets wait in the pool while the buffer is full
                 s = ensure_pool(ctx, uint64_t(gsize) * block, opt->precision);
