@@ -21,7 +21,7 @@
 #define THOR_PEEL_LOOKAHEAD 2
 #endif
 #ifndef THOR_PASS_LOOKAHEAD
-#define THOR_PASS_LOOKAHEAD 6
+#define THOR_PASS_LOOKAHEAD 8
 #endif
 
 namespace thor {

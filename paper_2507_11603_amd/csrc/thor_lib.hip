@@ -398,7 +398,7 @@ __device__ __forceinline__ void deposit_lds(uint32_t* keys, V* vals, const OutDe
     agg_flush<V>(o, ci, v);
 }
 
-template <class R, class V>
+template <class R, class V, class AR>
 __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, const SeedBuf& sb,
                                           unsigned long long* work, unsigned long long* gstats) {
     // FP32 (mixed) rays read the pencil records of their axis: consecutive
@@ -413,7 +413,7 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
     bool pos = true;
     double lo = 0.0, dx = 0.0, pa = 0.0, tau = 0.0, w = 0.0;
     int64_t stride = 0, idx = 0;
-    const AxisRec* axr = nullptr;
+    const AR* axr = nullptr;
     uint64_t ci = 0;
     R dvp = R(0);
     uint64_t cur = 0, end = 0;             // the wave's chunk, [cur, end)
@@ -475,7 +475,8 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
                         idx = int64_t(a == 0 ? (z * g.ny + y) * g.nx + x
                                              : (a == 1 ? (z * g.nx + x) * g.ny + y : (y * g.nx + x) * g.nz + z));
                         stride = pos ? 1 : -1;
-                        axr = sel3(a, g.axr[0], g.axr[1], g.axr[2]);
+                        if constexpr (sizeof(AR) == sizeof(AxisRec3)) axr = sel3(a, g.axc[0], g.axc[1], g.axc[2]);
+                        else axr = sel3(a, g.axr[0], g.axr[1], g.axr[2]);
                     } else {
                         idx = int64_t(cell_index(g, sd.c));
                         stride = (a == 0 ? int64_t(1) : (a == 1 ? int64_t(g.nx) : int64_t(g.nx) * int64_t(g.ny))) *
@@ -503,7 +504,7 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
             bool cut = false;
             const double href = sel3(a, g.href[0], g.href[1], g.href[2]);
             if constexpr (kAxis) {
-                AxisRec rc[kLook];
+                AR rc[kLook];
 #pragma unroll
                 for (int j = 0; j < kLook; ++j)
                     if (j < mm) rc[j] = axr[idx + int64_t(j) * stride];
@@ -512,7 +513,7 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
                     if (j >= mm || cut) break;
                     // every cell after the event's is crossed whole: segment = cell width
                     cnt.peel_visits++;
-                    if (rc[j].k0 > 0.0f || rc[j].kd > 0.0f) {
+                    if (rc[j].k0 > 0.0f || rec_kd(rc[j]) > 0.0f) {
                         const float av = float(kDampTimesVth) * rc[j].ivth;
                         if (g.hubble > 0.0) {
                             // entry face of cell j, the Hubble flow there, sub-steps
@@ -526,11 +527,11 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
                             const double ds = dx / n;
                             for (int q = 0; q < n; ++q) {
                                 const float x = float(u0 - g.hubble * ((q + 0.5) * ds)) * rc[j].ivth;
-                                tau += (double(rc[j].k0) * double(voigt32(av, x, daw)) + double(rc[j].kd)) * ds;
+                                tau += (double(rc[j].k0) * double(voigt32(av, x, daw)) + double(rec_kd(rc[j]))) * ds;
                             }
                         } else {
                             const float x = (dvp - (pos ? rc[j].v : -rc[j].v)) * rc[j].ivth;
-                            tau += (double(rc[j].k0) * double(voigt32(av, x, daw)) + double(rc[j].kd)) * dx;
+                            tau += (double(rc[j].k0) * double(voigt32(av, x, daw)) + double(rec_kd(rc[j]))) * dx;
                         }
                         cut = tau > o.tau_cut;
                     }
@@ -585,21 +586,23 @@ __device__ __forceinline__ void peel_pass(const GridDev& g, const OutDev& o, con
 // FP32 pass: four waves per SIMD (at most 128 VGPRs), each lane with the
 // records of THOR_PASS_LOOKAHEAD cells in flight: on the 1024^3 web box six
 // cells at four waves beat two at six waves by 6 % (a wave's gathers are
-// latency-bound; more of them per lane hide more of it).
+// latency-bound; more of them per lane hide more of it), and with 12-byte
+// records eight cells beat six by 1.3 %.
 // V: float32 cube, or unsigned long long for the fixed-point cube.
 #ifndef THOR_PEEL_WAVES
 #define THOR_PEEL_WAVES 4
 #endif
-template <class V>
+// AR: the pencil record (AxisRec, or AxisRec3 on grids without dust).
+template <class V, class AR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(THOR_PEEL_WAVES)))
 void k_peel_pass_f32(GridDev g, OutDev o, SeedBuf sb, unsigned long long* work, unsigned long long* gstats) {
-    peel_pass<float, V>(g, o, sb, work, gstats);
+    peel_pass<float, V, AR>(g, o, sb, work, gstats);
 }
 
 template <class V>
 __global__ __launch_bounds__(256) void k_peel_pass_f64(GridDev g, OutDev o, SeedBuf sb, unsigned long long* work,
                                                        unsigned long long* gstats) {
-    peel_pass<double, V>(g, o, sb, work, gstats);
+    peel_pass<double, V, AxisRec>(g, o, sb, work, gstats);
 }
 
 // The fixed-point cube as float32 (units of 1/scale).
@@ -756,20 +759,22 @@ __global__ void k_pack_grid(const float* __restrict__ n, const float* __restrict
 
 // Pencil-order copy of the cell records for rays along `axis`: index with
 // that axis fastest ([z][y][x] for x, [z][x][y] for y, [y][x][z] for z).
-__global__ void k_pack_axis(const CellRec* __restrict__ rec, AxisRec* __restrict__ out, int axis, int nx, int ny,
+template <class AR>
+__global__ void k_pack_axis(const CellRec* __restrict__ rec, AR* __restrict__ out, int axis, int nx, int ny,
                             int nz, double sigma_d, uint64_t count) {
     for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
          i += uint64_t(gridDim.x) * blockDim.x) {
         const uint64_t x = i % uint64_t(nx), y = (i / uint64_t(nx)) % uint64_t(ny), z = i / (uint64_t(nx) * ny);
         const CellRec r = rec[i];
-        AxisRec o;
+        AR o;
         o.v = axis == 0 ? r.lo.x : (axis == 1 ? r.lo.y : r.lo.z);
         if (r.lo.w > 0.0f) {
             o.ivth = float(1.0 / sqrt(kVth2PerT * double(r.hi.x)));
             o.k0 = r.hi.w;
-            o.kd = float(sigma_d * double(r.lo.w));
+            if constexpr (sizeof(AR) == sizeof(AxisRec)) o.kd = float(sigma_d * double(r.lo.w));
         } else {
-            o.ivth = 0.0f; o.k0 = 0.0f; o.kd = 0.0f;
+            o.ivth = 0.0f; o.k0 = 0.0f;
+            if constexpr (sizeof(AR) == sizeof(AxisRec)) o.kd = 0.0f;
         }
         const uint64_t j = axis == 0 ? i : (axis == 1 ? (z * nx + x) * ny + y : (y * nx + x) * nz + z);
         out[j] = o;
@@ -1025,7 +1030,8 @@ struct thor_ctx {
     unsigned long long* h_s_done = nullptr;    // pinned mirror of d_done
     unsigned long long* h_s_misc = nullptr;    // pinned: counters then cursor
     hipStream_t cap_stream = nullptr;      // private stream for graph capture
-    AxisRec* d_axr[3] = {nullptr, nullptr, nullptr};   // pencil records per axis (mixed peel pass)
+    void* d_axr[3] = {nullptr, nullptr, nullptr};      // pencil records per axis (mixed peel pass)
+    uint64_t axr_bytes[3] = {0, 0, 0};
     PeelSeed* d_seeds = nullptr;           // peel seed buffer of the grid persistent path
     uint64_t seed_cap = 0;                 // slots
     unsigned long long* d_seedctl = nullptr;   // claimed slots, parked waves, then kXcds pass work counters
@@ -1553,9 +1559,15 @@ thor_status ensure_seeds(thor_ctx* ctx, uint64_t slots, SeedBuf* sb) {
 
 template <class R, class V>
 void launch_peel_pass_v(thor_ctx* ctx, const OutDev& out, const SeedBuf& sb) {
-    if constexpr (sizeof(R) == 4)
-        hipLaunchKernelGGL(k_peel_pass_f32<V>, dim3(ctx->num_cu * 6), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
-                           ctx->d_seedctl + 2, ctx->d_stats);
+    const bool compact = !(ctx->grid.sigma_d > 0.0);     // the records ensure_axis_records built
+    if constexpr (sizeof(R) == 4) {
+        if (compact)
+            hipLaunchKernelGGL((k_peel_pass_f32<V, AxisRec3>), dim3(ctx->num_cu * 6), dim3(256), 0, ctx->stream,
+                               ctx->grid, out, sb, ctx->d_seedctl + 2, ctx->d_stats);
+        else
+            hipLaunchKernelGGL((k_peel_pass_f32<V, AxisRec>), dim3(ctx->num_cu * 6), dim3(256), 0, ctx->stream,
+                               ctx->grid, out, sb, ctx->d_seedctl + 2, ctx->d_stats);
+    }
     else
         hipLaunchKernelGGL(k_peel_pass_f64<V>, dim3(ctx->num_cu * 4), dim3(256), 0, ctx->stream, ctx->grid, out, sb,
                            ctx->d_seedctl + 2, ctx->d_stats);
@@ -1692,23 +1704,37 @@ void thor_destroy(thor_ctx* ctx) {
 
 void free_axis_records(thor_ctx* ctx) {
     for (int a = 0; a < 3; ++a) {
-        dfree(ctx, ctx->d_axr[a], ctx->grid.ncell * sizeof(AxisRec));
+        dfree(ctx, ctx->d_axr[a], ctx->axr_bytes[a]);
         ctx->d_axr[a] = nullptr;
+        ctx->axr_bytes[a] = 0;
         ctx->grid.axr[a] = nullptr;
+        ctx->grid.axc[a] = nullptr;
     }
 }
 
 // Pencil records for peel rays along axis a (mixed precision), built once per
-// grid from the cell records; staging, outside the timed transport.
+// grid from the cell records; staging, outside the timed transport.  Compact
+// (12 B) when the grid has no dust.
 thor_status ensure_axis_records(thor_ctx* ctx, int a) {
     if (ctx->d_axr[a]) return THOR_OK;
     const uint64_t cells = ctx->grid.ncell;
-    thor_status s = dalloc(ctx, (void**)&ctx->d_axr[a], cells * sizeof(AxisRec), "axis records");
+    const bool compact = !(ctx->grid.sigma_d > 0.0);
+    const uint64_t bytes = cells * (compact ? sizeof(AxisRec3) : sizeof(AxisRec));
+    thor_status s = dalloc(ctx, &ctx->d_axr[a], bytes, "axis records");
     if (s) return s;
-    hipLaunchKernelGGL(k_pack_axis, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->d_rec, ctx->d_axr[a], a,
-                       ctx->grid.nx, ctx->grid.ny, ctx->grid.nz, ctx->grid.sigma_d, cells);
+    ctx->axr_bytes[a] = bytes;
+    if (compact) {
+        hipLaunchKernelGGL(k_pack_axis<AxisRec3>, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->d_rec,
+                           static_cast<AxisRec3*>(ctx->d_axr[a]), a, ctx->grid.nx, ctx->grid.ny, ctx->grid.nz,
+                           ctx->grid.sigma_d, cells);
+        ctx->grid.axc[a] = static_cast<const AxisRec3*>(ctx->d_axr[a]);
+    } else {
+        hipLaunchKernelGGL(k_pack_axis<AxisRec>, dim3(ctx->num_cu * 8), dim3(256), 0, ctx->stream, ctx->d_rec,
+                           static_cast<AxisRec*>(ctx->d_axr[a]), a, ctx->grid.nx, ctx->grid.ny, ctx->grid.nz,
+                           ctx->grid.sigma_d, cells);
+        ctx->grid.axr[a] = static_cast<const AxisRec*>(ctx->d_axr[a]);
+    }
     HIPCHK(ctx, hipGetLastError());
-    ctx->grid.axr[a] = ctx->d_axr[a];
     return THOR_OK;
 }
 
