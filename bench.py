@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--wide-lanes", type=int, default=0)
     ap.add_argument("--park-lanes", type=int, default=0)
     ap.add_argument("--refill-64ths", type=int, default=0)
+    ap.add_argument("--seed-slots", type=int, default=0,
+                    help="peel-seed buffer slots (48 B each; 0: library default, 2^28 to 2^30 by free memory)")
     ap.add_argument("--fuse-bins", type=int, default=0,
                     help="photon fusing of peel rays: sub-bins per cube frequency bin (0: off)")
     ap.add_argument("--seed-sort", type=int, default=0,
@@ -552,7 +554,7 @@ def main():
     kw = dict(precision=a.precision, path="persistent", waves_per_cu=a.waves_per_cu, block=a.block or 256,
               visits_per_turn=a.turn_visits or 256, wide_lanes=a.wide_lanes or 8, park_lanes=a.park_lanes or 32,
               refill_64ths=a.refill_64ths or 16, presort=a.presort, seed_sort=a.seed_sort,
-              fuse_bins=a.fuse_bins)
+              fuse_bins=a.fuse_bins, seed_slots=a.seed_slots)
     wl, tot, dt, plain, host = web_headline(a, kw)
     print("[bench] web %d^3: %d packets in %.2f s" % (a.grid, tot["emitted"], dt), file=sys.stderr, flush=True)
     scat = tot["n_res"] + tot["n_dust"]
@@ -585,7 +587,7 @@ def main():
                    "precision": a.precision, "path": "persistent",
                    "knobs": {k: kw[k] for k in ("waves_per_cu", "block", "visits_per_turn", "wide_lanes",
                                                 "park_lanes", "refill_64ths", "presort", "seed_sort",
-                                                "fuse_bins")},
+                                                "fuse_bins", "seed_slots")},
                    "autotuned": kw.get("autotuned")},
         "packets_per_s": tot["emitted"] / dt,
         "scatterings_per_packet": scat / max(tot["emitted"], 1),

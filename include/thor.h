@@ -197,9 +197,11 @@ typedef struct {
                                    instead of the peel-seed pass */
     int32_t records;            /* 1: keep per-packet records of this call */
     uint64_t seed_slots;        /* PERSISTENT, grid, 1-3 observers: slots (48 B each) of
-                                   the peel-seed buffer; 0 = 2^28 (12.9 GB), or
-                                   max(2^26, 128 per lane of the launch) when that
-                                   cannot be allocated; at least observers x lanes.  A full
+                                   the peel-seed buffer; 0 = the largest power of two
+                                   from 2^28 to 2^30 whose seeds and sort arrays (64 B
+                                   a slot) fit in half the free device memory (and of the
+                                   budget left), else 2^28 (12.9 GB), else max(2^26, 128
+                                   per lane of the launch); at least observers x lanes.  A full
                                    buffer ends a transport kernel early (packets wait
                                    in device memory), the peel pass empties it and
                                    transport resumes. */

@@ -1099,8 +1099,11 @@ thor_status dalloc(thor_ctx* ctx, void** p, uint64_t bytes, const char* what) {
         return fail(THOR_E_BUDGET, "%s: %llu bytes exceed the HBM budget (%llu of %llu used)", what,
                     (unsigned long long)bytes, (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
     hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) return fail(THOR_E_NOMEM, "%s: hipMalloc(%llu) failed: %s", what,
-                                     (unsigned long long)bytes, hipGetErrorString(e));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();   // a caller may fall back to a smaller size: leave no error behind
+        return fail(THOR_E_NOMEM, "%s: hipMalloc(%llu) failed: %s", what, (unsigned long long)bytes,
+                    hipGetErrorString(e));
+    }
     ctx->used += bytes;
     return THOR_OK;
 }
@@ -1998,18 +2001,37 @@ thor_status thor_transport(thor_ctx* ctx, const thor_transport_opts* opt, thor_s
         std::memset(&sb, 0, sizeof sb);
         const bool seeds = grid && opt->n_obs > 0 && opt->n_obs <= kMaxSeedObs && !opt->inline_peel;
         if (seeds) {
-            // default: 2^28 slots (12.9 GB; fewer transport / peel-pass rounds),
-            // else 2^26 (3.2 GB) or two runs of kSeedChunk per lane when that
-            // much cannot be had; a smaller buffer shrinks the runs, down to
-            // one event's rays
+            // default: the largest power of two from 2^28 to 2^30 slots whose
+            // seeds and sort arrays (64 B a slot) take at most half of the device
+            // memory free (and of the budget left); else 2^28 (12.9 GB), else
+            // 2^26 (3.2 GB) or two runs of kSeedChunk per lane when that much
+            // cannot be had; a smaller buffer shrinks the runs, down to one
+            // event's rays.  More seeds per round put more rays on each pencil,
+            // so the rays a peel-pass wave marches share more cache lines.
             const uint64_t lanes = uint64_t(gsize) * block;
             const uint64_t ev_rays = uint64_t(opt->n_obs);
             const uint64_t small = std::max<uint64_t>(uint64_t(1) << 26, lanes * 2 * kSeedChunk);
-            uint64_t slots = opt->seed_slots ? opt->seed_slots : std::max<uint64_t>(uint64_t(1) << 28, small);
+            const uint64_t base = std::max<uint64_t>(uint64_t(1) << 28, small);
+            uint64_t slots = opt->seed_slots;
+            if (!slots) {
+                size_t free_b = 0, total_b = 0;
+                HIPCHK(ctx, hipMemGetInfo(&free_b, &total_b));
+                // what this context already holds for seeds counts as free
+                uint64_t avail = uint64_t(free_b) + ctx->seed_cap * sizeof(PeelSeed) + ctx->ssort_cap * 16;
+                if (ctx->budget)
+                    avail = std::min<uint64_t>(avail, ctx->budget - std::min(ctx->used, ctx->budget) +
+                                                          ctx->seed_cap * sizeof(PeelSeed) + ctx->ssort_cap * 16);
+                slots = base;
+                while (slots < (uint64_t(1) << 30) && 2 * slots * (sizeof(PeelSeed) + 16) <= avail / 2) slots *= 2;
+            }
             if (slots < lanes * ev_rays)
                 return fail(THOR_E_INVAL, "seed_slots must be at least %llu (observers per lane)",
                             (unsigned long long)(lanes * ev_rays));
             s = ensure_seeds(ctx, slots, &sb);
+            if (s && !opt->seed_slots && slots > base) {
+                slots = base;
+                s = ensure_seeds(ctx, slots, &sb);
+            }
             if (s && !opt->seed_slots && slots != small) {
                 slots = small;
                 s = ensure_seeds(ctx, slots, &sb);
