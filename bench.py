@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--plain-packets", type=int, default=20_000,
                     help="packets of the plain FP64 path on the same box (0: skip)")
     ap.add_argument("--shell", type=int, default=20, help="batches of 1e6 packets of the 128^3 shell (0: skip)")
+    ap.add_argument("--shell-only", type=int, default=0, help="print only the shell record")
     ap.add_argument("--sphere", type=int, default=100_000,
                     help="packets of the meshless tau0 = 1e5 sphere, one persistent call (0: skip)")
     ap.add_argument("--sphere-only", type=int, default=0, help="print only the sphere record")
@@ -250,30 +251,53 @@ def web_headline(a, kw):
     return wl, tot, dt, plain, host
 
 
-def roofline_web(tot):
-    split = kernel_split(tot)
-    dom = max(split, key=lambda k: split[k]["ms"])
-    d = split[dom]
+# What bounds each kernel of the grid path (counters on the 1024^3 box): the
+# peel pass gathers pencil records (HBM), the transport and tail kernels issue
+# VALU instructions on divergent histories (ALU).
+KERNEL_BOUND = {"transport": "alu", "tail": "alu", "peel_pass": "hbm"}
+
+
+def kernel_roofline(split, k):
+    """Roofline block of kernel k: algorithmic bytes (20 B per cell visit) per
+    launch over its average launch time against HBM; for an ALU-bound kernel
+    the achieved figure is its VALU instruction rate, which needs a counter
+    record (attach_counters) and stays None without one."""
+    d = split[k]
     launches = max(d["launches"], 1)
-    roof = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": d["achieved_GBps"], "peak": HBM_PEAK_GBS,
+    roof = {"bound": "hbm", "kernel": KERNEL_NAMES[k], "achieved": d["achieved_GBps"], "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": d["hbm_frac"], "traffic": None,
             "launches": d["launches"], "avg_launch_ms": d["ms"] / launches,
             "algorithmic_bytes_per_launch": BYTES_PER_VISIT * d["visits"] / launches,
             "bytes_per_visit": BYTES_PER_VISIT}
-    return roof, split, dom
+    if KERNEL_BOUND[k] == "alu":
+        roof.update(bound="alu", achieved=None, peak=VALU_PEAK_IPS, unit="wave64 VALU instructions/s", frac=None,
+                    hbm_achieved_GBps=d["achieved_GBps"], hbm_frac=d["hbm_frac"])
+    return roof
 
 
-def attach_traffic(roof, split, dom, rec, packets):
-    """HBM bytes per launch of the dominant kernel from a counter record of
-    the same workload (per packet there, scaled to this run's launches)."""
-    kname = {"transport": "k_persistent", "tail": "k_tail", "peel_pass": "k_peel_pass"}[dom]
+def roofline_web(tot):
+    split = kernel_split(tot)
+    dom = max(split, key=lambda k: split[k]["ms"])
+    return kernel_roofline(split, dom), split, dom
+
+
+def attach_counters(roof, split, k, rec, packets):
+    """From a counter record of the same workload (per packet there, scaled to
+    this run): HBM bytes per launch of kernel k, and for an ALU-bound kernel
+    its VALU instructions over its device time."""
+    kname = {"transport": "k_persistent", "tail": "k_tail", "peel_pass": "k_peel_pass"}[k]
     kr = rec["kernels"].get(kname)
-    if not kr or "read_bytes_per_batch" not in kr:
+    if not kr:
         return
-    per_packet = (kr["read_bytes_per_batch"] + kr["write_bytes_per_batch"]) / max(rec["packets"], 1)
-    launches = max(split[dom]["launches"], 1)
-    roof["traffic"] = per_packet * packets / launches
-    roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes_per_launch"]
+    scale = packets / max(rec["packets"], 1)
+    launches = max(split[k]["launches"], 1)
+    if "read_bytes_per_batch" in kr:
+        roof["traffic"] = (kr["read_bytes_per_batch"] + kr["write_bytes_per_batch"]) * scale / launches
+        roof["traffic_over_algorithmic"] = roof["traffic"] / roof["algorithmic_bytes_per_launch"]
+    if roof["bound"] == "alu" and "valu_insts_per_batch" in kr and split[k]["ms"] > 0:
+        ips = kr["valu_insts_per_batch"] * scale / (split[k]["ms"] / 1e3)
+        roof.update(achieved=ips, frac=ips / VALU_PEAK_IPS, valu_busy_pct=kr.get("valu_busy_pct"),
+                    valu_lane_util_pct=kr.get("valu_lane_util_pct"))
     roof["counters"] = rec["path"]
 
 
@@ -338,7 +362,7 @@ def shell_box(a):
            "packets_per_s": st["emitted"] / dt, "longest_history": st["max_events"],
            "kernels": split, "dominant": KERNEL_NAMES[dom]}
     rec = counter_record("shell128")
-    roof = {"bound": "valu", "kernel": KERNEL_NAMES[dom], "achieved": None, "peak": VALU_PEAK_IPS,
+    roof = {"bound": "alu", "kernel": KERNEL_NAMES[dom], "achieved": None, "peak": VALU_PEAK_IPS,
             "unit": "wave64 VALU instructions/s", "frac": None}
     if rec is not None and dom in ("transport", "tail"):
         kr = rec["kernels"].get({"transport": "k_persistent", "tail": "k_tail"}[dom], {})
@@ -404,7 +428,7 @@ def sphere_box(a):
            "scatterings_per_packet": scat / max(st["emitted"], 1), "kernel_ms": st["kernel_ms"],
            "upar_trials_per_scattering": st["upar_trials"] / max(st["n_res"], 1),
            "longest_history": st["max_events"], "kernels": split}
-    roof = {"bound": "valu", "kernel": "k_persistent<float, false, false>", "achieved": None,
+    roof = {"bound": "alu", "kernel": "k_persistent<float, false, false>", "achieved": None,
             "peak": VALU_PEAK_IPS, "unit": "wave64 VALU instructions/s", "frac": None}
     rec = counter_record("sphere")
     if rec is not None:
@@ -548,6 +572,9 @@ def main():
     if a.sphere_only:
         print(json.dumps({"sphere": sphere_box(a)}), flush=True)
         return
+    if a.shell_only:
+        print(json.dumps({"shell": shell_box(a)}), flush=True)
+        return
     if a.mg2_only:
         print(json.dumps({"mg2": mg2_box(a)}), flush=True)
         return
@@ -560,9 +587,11 @@ def main():
     scat = tot["n_res"] + tot["n_dust"]
     value = scat / dt
     roof, split, dom = roofline_web(tot)
+    gather = kernel_roofline(split, "peel_pass")
     rec = counter_record("web%d" % a.grid) if a.precision == "mixed" else None
     if rec is not None and rec.get("fields") == a.fields:
-        attach_traffic(roof, split, dom, rec, a.packets)
+        attach_counters(roof, split, dom, rec, a.packets * a.steps)
+        attach_counters(gather, split, "peel_pass", rec, a.packets * a.steps)
     visits = tot["main_visits"] + tot["peel_visits"]
     ks = tot["kernel_ms"] / 1e3
     path_gbs = BYTES_PER_VISIT * visits / ks / 1e9
@@ -595,6 +624,8 @@ def main():
         "path_hbm": {"achieved": path_gbs, "frac": path_gbs / HBM_PEAK_GBS, "kernel_ms": tot["kernel_ms"],
                      "main_visits": tot["main_visits"], "peel_visits": tot["peel_visits"]},
         "roofline": roof,
+        # the peel pass's HBM-gather figure, whichever kernel dominates
+        "hbm_gather": gather,
         "kernels": split,
         "passes": tot["passes"],
         "presort_ms": tot.get("presort_ms", 0.0),

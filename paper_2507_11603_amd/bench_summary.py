@@ -41,12 +41,24 @@ def render(d: dict, command: str, stats: str | None) -> str:
                      % (name, k[name]["ms"], k[name]["launches"], k[name]["visits"], k[name]["achieved_GBps"],
                         k[name]["hbm_frac"]))
     L.append("* presort of the queue: %.1f ms" % d.get("presort_ms", 0.0))
-    L.append("* roofline (dominant kernel `%s`): %.1f GB/s = %.3f of %.0f GB/s; average launch %.3f ms; "
-             "HBM traffic per launch %s%s" % (
-                 r["kernel"], r["achieved"], r["frac"], r["peak"], r["avg_launch_ms"],
-                 "%.4g B (%.2f of the algorithmic bytes)" % (r["traffic"], r["traffic_over_algorithmic"])
-                 if r.get("traffic") else "not measured for these sources",
-                 ", from `%s`" % r["counters"] if r.get("counters") else ""))
+    def roof_line(title, r):
+        traffic = ("%.4g B (%.2f of the algorithmic bytes)" % (r["traffic"], r["traffic_over_algorithmic"])
+                   if r.get("traffic") else "not measured for these sources")
+        src = ", from `%s`" % r["counters"] if r.get("counters") else ""
+        if r["bound"] == "alu":
+            rate = ("%.4g wave64 VALU instructions/s = %.3f of %.4g (VALU %.0f %% busy, %.0f %% lane utilisation)"
+                    % (r["achieved"], r["frac"], r["peak"], r.get("valu_busy_pct") or 0.0,
+                       r.get("valu_lane_util_pct") or 0.0) if r.get("achieved") else "VALU rate not measured")
+            return ("* %s `%s`, bound by VALU issue: %s; average launch %.3f ms; algorithmic bytes %.1f GB/s "
+                    "(%.3f of HBM); HBM traffic per launch %s%s"
+                    % (title, r["kernel"], rate, r["avg_launch_ms"], r["hbm_achieved_GBps"], r["hbm_frac"],
+                       traffic, src))
+        return ("* %s `%s`, bound by HBM gathers: %.1f GB/s = %.3f of %.0f GB/s; average launch %.3f ms; "
+                "HBM traffic per launch %s%s" % (title, r["kernel"], r["achieved"], r["frac"], r["peak"],
+                                                 r["avg_launch_ms"], traffic, src))
+    L.append(roof_line("roofline (dominant kernel)", r))
+    if "hbm_gather" in d and d["hbm_gather"]["kernel"] != r["kernel"]:
+        L.append(roof_line("HBM-gather roofline of the peel pass", d["hbm_gather"]))
     if "plain_fp64" in d:
         p = d["plain_fp64"]
         L.append("* plain FP64 path (%s): %.4g scatterings/s -> the persistent mixed path is %.0fx faster"

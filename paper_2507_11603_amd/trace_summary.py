@@ -72,11 +72,18 @@ def summarise(trace_dir: str, first_call: int, calls: int, bench: dict | None, c
         lines.append("| %s | %d | %.2f | %.3f |" % (k, n, ms, ms / n))
     if bench:
         roof = bench.get("roofline", {})
-        lines += ["", "bench.py (HIP events on the library stream) for the dominant kernel `%s`: %d launches, "
-                  "average %.3f ms, %.4g algorithmic bytes per launch, %.1f GB/s = %.3f of %.0f GB/s."
-                  % (roof.get("kernel"), roof.get("launches", 0), roof.get("avg_launch_ms", 0.0),
-                     roof.get("algorithmic_bytes_per_launch", 0.0), roof.get("achieved", 0.0),
-                     roof.get("frac", 0.0), roof.get("peak", 0.0))]
+        if roof.get("bound") == "alu":
+            rate = ("%.4g wave64 VALU instructions/s = %.3f of %.4g" % (roof["achieved"], roof["frac"], roof["peak"])
+                    if roof.get("achieved") else "VALU rate not measured")
+            lines += ["", "bench.py (HIP events on the library stream) for the dominant kernel `%s` (bound by "
+                      "VALU issue): %d launches, average %.3f ms, %s." % (roof.get("kernel"), roof.get("launches", 0),
+                                                                        roof.get("avg_launch_ms", 0.0), rate)]
+        else:
+            lines += ["", "bench.py (HIP events on the library stream) for the dominant kernel `%s`: %d launches, "
+                      "average %.3f ms, %.4g algorithmic bytes per launch, %.1f GB/s = %.3f of %.0f GB/s."
+                      % (roof.get("kernel"), roof.get("launches", 0), roof.get("avg_launch_ms", 0.0),
+                         roof.get("algorithmic_bytes_per_launch", 0.0), roof.get("achieved", 0.0),
+                         roof.get("frac", 0.0), roof.get("peak", 0.0))]
         kshort = (roof.get("kernel") or "").split("<")[0]
         tr = [(n, ms) for k, (n, ms) in _table(sel) if kshort and kshort in k]
         if tr:

@@ -57,3 +57,34 @@ def test_totals_over_calls_and_headline_roofline():
     assert abs(roof["algorithmic_bytes_per_launch"] - 20 * (2000 - 100) / 4) < 1e-9
     assert abs(roof["achieved"] - roof["algorithmic_bytes_per_launch"] / 0.030 / 1e9) < 1e-6
     assert abs(roof["frac"] - roof["achieved"] / 8000.0) < 1e-12
+
+
+def test_alu_bound_dominant_kernel_and_counter_record():
+    """When the transport kernel has the most device time the headline
+    roofline is its VALU issue rate (bound "alu"), taken from the counter
+    record scaled to this run's packets; without a record it stays None.  The
+    peel pass's HBM-gather block is reported beside it."""
+    b = _bench()
+    st = {"transport_ms": 700.0, "tail_ms": 10.0, "peel_ms": 600.0, "passes": 7, "kernel_ms": 1310.0,
+          "main_visits": 1000, "peel_visits": 30000, "peel_contrib": 500, "tail_main_visits": 10,
+          "tail_peel_visits": 10, "tail_events": 5, "max_events": 9}
+    tot = b.add_stats(None, st)
+    roof, split, dom = b.roofline_web(tot)
+    assert dom == "transport" and roof["bound"] == "alu" and roof["kernel"].startswith("k_persistent")
+    assert roof["achieved"] is None and roof["frac"] is None
+    assert roof["peak"] == 256 * 4 * 2.4e9 / 4 and roof["unit"] == "wave64 VALU instructions/s"
+    gather = b.kernel_roofline(split, "peel_pass")
+    assert gather["bound"] == "hbm" and gather["frac"] == split["peel_pass"]["hbm_frac"]
+    # a record taken at 100 packets; this run had 1000: everything scales by 10
+    rec = {"packets": 100, "path": "profiles/x.json",
+           "kernels": {"k_persistent": {"read_bytes_per_batch": 3.0e6, "write_bytes_per_batch": 1.0e6,
+                                        "valu_insts_per_batch": 2.0e9, "valu_busy_pct": 70.0,
+                                        "valu_lane_util_pct": 24.0},
+                       "k_peel_pass": {"read_bytes_per_batch": 5.0e6, "write_bytes_per_batch": 1.0e6}}}
+    b.attach_counters(roof, split, "transport", rec, 1000)
+    b.attach_counters(gather, split, "peel_pass", rec, 1000)
+    # the transport kernel alone: the call's transport time less the tail kernel's
+    assert abs(roof["achieved"] - 2.0e10 / 0.69) < 1e-9 * 2.0e10 / 0.69
+    assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-15
+    assert abs(roof["traffic"] - 4.0e7 / 7) < 1e-6 and roof["counters"] == "profiles/x.json"
+    assert abs(gather["traffic"] - 6.0e7 / 7) < 1e-6 and gather["achieved"] == split["peel_pass"]["achieved_GBps"]

@@ -193,7 +193,9 @@ def test_web512_against_oracle(gpu):
     through the FP64 persistent path follow the oracle's histories (mostly)
     with the mean scattering count within 1 %; 1e6 mixed-precision packets
     of another seed pass a spectrum chi^2 against the oracle's 1e4 and their
-    peeled flux per observer lies within 4 sigma of the oracle's."""
+    peeled flux per observer lies within 4 sigma of the oracle's.  The same
+    1e6 packets through the FP64 path give the precision form's error report
+    (spectrum chi^2, SB-map L1, flux per observer, scattering-count drift)."""
     wl = W.web(n_grid=512, fields=W.web_fields(512), cube_npix=64, cube_nb=200)
     n = 10000
     parts = [oracle.run_threaded(wl["geom"], wl["src"], wl["opts"], i * 1000, 1000, _threads(), records=True)
@@ -207,7 +209,8 @@ def test_web512_against_oracle(gpu):
     ratio = g["records"]["n_res"].mean() / rec["n_res"].mean()
     _say("fp64 same seed: identical histories %.3f, mean n_res ratio %.4f" % (same, ratio))
     assert same > 0.6 and abs(ratio - 1) < 0.01
-    m = gpu.run(dict(wl, src=dict(wl["src"], seed=1004)), n=1_000_000, precision="mixed", path="persistent")
+    wl2 = dict(wl, src=dict(wl["src"], seed=1004))
+    m = gpu.run(wl2, n=1_000_000, precision="mixed", path="persistent", records=True)
     chi2, dof, p = chi2_two_sample(m["spectrum"], spec)
     tot = m["cube"].astype(np.float64).sum(axis=(1, 2, 3)) / 1e6
     mean, err = flux.mean(axis=0), flux.std(axis=0, ddof=1) / np.sqrt(len(flux))
@@ -215,6 +218,21 @@ def test_web512_against_oracle(gpu):
          % (chi2, dof, p, tot, mean, err))
     assert p > 0.01
     assert np.all(np.abs(tot - mean) < 4 * err)
+    # the precision form against the all-FP64 path on the same 1e6 packets:
+    # spectrum, surface-brightness maps (cube summed over frequency), peeled
+    # flux per observer, scattering-count drift
+    d = gpu.run(wl2, n=1_000_000, precision="fp64", path="persistent", records=True)
+    chi2, dof, p = chi2_two_sample(m["spectrum"], d["spectrum"])
+    sb_m = m["cube"].astype(np.float64).sum(axis=3)
+    sb_d = d["cube"].astype(np.float64).sum(axis=3)
+    l1 = np.abs(sb_m - sb_d).sum() / sb_d.sum()
+    rel = sb_m.sum(axis=(1, 2)) / sb_d.sum(axis=(1, 2)) - 1
+    nm, nd = m["records"]["n_res"].astype(float), d["records"]["n_res"].astype(float)
+    drift = nm.mean() / nd.mean() - 1
+    _say("precision form, mixed vs fp64 on the same 1e6 packets: spectrum chi2 %.1f dof %d p %.3f; "
+         "SB-map L1 rel %.4f; peeled flux per observer rel %s; scatterings drift %.2e; identical histories %.3f"
+         % (chi2, dof, p, l1, np.array2string(rel, precision=5), drift, np.mean(nm == nd)))
+    assert p > 0.001 and abs(drift) < 0.01 and np.all(np.abs(rel) < 0.01)
 
 
 def test_web1024_bench_configuration_against_oracle(gpu):
