@@ -356,6 +356,34 @@ def test_fixed64_cube_is_bit_reproducible(gpu, precision):
     assert np.allclose(v, f, rtol=2e-3, atol=1e-6 * f.max())
 
 
+# ------------------------------------------------------------ compact pencil records
+def test_compact_pencil_records_same_cube(gpu):
+    """Grids without dust march peel rays over 12-byte pencil records (no dust
+    opacity).  The same box with a dust cross-section so small that every
+    record's FP32 dust opacity is zero takes the 16-byte records instead; the
+    fixed-point cube, the spectrum and every record are the same bit for bit."""
+    wl = W.web(n_grid=64, fields=W.web_fields(64), cube_npix=32, cube_nb=50)
+    o = wl["opts"]
+    shape = (len(o["observers"]), o["cube"]["ny"], o["cube"]["nx"], o["cube"]["nb"])
+    res = []
+    for sigma_d in (0.0, 1e-70):
+        T = gpu.Transport(0)
+        try:
+            T.load(dict(wl["geom"], sigma_d=sigma_d))
+            T.emit(wl["src"], 20000, 0)
+            _, st = T.transport(o, precision="mixed", path="persistent", records=True, accum="fixed64")
+            res.append((T.cube_fixed(shape), T.spectrum(), T.records(), st))
+        finally:
+            T.close()
+    (c0, s0, r0, st0), (c1, s1, r1, st1) = res
+    _say("compact records: %d peel visits, %d nonzero voxels" % (st0["peel_visits"], np.count_nonzero(c0)))
+    assert st0["passes"] >= 1 and st0["peel_visits"] > 0 and st1["n_dust"] == 0
+    assert np.array_equal(c0, c1)
+    assert np.array_equal(s0, s1)
+    for k in ("n_res", "n_dust", "fate", "dv"):
+        assert np.array_equal(r0[k], r1[k]), k
+
+
 # ------------------------------------------------------------ spatial presort
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_presort_changes_only_the_order(gpu, precision):
