@@ -384,6 +384,32 @@ def test_compact_pencil_records_same_cube(gpu):
         assert np.array_equal(r0[k], r1[k]), k
 
 
+# ------------------------------------------------------------ seed-buffer sizing
+def test_seed_buffer_under_a_budget(gpu):
+    """The default seed buffer takes up to 2^30 slots when the device has the
+    memory; a context with a 6 GiB HBM budget cannot hold 2^28 slots (12.9 GB)
+    and falls back to the small buffer.  Both give the same fixed-point cube,
+    spectrum and records."""
+    wl = W.web(n_grid=64, fields=W.web_fields(64), cube_npix=32, cube_nb=50)
+    o = wl["opts"]
+    shape = (len(o["observers"]), o["cube"]["ny"], o["cube"]["nx"], o["cube"]["nb"])
+    res = []
+    for budget in (0, 6 << 30):
+        T = gpu.Transport(0, hbm_budget_bytes=budget)
+        try:
+            T.load(wl["geom"])
+            T.emit(wl["src"], 20000, 0)
+            _, st = T.transport(o, precision="mixed", path="persistent", records=True, accum="fixed64")
+            res.append((T.cube_fixed(shape), T.spectrum(), T.records(), st))
+        finally:
+            T.close()
+    (c0, s0, r0, _), (c1, s1, r1, _) = res
+    assert np.array_equal(c0, c1)
+    assert np.array_equal(s0, s1)
+    for k in ("n_res", "n_dust", "fate", "dv"):
+        assert np.array_equal(r0[k], r1[k]), k
+
+
 # ------------------------------------------------------------ spatial presort
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_presort_changes_only_the_order(gpu, precision):
