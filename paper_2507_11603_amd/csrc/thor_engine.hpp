@@ -20,8 +20,18 @@
 #ifndef THOR_PEEL_LOOKAHEAD
 #define THOR_PEEL_LOOKAHEAD 2
 #endif
+// (THOR_PASS_LOOKAHEAD: 12-byte records of grids without dust; the 16-byte
+// records with dust take THOR_PASS_LOOKAHEAD_DUST, within the same registers)
 #ifndef THOR_PASS_LOOKAHEAD
-#define THOR_PASS_LOOKAHEAD 8
+#define THOR_PASS_LOOKAHEAD 5
+#endif
+#ifndef THOR_PASS_LOOKAHEAD_DUST
+#define THOR_PASS_LOOKAHEAD_DUST 4
+#endif
+// peel pass, FP32 rays: request the next group's records before summing the
+// current group (two groups in flight per lane)
+#ifndef THOR_PASS_PREFETCH
+#define THOR_PASS_PREFETCH 1
 #endif
 
 namespace thor {
